@@ -1,0 +1,196 @@
+/*
+ * qp_pt2.h -- C ABI of the MI355X (gfx950) Epstein-Nesbet PT2 / CIPSI-selection
+ * sweep of Quantum Package 2.0 (arXiv:1902.08154).
+ *
+ * For every external determinant alpha that is a single or double excitation
+ * of the wave function Psi (and not in Psi), the sweep forms
+ *     N_alpha,k = <Psi_k|H|alpha> = sum_J c_Jk <J|H|alpha>     (Slater-Condon)
+ *     e_alpha,k = N_alpha,k^2 / (E0_k - <alpha|H|alpha>)        (eq. e2)
+ *     E_PT2,k   = sum_alpha e_alpha,k                           (eq. PT2)
+ * and keeps the alpha with the largest |sum_k e_alpha,k / max_J c_Jk^2|
+ * (multi-state selection criterion of sec. "CIPSI selection and PT2 energy").
+ * Each alpha is produced by exactly one generator: generators are the
+ * determinants of Psi sorted by decreasing sum_k c_Jk^2 (ties: ascending bit
+ * string), and alpha belongs to the first generator it is connected to
+ * (generator decomposition E_PT2 = sum_I eps_I of the same section).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers on the context's device unless
+ *    stated otherwise; they are owned by the caller.  Every call only enqueues
+ *    work on `stream` (a hipStream_t; NULL = default stream), except where a
+ *    host synchronisation is documented.  Outputs are valid once the stream
+ *    has synchronised.
+ *  - Orbitals are spatial, 0-based, n_orb in [1, 256].  A determinant is
+ *    uint64_t[2][n_int], n_int = (n_orb-1)/64 + 1: the spin-up string (words
+ *    0..n_int-1) then the spin-down string; bit b of word w is orbital
+ *    64*w + b.  Bits at positions >= n_orb must be zero.  Every determinant of
+ *    one call has the same number of up and of down electrons.  The sign
+ *    convention is the paper's: up spin-orbitals before down ones, increasing
+ *    index within each spin (sec. "Internal representation of determinants");
+ *    any other phase is folded into the coefficients.
+ *  - Bit-string order ("key"): up words from high to low, then down words from
+ *    high to low, compared as unsigned integers.
+ *  - h is the real symmetric one-electron matrix, row-major [n_orb][n_orb].
+ *    Two-electron integrals are chemist-notation (pq|rs), real, 8-fold
+ *    symmetric, packed at offset tri(tri(p,q), tri(r,s)) with
+ *    tri(a,b) = M(M+1)/2 + m, M = max(a,b), m = min(a,b): the paper's
+ *    Algorithm 1 evaluated on 1-based indices, minus one.  Length
+ *    P(P+1)/2 with P = n_orb(n_orb+1)/2.
+ *  - Coefficients are [n_states][n_det] row-major FP64; n_states in [1, 4].
+ *    The library does not normalise them.
+ *  - All arithmetic on energies is IEEE FP64.  A zero denominator
+ *    E0 - H_alpha,alpha is not an error: IEEE results propagate and
+ *    stats.min_abs_delta reports the smallest |denominator|.
+ *  - Return value: QP_OK (0) or a negative QP_E_* code; qp_last_error() then
+ *    holds a message.  A failed call leaves outputs unspecified.
+ */
+#ifndef QP_PT2_H
+#define QP_PT2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QP_OK            0
+#define QP_E_ARG        -1  /* null pointer, negative size, bad flag            */
+#define QP_E_NORB       -2  /* n_orb outside [1,256] or a bit set at >= n_orb   */
+#define QP_E_ELEC       -3  /* per-spin electron counts differ between dets     */
+#define QP_E_DUP        -4  /* the same determinant appears twice               */
+#define QP_E_NOINT      -5  /* integrals not set, or n_orb mismatch             */
+#define QP_E_OOM        -6  /* device allocation failed                         */
+#define QP_E_HIP        -7  /* a HIP runtime call failed                        */
+#define QP_E_STATES     -8  /* n_states outside [1,4]                           */
+#define QP_E_OVERFLOW   -9  /* selection candidate buffer overflowed            */
+
+#define QP_MAX_STATES    4
+#define QP_MAX_ORB       256
+
+/* qp_pt2 flags */
+#define QP_FLAG_FINGERPRINT  1  /* also compute stats.fingerprint of the alpha set */
+#define QP_FLAG_NOCHECK      2  /* skip input validation (duplicates, counts, bits) */
+
+typedef struct qp_ctx qp_ctx;
+
+/* Device-side statistics of one sweep (written by qp_pt2 / qp_pt2_backward). */
+typedef struct {
+    uint64_t n_alpha;        /* |A|: external determinants (each counted once)     */
+    uint64_t n_cells;        /* (generator, alpha) candidate cells examined          */
+    uint64_t fingerprint;    /* sum mod 2^64 over alpha of fold(alpha), see below  */
+    uint64_t n_coarse;       /* total coarse-filter entries: pairs (I,J), J != I,
+                                with excitation degree <= 4                        */
+    uint64_t n_candidates;   /* selection candidates written before the final sort */
+    uint64_t overflow;       /* nonzero: candidate buffer overflowed (QP_E_OVERFLOW)*/
+    uint64_t n_connections;  /* (alpha, J != generator) pairs with degree <= 2
+                                that contributed a matrix element                  */
+    uint64_t reserved;
+    double   S[QP_MAX_STATES];  /* sum_alpha N^2/(E0-H_aa)^2 = -dE_PT2/dE0 (rPT2) */
+    double   min_abs_delta;     /* min over alpha, k of |E0_k - H_alpha,alpha|      */
+    double   reserved_d[3];
+} qp_pt2_stats;
+/* fold(alpha): h = 0; for each word x of alpha (up words 0..n_int-1, then down
+ * words 0..n_int-1): h = splitmix64_mix(h ^ x), where splitmix64_mix is the
+ * output function of SplitMix64 (Steele, Lea & Flood, 2014):
+ *   z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9; z = (z ^ (z >> 27)) * 0x94d049bb133111eb;
+ *   return z ^ (z >> 31). */
+
+/* Create a context bound to HIP device `device`.  Allocates nothing on the
+ * device until the first call that needs it.  *ctx is owned by the caller and
+ * released with qp_destroy. */
+int  qp_create(qp_ctx **ctx, int device);
+void qp_destroy(qp_ctx *ctx);
+/* Message of the last failed call on ctx (never NULL; "" if none). */
+const char *qp_last_error(const qp_ctx *ctx);
+
+/*
+ * qp_set_integrals -- one-electron matrix and two-electron integrals
+ * (sec. "Matrix elements of the Hamiltonian"; storage: sec. "Storage of the
+ * two-electron integrals", Algorithm 1).
+ *   h          device [n_orb][n_orb], symmetric.
+ *   eri_packed device, length P(P+1)/2, layout above.
+ * The context builds its own device layouts from these (dense per-hole-pair
+ * blocks, about 1.5x the packed size plus n^3 tables) and does not keep the
+ * caller's pointers: the caller may free them once the stream has synchronised.
+ * Replaces any previous integrals.  Errors: QP_E_ARG, QP_E_NORB, QP_E_OOM,
+ * QP_E_HIP.
+ */
+int qp_set_integrals(qp_ctx *ctx, const double *h, const double *eri_packed, int n_orb,
+                     void *stream);
+
+/*
+ * qp_pt2 -- the forward sweep: E_PT2 per state, the selected alpha, optional
+ * per-generator partition (eqs. e2, PT2; generator decomposition and
+ * selection of sec. "CIPSI selection and PT2 energy").
+ *   dets      device uint64 [n_det][2][n_int]    (distinct determinants)
+ *   coefs     device double [n_states][n_det]
+ *   E0        device double [n_states]            (independent input)
+ *   n_select  >= 0: number of alpha to keep (fewer if |A| < n_select)
+ *   flags     QP_FLAG_*
+ * Outputs (device):
+ *   e_pt2     double [n_states]                   (required)
+ *   sel_dets  uint64 [n_select][2][n_int]         (required if n_select > 0)
+ *   sel_e     double [n_select][n_states]: e_alpha,k of each selected alpha,
+ *             ordered by |sum_k e_k/max_J c_Jk^2| descending, ties by key
+ *             ascending                            (required if n_select > 0)
+ *   n_sel     int64 [1]                           (required if n_select > 0)
+ *   stats     qp_pt2_stats [1]                    (optional, NULL)
+ *   eps_gen   double [n_states][n_det]: eps_I of determinant I (caller's index)
+ *                                                 (optional, NULL)
+ * Host synchronisation: the call synchronises `stream` once (to size the
+ * coarse-filter lists and to check validation and overflow results).
+ * Errors: QP_E_ARG, QP_E_STATES, QP_E_NOINT, QP_E_NORB, QP_E_ELEC, QP_E_DUP,
+ * QP_E_OOM, QP_E_HIP, QP_E_OVERFLOW.
+ */
+int qp_pt2(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
+           int n_states, const double *E0, int64_t n_select, int flags,
+           double *e_pt2, uint64_t *sel_dets, double *sel_e, int64_t *n_sel,
+           qp_pt2_stats *stats, double *eps_gen, void *stream);
+
+/*
+ * qp_pt2_backward -- adjoint of qp_pt2's E_PT2 output.  Recomputes every
+ * numerator N_alpha,k (nothing is stored by the forward call) and returns the
+ * partial derivatives of L = sum_k g_k E_PT2,k with A and E0 held as
+ * independent inputs:
+ *   grad_coefs[k][J] = 2 g_k sum_alpha (N_alpha,k / delta_alpha,k) <J|H|alpha>
+ *   grad_E0[k]       = -g_k sum_alpha N_alpha,k^2 / delta_alpha,k^2
+ *   grad_h[p][q]     symmetric G with dL = sum_pq G_pq dh_pq for symmetric dh:
+ *                    diagonal terms from d<alpha|H|alpha>/dh_pp (occupation of
+ *                    p in alpha), off-diagonal terms from the single-excitation
+ *                    elements (d<J|H|alpha>/dh_xy = phase).
+ *   grad_e_pt2 device double [n_states] (g_k); outputs device, overwritten:
+ *   grad_coefs [n_states][n_det], grad_E0 [n_states], grad_h [n_orb][n_orb]
+ *   (any output may be NULL to skip it).  stats as in qp_pt2 (optional).
+ * Gradient accumulation uses FP64 atomics: results agree between runs to
+ * rounding, not bitwise.  Errors as qp_pt2.
+ */
+int qp_pt2_backward(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
+                    int n_states, const double *E0, const double *grad_e_pt2, int flags,
+                    double *grad_coefs, double *grad_E0, double *grad_h,
+                    qp_pt2_stats *stats, void *stream);
+
+/*
+ * qp_energy -- variational energy E0_k = <Psi_k|H|Psi_k> / <Psi_k|Psi_k>
+ * (eq. evar) over the determinant list, for preparing the E0 input.
+ *   E0_out device double [n_states].  Errors as qp_pt2.
+ */
+int qp_energy(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
+              int n_states, int flags, double *E0_out, void *stream);
+
+/*
+ * qp_set_timing / qp_last_timing -- diagnostics.  When enabled, every
+ * qp_pt2 / qp_pt2_backward call records HIP events on its stream around the
+ * sweep kernel (the per-generator batch kernel, the dominant cost).
+ * qp_last_timing waits for the last recorded event and writes
+ * out_ms[0] = duration of the last sweep kernel, out_ms[1] = duration from the
+ * call's first enqueued kernel to its last (ms).  Errors: QP_E_ARG when timing
+ * is off or no call has been timed, QP_E_HIP.
+ */
+int qp_set_timing(qp_ctx *ctx, int enable);
+int qp_last_timing(qp_ctx *ctx, double *out_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QP_PT2_H */

@@ -53,7 +53,8 @@ def _load():
                                      _P, _P, _P, _P, _P, _P, _P,
                                      _I64, _P, _P, _P, _P,
                                      _I64, _P, _P, _P, _P, _P,
-                                     _P, _P, _P, _P]
+                                     _P, _P, _P, _P,
+                                     _P, _P, _P, _P, _P]
         lib.orc_alpha_eval.restype = _I
         lib.orc_alpha_eval.argtypes = [_I, _I, _P, _P, _P, _P, _I64, _I, _P, _P, _P, _P, _P, _P]
         lib.orc_eps_generators.restype = _I
@@ -146,21 +147,26 @@ def pt2_full(n_orb, h, eri, dets, coefs, E0, n_select=0, dump_all=False, grad_up
     if grad_up is not None:
         gu = _c(np.atleast_1d(grad_up), np.float64)
         dc = np.zeros((ns, nd)); dE0 = np.zeros(ns); dh = np.zeros((n_orb, n_orb))
+    abs_e = np.zeros(ns); T = np.zeros(ns)
+    S_gen = np.zeros((ns, nd)) if eps_gen else None
+    abs_gen = np.zeros((ns, nd)) if eps_gen else None
+    sel_D = np.zeros(n_select) if n_select > 0 else None
     rc = _load().orc_pt2_full(n_orb, nint, _ptr(h), _ptr(eri), _ptr(dets), _ptr(coefs), nd, ns,
                               _ptr(E0), nparts, part,
                               _ptr(e_pt2), _ptr(S), _ptr(n_alpha), _ptr(fp), _ptr(nconn), _ptr(mind),
                               _ptr(epsg), n_select, _ptr(sel_dets), _ptr(sel_e), _ptr(sel_key),
                               _ptr(n_sel), all_cap, _ptr(all_dets), _ptr(all_e), _ptr(all_N),
-                              _ptr(all_D), _ptr(all_owner), _ptr(gu), _ptr(dc), _ptr(dE0), _ptr(dh))
+                              _ptr(all_D), _ptr(all_owner), _ptr(gu), _ptr(dc), _ptr(dE0), _ptr(dh),
+                              _ptr(abs_e), _ptr(T), _ptr(S_gen), _ptr(abs_gen), _ptr(sel_D))
     if rc != 0:
         raise MemoryError("oracle pt2_full failed")
     r = FullResult(e_pt2=e_pt2, S=S, n_alpha=int(n_alpha[0]), fp=int(fp[0]), n_conn=int(nconn[0]),
-                   min_abs_delta=float(mind[0]))
+                   min_abs_delta=float(mind[0]), abs_e=abs_e, T=T, E0=E0)
     if eps_gen:
-        r["eps_gen"] = epsg
+        r.update(eps_gen=epsg, S_gen=S_gen, abs_gen=abs_gen)
     if n_select > 0:
         m = int(n_sel[0])
-        r.update(sel_dets=sel_dets[:m], sel_e=sel_e[:m], sel_key=sel_key[:m])
+        r.update(sel_dets=sel_dets[:m], sel_e=sel_e[:m], sel_key=sel_key[:m], sel_D=sel_D[:m])
     if dump_all:
         m = r["n_alpha"]
         r.update(all_dets=all_dets[:m], all_e=all_e[:m], all_N=all_N[:m], all_D=all_D[:m],

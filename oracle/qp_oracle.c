@@ -146,25 +146,36 @@ static int set_minus(const u64 *x, const u64 *y, int nint, int n, int *out, int 
     return m;
 }
 
+/* Neumaier-compensated sum (the denominators E0 - H_aa of eq. e2 can be
+ * small, so the diagonal is accumulated to within a few ulps) */
+typedef struct { double s, c; } neumaier;
+static void nm_add(neumaier *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double nm_val(const neumaier *a) { return a->s + a->c; }
+
 /* Diagonal rule: sum_i h_ii + 1/2 sum_{i != j} [(ii|jj) - delta_spin (ij|ji)] */
 double orc_diagonal(const orc_ints *I, const u64 *d)
 {
     int n = I->n, nint = I->nint;
-    double one = 0.0, two = 0.0;
+    neumaier acc = {0.0, 0.0};
     for (int si = 0; si < 2; ++si)
         for (int i = 0; i < n; ++i) {
             if (!occupied(d, nint, si, i)) continue;
-            one += hcore(I, i, i);
+            nm_add(&acc, hcore(I, i, i));
             for (int sj = 0; sj < 2; ++sj)
                 for (int j = 0; j < n; ++j) {
                     if (!occupied(d, nint, sj, j)) continue;
                     if (si == sj && i == j) continue;
-                    double v = eri(I, i, i, j, j);
-                    if (si == sj) v -= eri(I, i, j, j, i);
-                    two += v;
+                    nm_add(&acc, 0.5 * eri(I, i, i, j, j));
+                    if (si == sj) nm_add(&acc, -0.5 * eri(I, i, j, j, i));
                 }
         }
-    return one + 0.5 * two;
+    return nm_val(&acc);
 }
 
 /* Off-diagonal Slater-Condon element <bra|H|ket>, bra != ket.  Also returns
@@ -223,16 +234,6 @@ double orc_matrix_element(int n, int nint, const double *h, const double *eri_pa
 /* ------------------------------------------------------------------------ */
 /* helpers: compensated sum, splitmix64 fingerprint, hash set of dets         */
 /* ------------------------------------------------------------------------ */
-
-typedef struct { double s, c; } neumaier;
-static void nm_add(neumaier *a, double x)
-{
-    double t = a->s + x;
-    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
-    else a->c += (x - t) + a->s;
-    a->s = t;
-}
-static double nm_val(const neumaier *a) { return a->s + a->c; }
 
 /* splitmix64 output function (Steele, Lea & Flood 2014) */
 static u64 mix64(u64 z)
@@ -547,7 +548,10 @@ static int sel_cmp(const void *a, const void *b)
  *   per-alpha fingerprints), n_conn (sum over alpha of connected internal
  *   dets), min_abs_delta, eps_gen[ns][n_det] (caller's det index),
  *   selection: the first n_select alpha by (|e~| desc, key asc) ->
- *   sel_dets [n_select][2][nint], sel_e [n_select][ns], sel_key[n_select] (|e~|), *n_sel;
+ *   sel_dets [n_select][2][nint], sel_e [n_select][ns], sel_key[n_select] (|e~|),
+ *   sel_D [n_select] (H_alpha,alpha), *n_sel;
+ *   conditioning sums for rounding-aware comparisons: abs_e[ns] = sum |e|,
+ *   T[ns] = sum N^2/|delta|^3, and per generator S_gen, abs_gen [ns][n_det];
  *   all_dets/all_e/all_D/all_owner: every alpha in ascending key order when
  *   all_cap >= n_alpha (all_e [n][ns]; all_N [n][ns]);
  *   gradients when grad_up != NULL: dc [ns][n_det], dE0 [ns], dh [n][n].
@@ -561,7 +565,8 @@ int orc_pt2_full(int n, int nint, const double *h, const double *eri_packed,
                  int64_t n_select, u64 *sel_dets, double *sel_e, double *sel_key, int64_t *n_sel,
                  int64_t all_cap, u64 *all_dets, double *all_e, double *all_N, double *all_D,
                  int64_t *all_owner,
-                 const double *grad_up, double *dc, double *dE0, double *dh)
+                 const double *grad_up, double *dc, double *dE0, double *dh,
+                 double *abs_e, double *T, double *S_gen, double *abs_gen, double *sel_D)
 {
     if (ns < 1 || ns > ORC_MAX_STATES) return -1;
     orc_ints I = {n, nint, h, eri_packed};
@@ -608,12 +613,15 @@ int orc_pt2_full(int n, int nint, const double *h, const double *eri_packed,
         }
     }
 
-    neumaier accE[ORC_MAX_STATES], accS[ORC_MAX_STATES];
+    neumaier accE[ORC_MAX_STATES], accS[ORC_MAX_STATES], accA[ORC_MAX_STATES], accT[ORC_MAX_STATES];
     memset(accE, 0, sizeof(accE)); memset(accS, 0, sizeof(accS));
-    neumaier *acc_gen = NULL;
-    if (eps_gen) {
+    memset(accA, 0, sizeof(accA)); memset(accT, 0, sizeof(accT));
+    neumaier *acc_gen = NULL, *accS_gen = NULL, *accA_gen = NULL;
+    if (eps_gen || S_gen || abs_gen) {
         acc_gen = (neumaier *)calloc((size_t)ns * (n_det ? n_det : 1), sizeof(neumaier));
-        if (!acc_gen) return -1;
+        accS_gen = (neumaier *)calloc((size_t)ns * (n_det ? n_det : 1), sizeof(neumaier));
+        accA_gen = (neumaier *)calloc((size_t)ns * (n_det ? n_det : 1), sizeof(neumaier));
+        if (!acc_gen || !accS_gen || !accA_gen) return -1;
     }
     u64 fps = 0;
     int64_t conn = 0;
@@ -630,7 +638,13 @@ int orc_pt2_full(int n, int nint, const double *h, const double *eri_packed,
             e[i * ns + s] = ea;
             nm_add(&accE[s], ea);
             nm_add(&accS[s], N * N / (delta * delta));
-            if (acc_gen) nm_add(&acc_gen[(size_t)s * n_det + owner_det], ea);
+            nm_add(&accA[s], fabs(ea));
+            nm_add(&accT[s], N * N / fabs(delta * delta * delta));
+            if (acc_gen) {
+                nm_add(&acc_gen[(size_t)s * n_det + owner_det], ea);
+                nm_add(&accS_gen[(size_t)s * n_det + owner_det], N * N / (delta * delta));
+                nm_add(&accA_gen[(size_t)s * n_det + owner_det], fabs(ea));
+            }
             if (fabs(delta) < mind) mind = fabs(delta);
         }
         fps += orc_det_fingerprint(a, nint);
@@ -639,7 +653,14 @@ int orc_pt2_full(int n, int nint, const double *h, const double *eri_packed,
     for (int s = 0; s < ns; ++s) {
         e_pt2[s] = nm_val(&accE[s]);
         if (S) S[s] = nm_val(&accS[s]);
+        if (abs_e) abs_e[s] = nm_val(&accA[s]);
+        if (T) T[s] = nm_val(&accT[s]);
     }
+    for (int s = 0; s < ns && acc_gen; ++s)
+        for (int64_t j = 0; j < n_det; ++j) {
+            if (S_gen) S_gen[(size_t)s * n_det + j] = nm_val(&accS_gen[(size_t)s * n_det + j]);
+            if (abs_gen) abs_gen[(size_t)s * n_det + j] = nm_val(&accA_gen[(size_t)s * n_det + j]);
+        }
     if (n_alpha) *n_alpha = (int64_t)na;
     if (fp_sum) *fp_sum = fps;
     if (n_conn) *n_conn = conn;
@@ -679,6 +700,7 @@ int orc_pt2_full(int n, int nint, const double *h, const double *eri_packed,
             if (sel_dets) memcpy(sel_dets + r * 2 * nint, C.akeys + i * 2 * nint, sizeof(u64) * 2 * nint);
             if (sel_e) for (int s = 0; s < ns; ++s) sel_e[r * ns + s] = e[i * ns + s];
             if (sel_key) sel_key[r] = it[r].key;
+            if (sel_D) sel_D[r] = D[i];
         }
         *n_sel = m;
         free(it);
@@ -720,7 +742,7 @@ int orc_pt2_full(int n, int nint, const double *h, const double *eri_packed,
         free(w);
     }
 
-    free(order); free(D); free(e); free(acc_gen);
+    free(order); free(D); free(e); free(acc_gen); free(accS_gen); free(accA_gen);
     free(C.akeys); free(C.num); free(C.owner); free(C.nconn);
     detmap_free(&psi); detmap_free(&amap);
     free(rank); free(gen_of_rank);

@@ -1,0 +1,86 @@
+"""ctypes declarations of libqp_pt2.so (include/qp_pt2.h).  Loading fails loudly
+when the library has not been built: there is no fallback path."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqp_pt2.so")
+
+QP_OK = 0
+QP_E_ARG = -1
+QP_E_NORB = -2
+QP_E_ELEC = -3
+QP_E_DUP = -4
+QP_E_NOINT = -5
+QP_E_OOM = -6
+QP_E_HIP = -7
+QP_E_STATES = -8
+QP_E_OVERFLOW = -9
+
+QP_FLAG_FINGERPRINT = 1
+QP_FLAG_NOCHECK = 2
+QP_MAX_STATES = 4
+
+ERROR_NAMES = {
+    QP_E_ARG: "QP_E_ARG", QP_E_NORB: "QP_E_NORB", QP_E_ELEC: "QP_E_ELEC", QP_E_DUP: "QP_E_DUP",
+    QP_E_NOINT: "QP_E_NOINT", QP_E_OOM: "QP_E_OOM", QP_E_HIP: "QP_E_HIP", QP_E_STATES: "QP_E_STATES",
+    QP_E_OVERFLOW: "QP_E_OVERFLOW",
+}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n_alpha", ctypes.c_uint64),
+        ("n_cells", ctypes.c_uint64),
+        ("fingerprint", ctypes.c_uint64),
+        ("n_coarse", ctypes.c_uint64),
+        ("n_candidates", ctypes.c_uint64),
+        ("overflow", ctypes.c_uint64),
+        ("n_connections", ctypes.c_uint64),
+        ("reserved", ctypes.c_uint64),
+        ("S", ctypes.c_double * QP_MAX_STATES),
+        ("min_abs_delta", ctypes.c_double),
+        ("reserved_d", ctypes.c_double * 3),
+    ]
+
+
+# every entry point declared in include/qp_pt2.h
+EXPORTS = ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
+           "qp_pt2_backward", "qp_energy", "qp_set_timing", "qp_last_timing")
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1902_08154_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.qp_create.argtypes = [ctypes.POINTER(_P), _I]
+    lib.qp_create.restype = _I
+    lib.qp_destroy.argtypes = [_P]
+    lib.qp_destroy.restype = None
+    lib.qp_last_error.argtypes = [_P]
+    lib.qp_last_error.restype = ctypes.c_char_p
+    lib.qp_set_integrals.argtypes = [_P, _P, _P, _I, _P]
+    lib.qp_set_integrals.restype = _I
+    lib.qp_pt2.argtypes = [_P, _P, _P, _I64, _I, _P, _I64, _I, _P, _P, _P, _P, _P, _P, _P]
+    lib.qp_pt2.restype = _I
+    lib.qp_pt2_backward.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I, _P, _P, _P, _P, _P]
+    lib.qp_pt2_backward.restype = _I
+    lib.qp_energy.argtypes = [_P, _P, _P, _I64, _I, _I, _P, _P]
+    lib.qp_energy.restype = _I
+    lib.qp_set_timing.argtypes = [_P, _I]
+    lib.qp_set_timing.restype = _I
+    lib.qp_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_double)]
+    lib.qp_last_timing.restype = _I
+    _lib = lib
+    return lib

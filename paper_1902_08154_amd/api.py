@@ -1,0 +1,174 @@
+"""Thin Python binding over the C ABI: argument marshalling only.
+
+Every function takes torch tensors that already live on the context's HIP
+device and passes their raw pointers and the current stream to libqp_pt2.so.
+Determinant bit strings are carried in torch.int64 tensors (same bits as the
+uint64 words of the ABI) of shape [n_det, 2, n_int].
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+
+class QPError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_lib.ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, name: str, device):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    if t.device != device:
+        raise TypeError(f"{name} is on {t.device}, context is on {device}")
+
+
+class Context:
+    """Owns one qp_ctx (device layouts of the integrals and scratch)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = self._lib.qp_create(ctypes.byref(h), device)
+        if rc != 0:
+            raise QPError(rc, "qp_create failed")
+        self._h = h
+        self.n_orb = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.qp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != 0:
+            msg = self._lib.qp_last_error(self._h).decode()
+            raise QPError(rc, msg)
+
+    # ------------------------------------------------------------------ ABI
+    def qp_set_integrals(self, h: torch.Tensor, eri_packed: torch.Tensor):
+        _need(h, torch.float64, "h", self.device)
+        _need(eri_packed, torch.float64, "eri_packed", self.device)
+        n = h.shape[0]
+        self._check(self._lib.qp_set_integrals(self._h, _ptr(h), _ptr(eri_packed), n, _stream(self.device)))
+        self.n_orb = n
+
+    def qp_pt2(self, dets, coefs, E0, n_select=0, flags=0, e_pt2=None, sel_dets=None, sel_e=None,
+               n_sel=None, stats=None, eps_gen=None):
+        self._check(self._lib.qp_pt2(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], coefs.shape[0],
+                                     _ptr(E0), n_select, flags, _ptr(e_pt2), _ptr(sel_dets), _ptr(sel_e),
+                                     _ptr(n_sel), _ptr(stats), _ptr(eps_gen), _stream(self.device)))
+
+    def qp_pt2_backward(self, dets, coefs, E0, grad_e_pt2, flags=0, grad_coefs=None, grad_E0=None,
+                        grad_h=None, stats=None):
+        self._check(self._lib.qp_pt2_backward(self._h, _ptr(dets), _ptr(coefs), dets.shape[0],
+                                              coefs.shape[0], _ptr(E0), _ptr(grad_e_pt2), flags,
+                                              _ptr(grad_coefs), _ptr(grad_E0), _ptr(grad_h), _ptr(stats),
+                                              _stream(self.device)))
+
+    def qp_energy(self, dets, coefs, E0_out, flags=0):
+        self._check(self._lib.qp_energy(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], coefs.shape[0],
+                                        flags, _ptr(E0_out), _stream(self.device)))
+
+    def qp_set_timing(self, enable: bool):
+        self._check(self._lib.qp_set_timing(self._h, 1 if enable else 0))
+
+    def qp_last_timing(self):
+        """(sweep kernel ms, whole call ms) of the last timed call."""
+        out = (ctypes.c_double * 2)()
+        self._check(self._lib.qp_last_timing(self._h, out))
+        return float(out[0]), float(out[1])
+
+    # ---------------------------------------------------------- conveniences
+    def _inputs(self, dets, coefs, E0=None):
+        _need(dets, torch.int64, "dets", self.device)
+        if dets.dim() != 3 or dets.shape[1] != 2:
+            raise ValueError("dets must have shape [n_det, 2, n_int]")
+        _need(coefs, torch.float64, "coefs", self.device)
+        if coefs.dim() != 2 or coefs.shape[1] != dets.shape[0]:
+            raise ValueError("coefs must have shape [n_states, n_det]")
+        if E0 is not None:
+            _need(E0, torch.float64, "E0", self.device)
+            if E0.numel() != coefs.shape[0]:
+                raise ValueError("E0 must have n_states entries")
+
+    def pt2(self, dets, coefs, E0, n_select=0, eps_gen=False, fingerprint=False, check=True):
+        """Forward sweep.  Returns a dict with e_pt2 [ns], sel_dets [m,2,nint],
+        sel_e [m,ns], stats (dict) and optionally eps_gen [ns, n_det]."""
+        self._inputs(dets, coefs, E0)
+        ns, nd = coefs.shape
+        dev = self.device
+        e = torch.empty(ns, dtype=torch.float64, device=dev)
+        st = torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev)
+        sd = torch.empty((max(n_select, 1), 2, dets.shape[2]), dtype=torch.int64, device=dev)
+        se = torch.empty((max(n_select, 1), ns), dtype=torch.float64, device=dev)
+        nsel = torch.zeros(1, dtype=torch.int64, device=dev)
+        eg = torch.empty((ns, nd), dtype=torch.float64, device=dev) if eps_gen else None
+        flags = (_lib.QP_FLAG_FINGERPRINT if fingerprint else 0) | (0 if check else _lib.QP_FLAG_NOCHECK)
+        self.qp_pt2(dets, coefs, E0, n_select, flags, e, sd if n_select > 0 else None,
+                    se if n_select > 0 else None, nsel if n_select > 0 else None, st, eg)
+        m = int(nsel.item()) if n_select > 0 else 0
+        out = dict(e_pt2=e, sel_dets=sd[:m], sel_e=se[:m], stats=stats_to_dict(st, ns))
+        if eps_gen:
+            out["eps_gen"] = eg
+        return out
+
+    def pt2_backward(self, dets, coefs, E0, grad_e_pt2, want=("coefs", "E0", "h")):
+        self._inputs(dets, coefs, E0)
+        ns, nd = coefs.shape
+        dev = self.device
+        gc = torch.empty((ns, nd), dtype=torch.float64, device=dev) if "coefs" in want else None
+        gE = torch.empty(ns, dtype=torch.float64, device=dev) if "E0" in want else None
+        gh = torch.empty((self.n_orb, self.n_orb), dtype=torch.float64, device=dev) if "h" in want else None
+        g = grad_e_pt2.to(device=dev, dtype=torch.float64).contiguous()
+        self.qp_pt2_backward(dets, coefs, E0, g, 0, gc, gE, gh, None)
+        return gc, gE, gh
+
+    def energy(self, dets, coefs):
+        self._inputs(dets, coefs)
+        out = torch.empty(coefs.shape[0], dtype=torch.float64, device=self.device)
+        self.qp_energy(dets, coefs, out)
+        return out
+
+
+def stats_to_dict(st: torch.Tensor, ns: int) -> dict:
+    raw = bytes(st.cpu().numpy().tobytes())
+    s = _lib.Stats.from_buffer_copy(raw)
+    return dict(n_alpha=int(s.n_alpha), n_cells=int(s.n_cells), fingerprint=int(s.fingerprint),
+                n_coarse=int(s.n_coarse), n_candidates=int(s.n_candidates), overflow=int(s.overflow),
+                n_connections=int(s.n_connections), S=[float(s.S[k]) for k in range(ns)],
+                min_abs_delta=float(s.min_abs_delta))
+
+
+def to_device_dets(dets_u64, device) -> torch.Tensor:
+    """numpy uint64 [n_det,2,n_int] -> torch.int64 on device (same bits)."""
+    import numpy as np
+    a = np.ascontiguousarray(dets_u64, dtype=np.uint64).view(np.int64)
+    return torch.from_numpy(a.copy()).to(device)
+
+
+def from_device_dets(t: torch.Tensor):
+    import numpy as np
+    return t.cpu().numpy().view(np.uint64)

@@ -1,0 +1,98 @@
+"""Shared helpers for the GPU parity tests: run the HIP path through the C ABI
+and the oracle on the same seeded inputs, and compare."""
+import numpy as np
+
+from oracle import oracle as orc
+
+# E_PT2: relative 1e-10 plus the rounding terms of e_tolerance()
+E_RTOL = 1e-10
+
+
+def gpu_system(ctx, s):
+    import torch
+    from paper_1902_08154_amd.api import to_device_dets
+    dev = ctx.device
+    ctx.qp_set_integrals(torch.from_numpy(np.ascontiguousarray(s.h)).to(dev),
+                         torch.from_numpy(np.ascontiguousarray(s.eri)).to(dev))
+    dets = to_device_dets(s.dets, dev)
+    coefs = torch.from_numpy(np.ascontiguousarray(s.coefs)).to(dev)
+    return dets, coefs
+
+
+def run_gpu(ctx, s, E0, n_select=0, eps_gen=True, fingerprint=True):
+    import torch
+    from paper_1902_08154_amd.api import from_device_dets
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(np.asarray(E0, dtype=np.float64), device=ctx.device)
+    r = ctx.pt2(dets, coefs, E0t, n_select=n_select, eps_gen=eps_gen, fingerprint=fingerprint)
+    torch.cuda.synchronize()
+    out = dict(e_pt2=r["e_pt2"].cpu().numpy(), stats=r["stats"],
+               sel_dets=from_device_dets(r["sel_dets"]), sel_e=r["sel_e"].cpu().numpy())
+    if eps_gen:
+        out["eps_gen"] = r["eps_gen"].cpu().numpy()
+    return out
+
+
+U = 2.0 ** -53
+
+
+def e_tolerance(o, k):
+    """Allowed |E_gpu - E_oracle| for state k: the relative 1e-10 of the
+    specification, plus the rounding of the denominator E0 - H_aa (a few ulps
+    of |E0|, amplified by S = sum N^2/delta^2 = sum |e|/|delta|), plus the
+    rounding of a mixed-sign sum (a few ulps of sum |e|)."""
+    return 1e-10 * abs(o.e_pt2[k]) + 32 * U * (abs(o.E0[k]) + 1) * o.S[k] + 64 * U * o.abs_e[k]
+
+
+def s_tolerance(o, k):
+    # dS = sum 2 N^2 |d delta| / |delta|^3 ; T = sum N^2/|delta|^3
+    return 1e-10 * o.S[k] + 64 * U * (abs(o.E0[k]) + 1) * o.T[k] + 64 * U * o.S[k]
+
+
+def selection_keys(sel_e, coefs):
+    maxc2 = (np.asarray(coefs) ** 2).max(axis=1)
+    return np.abs((np.asarray(sel_e) / maxc2).sum(axis=1))
+
+
+def assert_selection_equal(g_dets, g_e, o, coefs):
+    """The selected bit strings must match the oracle's exactly; the only
+    allowed differences are swaps between alpha whose criteria are equal
+    within their rounding tolerance (near-ties), at the cut or in the order."""
+    o_dets, o_e, o_key, o_D = o.sel_dets, o.sel_e, o.sel_key, o.sel_D
+    assert g_dets.shape == o_dets.shape, (g_dets.shape, o_dets.shape)
+    maxc2 = (np.asarray(coefs) ** 2).max(axis=1)
+    delta = np.abs(o.E0[None, :] - o_D[:, None])
+    ktol = (np.abs(o_e) / maxc2 * (1e-10 + 32 * U * (np.abs(o.E0) + 1) / delta)).sum(axis=1)
+    ok = np.all(g_dets.reshape(len(g_dets), -1) == o_dets.reshape(len(o_dets), -1), axis=1)
+    if not ok.all():
+        okey = {bytes(d.tobytes()): i for i, d in enumerate(o_dets)}
+        for r in np.nonzero(~ok)[0]:
+            i = okey.get(bytes(g_dets[r].tobytes()))
+            if i is None:   # not in the oracle's list: must tie with the cut
+                i = len(o_key) - 1
+            lo, hi = min(i, r), max(i, r)
+            assert o_key[lo] - o_key[hi] <= ktol[lo] + ktol[hi], \
+                f"selection differs at rank {r} (oracle rank {i}) beyond rounding"
+    e_tol = 1e-10 * np.abs(o_e) + 32 * U * (np.abs(o.E0) + 1) * np.abs(o_e) / delta
+    assert np.all(np.abs(g_e[ok] - o_e[ok]) <= e_tol[ok] + 1e-300)
+
+
+def compare_full(ctx, s, E0, n_select):
+    """Full parity of one system: |A|, fingerprint, E_PT2, S, eps per generator,
+    selection.  Returns (gpu, oracle) results."""
+    o = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, n_select=n_select, eps_gen=True)
+    g = run_gpu(ctx, s, E0, n_select=n_select)
+    st = g["stats"]
+    assert st["n_alpha"] == o.n_alpha
+    assert st["fingerprint"] == o.fp
+    assert st["overflow"] == 0
+    for k in range(s.n_states):
+        assert abs(g["e_pt2"][k] - o.e_pt2[k]) <= e_tolerance(o, k), (k, g["e_pt2"], o.e_pt2)
+        assert abs(st["S"][k] - o.S[k]) <= s_tolerance(o, k), (k, st["S"], o.S)
+        tol_g = (1e-10 * np.abs(o.eps_gen[k]) + 32 * U * (abs(o.E0[k]) + 1) * o.S_gen[k]
+                 + 64 * U * o.abs_gen[k])
+        assert np.all(np.abs(g["eps_gen"][k] - o.eps_gen[k]) <= tol_g)
+    assert abs(st["min_abs_delta"] - o.min_abs_delta) <= 64 * U * (np.abs(o.E0).max() + 1)
+    if n_select > 0:
+        assert_selection_equal(g["sel_dets"], g["sel_e"], o, s.coefs)
+    return g, o

@@ -1,0 +1,43 @@
+"""The C-ABI library loads and exports every entry point the header declares
+(no compute call: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+from conftest import ROOT
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "qp_pt2.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qp_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for fn in ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
+               "qp_pt2_backward", "qp_energy"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1902_08154_amd import _lib
+    assert os.path.exists(_lib.LIB_PATH), "build the library first"
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for fn in _declared():
+        assert hasattr(lib, fn), fn
+    assert set(_lib.EXPORTS) == set(_declared())
+
+
+def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
+    from paper_1902_08154_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    import pytest
+    with pytest.raises(ImportError):
+        _lib.load()
+
+
+def test_stats_struct_layout():
+    from paper_1902_08154_amd import _lib
+    assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 8 * (4 + 1 + 3)
