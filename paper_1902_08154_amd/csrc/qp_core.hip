@@ -61,7 +61,7 @@ __global__ void build_Y(const double *eri, int n, double *Y)
 
 // Cj[j][p][q] = (pq|jj), Xj[j][p][q] = (pj|jq), Jm[p][q] = (pp|qq), Km[p][q] = (pq|qp)
 __global__ void build_small(const double *eri, const double *h, int n, double *Cj, double *Xj,
-                            double *Jm, double *Km, double *hc)
+                            double *Jm, double *Km, double *JK, double *hc)
 {
     const int64_t n3 = (int64_t)n * n * n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3;
@@ -73,6 +73,7 @@ __global__ void build_small(const double *eri, const double *h, int n, double *C
         if (j == 0) {
             Jm[pq] = packed_eri(eri, p, p, q, q);
             Km[pq] = packed_eri(eri, p, q, q, p);
+            JK[pq] = Jm[pq] - Km[pq];
             hc[pq] = h[pq];
         }
     }
@@ -104,6 +105,9 @@ struct Scalars {
     unsigned long long conn_total;
     unsigned long long coarse_total;
     unsigned long long comp_count;
+    unsigned long long def_count;       // batches deferred to the general kernel
+    unsigned int item_counter2;         // general kernel's item counter
+    unsigned int pad2;
     int bad_bits;     // a bit set at >= n_orb
     int bad_elec;     // electron counts differ from det 0
     int dup;          // duplicate determinant
@@ -413,32 +417,61 @@ __global__ void make_coff(const int64_t *offs, int64_t n_det, int nchunk, const 
 
 // ---------------------------------------------------------------- reductions
 // per generator: sum its items in order; eps_gen in the caller's index
+// Deferred partials of one generator, in increasing batch order (its list is
+// built by atomic pushes, so it is re-ordered here for a fixed summation order).
+struct DefParts {
+    const int *head, *next;
+    const uint32_t *b;
+    const double *eps, *S, *dc;
+    const uint32_t *cnt;
+    const uint64_t *fp;
+};
+
 __global__ void reduce_items(const double *eps_item, const double *S_item, const uint32_t *cnt_item,
-                             const uint64_t *fp_item, const double *dc_item, int64_t n_det, int nel, int ns,
+                             const uint64_t *fp_item, const double *dc_item, int64_t n_det, int nq, int ns,
                              const int32_t *perm, double *eps_g, double *S_g, uint64_t *cnt_g, uint64_t *fp_g,
-                             double *eps_gen, double *dc)
+                             double *eps_gen, double *dc, DefParts dp)
 {
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= n_det) return;
     const int det = perm[g];
-    for (int k = 0; k < ns; ++k) {
-        double e = 0.0, s = 0.0, d = 0.0;
-        for (int i = 0; i < nel; ++i) {
-            int64_t sl = g * nel + i;
-            e += eps_item[sl * ns + k];
-            s += S_item[sl * ns + k];
-            if (dc_item) d += dc_item[sl * ns + k];
-        }
-        eps_g[g * ns + k] = e;
-        S_g[g * ns + k] = s;
-        if (eps_gen) eps_gen[k * n_det + det] = e;
-        if (dc_item && dc) dc[k * n_det + det] += d;
-    }
+    double e[QPD_MAX_STATES] = {0, 0, 0, 0}, s[QPD_MAX_STATES] = {0, 0, 0, 0}, d[QPD_MAX_STATES] = {0, 0, 0, 0};
     uint64_t c = 0, f = 0;
-    for (int i = 0; i < nel; ++i) {
-        int64_t sl = g * nel + i;
+    for (int i = 0; i < nq; ++i) {
+        const int64_t sl = g * nq + i;
+        for (int k = 0; k < ns; ++k) {
+            e[k] += eps_item[sl * ns + k];
+            s[k] += S_item[sl * ns + k];
+            if (dc_item) d[k] += dc_item[sl * ns + k];
+        }
         c += cnt_item[sl];
         if (fp_item) f += fp_item[sl];
+    }
+    if (dp.head) {
+        int64_t last = -1;
+        for (;;) {
+            int best = -1;
+            int64_t bb = INT64_MAX;
+            for (int x = dp.head[g]; x >= 0; x = dp.next[x]) {
+                const int64_t bx = dp.b[x];
+                if (bx > last && bx < bb) { bb = bx; best = x; }
+            }
+            if (best < 0) break;
+            for (int k = 0; k < ns; ++k) {
+                e[k] += dp.eps[(int64_t)best * ns + k];
+                s[k] += dp.S[(int64_t)best * ns + k];
+                if (dc_item && dp.dc) d[k] += dp.dc[(int64_t)best * ns + k];
+            }
+            c += dp.cnt[best];
+            if (fp_item && dp.fp) f += dp.fp[best];
+            last = bb;
+        }
+    }
+    for (int k = 0; k < ns; ++k) {
+        eps_g[g * ns + k] = e[k];
+        S_g[g * ns + k] = s[k];
+        if (eps_gen) eps_gen[k * n_det + det] = e[k];
+        if (dc_item && dc) dc[k * n_det + det] += d[k];
     }
     cnt_g[g] = c;
     fp_g[g] = f;
@@ -599,7 +632,8 @@ struct qp_ctx {
     int device = 0;
     std::string err;
     int n = 0;
-    double *h = nullptr, *X = nullptr, *Y = nullptr, *Cj = nullptr, *Xj = nullptr, *Jm = nullptr, *Km = nullptr;
+    double *h = nullptr, *X = nullptr, *Y = nullptr, *Cj = nullptr, *Xj = nullptr, *Jm = nullptr, *Km = nullptr,
+           *JK = nullptr;
     std::vector<DevBuf> bufs;
     int num_cu = 256;
     Scalars *host_sc = nullptr;   // pinned
@@ -614,7 +648,7 @@ namespace {
 enum BufId {
     B_W, B_IDX, B_RANK, B_F, B_HII, B_COUNTS, B_OFFS, B_BSUM, B_COFF, B_CENT, B_EPSI, B_SI, B_CNTI, B_FPI,
     B_DCI, B_EPSG, B_SG, B_CNTG, B_FPG, B_SC, B_HIST, B_CAND, B_COMP, B_SKEY, B_SBITS, B_SIDX, B_MAXC2,
-    B_ROW, B_C2, B_TOTAL, B_COUNT
+    B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFN, B_DEFH, B_DEFE, B_DEFS, B_DEFC, B_DEFF, B_DEFD, B_COUNT
 };
 
 int fail(qp_ctx *c, int code, const std::string &msg)
@@ -799,14 +833,80 @@ DevInts dev_ints(const qp_ctx *c)
 {
     DevInts I;
     I.n = c->n; I.h = c->h; I.X = c->X; I.Y = c->Y; I.Cj = c->Cj; I.Xj = c->Xj; I.Jm = c->Jm; I.Km = c->Km;
+    I.JK = c->JK;
     return I;
 }
 
-int sweep_grid(qp_ctx *c)
+template <int NINT>
+int occ_ns(int n, int ns, bool bwd)
 {
-    // several resident workgroups per CU; the kernel's LDS use caps this
-    return c->num_cu * 4;
+    switch (ns) {
+    case 1: return bwd ? sweep_occupancy<NINT, 1, true>(n) : sweep_occupancy<NINT, 1, false>(n);
+    case 2: return bwd ? sweep_occupancy<NINT, 2, true>(n) : sweep_occupancy<NINT, 2, false>(n);
+    case 3: return bwd ? sweep_occupancy<NINT, 3, true>(n) : sweep_occupancy<NINT, 3, false>(n);
+    default: return bwd ? sweep_occupancy<NINT, 4, true>(n) : sweep_occupancy<NINT, 4, false>(n);
+    }
 }
+
+// persistent grid: every resident one-wavefront workgroup the CUs can hold
+int sweep_grid(qp_ctx *c, int nint, int ns, bool bwd)
+{
+    int per_cu = 8;
+    switch (nint) {
+    case 1: per_cu = occ_ns<1>(c->n, ns, bwd); break;
+    case 2: per_cu = occ_ns<2>(c->n, ns, bwd); break;
+    case 3: per_cu = occ_ns<3>(c->n, ns, bwd); break;
+    default: per_cu = occ_ns<4>(c->n, ns, bwd); break;
+    }
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 32) per_cu = 32;
+    return c->num_cu * per_cu;
+}
+
+template <int NINT>
+int focc_ns(int n, int ns, bool bwd, int rc, int cc)
+{
+    switch (ns) {
+    case 1: return bwd ? fast_occupancy<NINT, 1, true>(n, rc, cc) : fast_occupancy<NINT, 1, false>(n, rc, cc);
+    case 2: return bwd ? fast_occupancy<NINT, 2, true>(n, rc, cc) : fast_occupancy<NINT, 2, false>(n, rc, cc);
+    case 3: return bwd ? fast_occupancy<NINT, 3, true>(n, rc, cc) : fast_occupancy<NINT, 3, false>(n, rc, cc);
+    default: return bwd ? fast_occupancy<NINT, 4, true>(n, rc, cc) : fast_occupancy<NINT, 4, false>(n, rc, cc);
+    }
+}
+
+int fast_grid(qp_ctx *c, int nint, int ns, bool bwd, int rc, int cc)
+{
+    int per_cu = 8;
+    switch (nint) {
+    case 1: per_cu = focc_ns<1>(c->n, ns, bwd, rc, cc); break;
+    case 2: per_cu = focc_ns<2>(c->n, ns, bwd, rc, cc); break;
+    case 3: per_cu = focc_ns<3>(c->n, ns, bwd, rc, cc); break;
+    default: per_cu = focc_ns<4>(c->n, ns, bwd, rc, cc); break;
+    }
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 32) per_cu = 32;
+    return c->num_cu * per_cu;
+}
+
+template <int NINT, int NS>
+void fast_dispatch_ns(const SweepArgs &a, int grid, bool bwd, hipStream_t st)
+{
+    if (bwd) launch_fast<NINT, NS, true>(a, grid, st);
+    else launch_fast<NINT, NS, false>(a, grid, st);
+}
+
+template <int NINT>
+void fast_dispatch(const SweepArgs &a, int grid, bool bwd, hipStream_t st)
+{
+    switch (a.ns) {
+    case 1: fast_dispatch_ns<NINT, 1>(a, grid, bwd, st); break;
+    case 2: fast_dispatch_ns<NINT, 2>(a, grid, bwd, st); break;
+    case 3: fast_dispatch_ns<NINT, 3>(a, grid, bwd, st); break;
+    default: fast_dispatch_ns<NINT, 4>(a, grid, bwd, st); break;
+    }
+}
+
+constexpr int Q_PER_GEN = 4;
 
 int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int ns, const double *E0,
               int64_t n_select, int flags, bool bwd, const double *gup, double *e_pt2, uint64_t *sel_dets,
@@ -821,7 +921,8 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     int rc = prepare(c, nint, dets, coefs, n_det, ns, flags, st, P);
     if (rc != QP_OK) return rc;
     const int nel = P.nel;
-    const int64_t n_items = n_det * nel;
+    const int Q = Q_PER_GEN;
+    const int64_t n_items = n_det * Q;
     double *eps_item = (double *)scratch(c, B_EPSI, sizeof(double) * std::max<int64_t>(1, n_items) * ns);
     double *S_item = (double *)scratch(c, B_SI, sizeof(double) * std::max<int64_t>(1, n_items) * ns);
     uint32_t *cnt_item = (uint32_t *)scratch(c, B_CNTI, sizeof(uint32_t) * std::max<int64_t>(1, n_items));
@@ -834,7 +935,24 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     unsigned int *hist = (unsigned int *)scratch(c, B_HIST, sizeof(unsigned int) * QP_HIST_BINS);
     if (!eps_item || !S_item || !cnt_item || !fp_item || (bwd && !dc_item) || !eps_g || !S_g || !cnt_g || !fp_g || !hist)
         return fail(c, QP_E_OOM, "device allocation failed (sweep buffers)");
-    const int grid = sweep_grid(c);
+    const int rscap = n <= 128 ? 4 : 2, cscap = n <= 128 ? 4 : 2;
+    const int fgrid = fast_grid(c, nint, ns, bwd, rscap, cscap);
+    const int ggrid = sweep_grid(c, nint, ns, bwd);
+    const int grid = std::max(fgrid, ggrid);
+    // batches the fast kernel hands to the general kernel
+    const int64_t def_cap = std::max<int64_t>(1 << 16, 16 * n_det);
+    uint32_t *def_g = (uint32_t *)scratch(c, B_DEFG, sizeof(uint32_t) * def_cap);
+    uint32_t *def_b = (uint32_t *)scratch(c, B_DEFB, sizeof(uint32_t) * def_cap);
+    int *def_next = (int *)scratch(c, B_DEFN, sizeof(int) * def_cap);
+    int *def_head = (int *)scratch(c, B_DEFH, sizeof(int) * n_det);
+    double *def_eps = (double *)scratch(c, B_DEFE, sizeof(double) * def_cap * ns);
+    double *def_S = (double *)scratch(c, B_DEFS, sizeof(double) * def_cap * ns);
+    uint32_t *def_cnt = (uint32_t *)scratch(c, B_DEFC, sizeof(uint32_t) * def_cap);
+    uint64_t *def_fp = (uint64_t *)scratch(c, B_DEFF, sizeof(uint64_t) * def_cap);
+    double *def_dc = bwd ? (double *)scratch(c, B_DEFD, sizeof(double) * def_cap * ns) : nullptr;
+    if (!def_g || !def_b || !def_next || !def_head || !def_eps || !def_S || !def_cnt || !def_fp || (bwd && !def_dc))
+        return fail(c, QP_E_OOM, "device allocation failed (deferred batches)");
+    HIPCHK(c, hipMemsetAsync(def_head, 0xFF, sizeof(int) * n_det, st));
     int64_t cand_cap = 0;
     Cand *cand = nullptr;
     if (n_select > 0) {
@@ -859,6 +977,7 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     a.n_det = n_det; a.dets = dets; a.coefs = coefs; a.E0 = E0;
     a.perm = P.perm; a.F = P.F; a.HII = P.HII; a.coff = P.coff; a.cent = P.cent;
     a.n_items = n_items;
+    a.q_per_gen = Q;
     a.item_counter = &P.sc->item_counter;
     a.flags = ((flags & QP_FLAG_FINGERPRINT) ? 1 : 0) | (bwd ? 2 : 0);
     a.eps_item = eps_item; a.S_item = S_item; a.cnt_item = cnt_item; a.fp_item = fp_item;
@@ -872,23 +991,63 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     a.cand = cand; a.cand_count = &P.sc->cand_count; a.cand_cap = cand_cap; a.hist = hist;
     a.tau_bin = &P.sc->tau_bin; a.overflow = &P.sc->overflow;
     a.gup = gup; a.dc_item = dc_item; a.dc = grad_coefs; a.dh = grad_h;
+    a.rscap = rscap; a.cscap = cscap;
+    a.def_mode = 0;
+    a.def_g = def_g; a.def_b = def_b; a.def_next = def_next; a.def_head = def_head;
+    a.def_count = &P.sc->def_count; a.def_cap = def_cap;
+    // the general kernel on the deferred batches: its own counter and slots
+    SweepArgs d = a;
+    d.def_mode = 1;
+    d.item_counter = &P.sc->item_counter2;
+    d.eps_item = def_eps; d.S_item = def_S; d.cnt_item = def_cnt; d.fp_item = def_fp; d.dc_item = def_dc;
 
+    bool deferred_used = true;
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], st));
-    if (n_items > 0) {
+    if (n_items > 0 && nel > 0) {
         switch (nint) {
-        case 1: sweep_dispatch<1>(a, grid, bwd, st); break;
-        case 2: sweep_dispatch<2>(a, grid, bwd, st); break;
-        case 3: sweep_dispatch<3>(a, grid, bwd, st); break;
-        default: sweep_dispatch<4>(a, grid, bwd, st); break;
+        case 1: fast_dispatch<1>(a, fgrid, bwd, st); sweep_dispatch<1>(d, ggrid, bwd, st); break;
+        case 2: fast_dispatch<2>(a, fgrid, bwd, st); sweep_dispatch<2>(d, ggrid, bwd, st); break;
+        case 3: fast_dispatch<3>(a, fgrid, bwd, st); sweep_dispatch<3>(d, ggrid, bwd, st); break;
+        default: fast_dispatch<4>(a, fgrid, bwd, st); sweep_dispatch<4>(d, ggrid, bwd, st); break;
+        }
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(c->host_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (c->host_sc->overflow & 2ull) {
+            // deferred list overflowed: redo everything with the general kernel
+            deferred_used = false;
+            HIPCHK(c, hipMemsetAsync(&P.sc->item_counter, 0, sizeof(unsigned int), st));
+            HIPCHK(c, hipMemsetAsync(&P.sc->cand_count, 0, sizeof(unsigned long long), st));
+            HIPCHK(c, hipMemsetAsync(&P.sc->overflow, 0, sizeof(unsigned long long), st));
+            HIPCHK(c, hipMemsetAsync(&P.sc->tau_bin, 0, sizeof(int), st));
+            HIPCHK(c, hipMemsetAsync(&P.sc->conn_total, 0, sizeof(unsigned long long), st));
+            HIPCHK(c, hipMemsetAsync(hist, 0, sizeof(unsigned int) * QP_HIST_BINS, st));
+            if (bwd) {
+                if (grad_coefs) HIPCHK(c, hipMemsetAsync(grad_coefs, 0, sizeof(double) * ns * n_det, st));
+                if (grad_h) HIPCHK(c, hipMemsetAsync(grad_h, 0, sizeof(double) * n * n, st));
+            }
+            switch (nint) {
+            case 1: sweep_dispatch<1>(a, ggrid, bwd, st); break;
+            case 2: sweep_dispatch<2>(a, ggrid, bwd, st); break;
+            case 3: sweep_dispatch<3>(a, ggrid, bwd, st); break;
+            default: sweep_dispatch<4>(a, ggrid, bwd, st); break;
+            }
+            HIPCHK(c, hipGetLastError());
         }
     } else {
         HIPCHK(c, hipMemsetAsync(eps_item, 0, sizeof(double) * ns, st));
+        deferred_used = false;
     }
-    HIPCHK(c, hipGetLastError());
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
+    DefParts dp;
+    memset(&dp, 0, sizeof(dp));
+    if (deferred_used) {
+        dp.head = def_head; dp.next = def_next; dp.b = def_b; dp.eps = def_eps; dp.S = def_S; dp.dc = def_dc;
+        dp.cnt = def_cnt; dp.fp = def_fp;
+    }
     hipLaunchKernelGGL(reduce_items, dim3(grid_for(n_det)), dim3(256), 0, st, eps_item, S_item, cnt_item,
-                       (flags & QP_FLAG_FINGERPRINT) ? fp_item : (uint64_t *)nullptr, dc_item, n_det, nel, ns,
-                       P.perm, eps_g, S_g, cnt_g, fp_g, bwd ? nullptr : eps_gen, bwd ? grad_coefs : nullptr);
+                       (flags & QP_FLAG_FINGERPRINT) ? fp_item : (uint64_t *)nullptr, dc_item, n_det, Q, ns,
+                       P.perm, eps_g, S_g, cnt_g, fp_g, bwd ? nullptr : eps_gen, bwd ? grad_coefs : nullptr, dp);
     const int64_t n_cells = n_det * cells_per_generator(n, P.nup, P.ndn);
     hipLaunchKernelGGL(reduce_total, dim3(1), dim3(256), 0, st, eps_g, S_g, cnt_g, fp_g, n_det, ns,
                        bwd ? nullptr : e_pt2, stats, P.sc, n_cells, gup, bwd ? grad_E0 : nullptr);
@@ -902,7 +1061,7 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
         HIPCHK(c, hipMemcpyAsync(c->host_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         const Scalars hs = *c->host_sc;
-        if (hs.overflow) return fail(c, QP_E_OVERFLOW, "selection candidate buffer overflowed");
+        if (hs.overflow & 1ull) return fail(c, QP_E_OVERFLOW, "selection candidate buffer overflowed");
         const int64_t M = (int64_t)hs.comp_count;
         const int64_t m = std::min<int64_t>(M, n_select);
         const int64_t PP = pow2_at_least(std::max<int64_t>(M, 1));
@@ -969,7 +1128,7 @@ void qp_destroy(qp_ctx *c)
     (void)hipDeviceSynchronize();
     for (auto &b : c->bufs) if (b.p) (void)hipFree(b.p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
-    double *arrs[] = {c->h, c->X, c->Y, c->Cj, c->Xj, c->Jm, c->Km};
+    double *arrs[] = {c->h, c->X, c->Y, c->Cj, c->Xj, c->Jm, c->Km, c->JK};
     for (double *p : arrs) if (p) (void)hipFree(p);
     if (c->host_sc) (void)hipHostFree(c->host_sc);
     if (c->host_det0) (void)hipHostFree(c->host_det0);
@@ -990,7 +1149,7 @@ int qp_set_integrals(qp_ctx *c, const double *h, const double *eri_packed, int n
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(c, hipStreamSynchronize(st));
-    double **arrs[] = {&c->h, &c->X, &c->Y, &c->Cj, &c->Xj, &c->Jm, &c->Km};
+    double **arrs[] = {&c->h, &c->X, &c->Y, &c->Cj, &c->Xj, &c->Jm, &c->Km, &c->JK};
     for (double **p : arrs) if (*p) { (void)hipFree(*p); *p = nullptr; }
     c->n = 0;
     const int64_t n = n_orb;
@@ -1001,7 +1160,7 @@ int qp_set_integrals(qp_ctx *c, const double *h, const double *eri_packed, int n
     if (hipMalloc(&c->X, nX * 8) != hipSuccess || hipMalloc(&c->Y, nY * 8) != hipSuccess ||
         hipMalloc(&c->Cj, n3 * 8) != hipSuccess || hipMalloc(&c->Xj, n3 * 8) != hipSuccess ||
         hipMalloc(&c->Jm, n2 * 8) != hipSuccess || hipMalloc(&c->Km, n2 * 8) != hipSuccess ||
-        hipMalloc(&c->h, n2 * 8) != hipSuccess) {
+        hipMalloc(&c->JK, n2 * 8) != hipSuccess || hipMalloc(&c->h, n2 * 8) != hipSuccess) {
         (void)hipGetLastError();
         for (double **p : arrs) if (*p) { (void)hipFree(*p); *p = nullptr; }
         return fail(c, QP_E_OOM, "device allocation failed (integral layouts)");
@@ -1010,7 +1169,7 @@ int qp_set_integrals(qp_ctx *c, const double *h, const double *eri_packed, int n
     if (P2 > 0)
         hipLaunchKernelGGL(build_Y, dim3(grid_for((int64_t)(P2 * P2), 256, 1 << 16)), dim3(256), 0, st, eri_packed, n_orb, c->Y);
     hipLaunchKernelGGL(build_small, dim3(grid_for((int64_t)n3, 256, 1 << 16)), dim3(256), 0, st, eri_packed, h, n_orb,
-                       c->Cj, c->Xj, c->Jm, c->Km, c->h);
+                       c->Cj, c->Xj, c->Jm, c->Km, c->JK, c->h);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     c->n = n_orb;

@@ -13,7 +13,7 @@
 //       antisymmetrised block per hole pair.            (n(n-1)/2)^2
 //   Cj[j][p][q] = (pq|jj),  Xj[j][p][q] = (pj|jq)     n^3 each
 //       Coulomb/exchange slices for Fock elements F^J_pq of any determinant.
-//   Jm[p][q] = (pp|qq),  Km[p][q] = (pq|qp)           n^2 each
+//   Jm[p][q] = (pp|qq),  Km[p][q] = (pq|qp),  JK = Jm - Km   n^2 each
 //   tri(a,b) = b(b+1)/2 + a (a<=b),  tris(a,b) = b(b-1)/2 + a (a<b)
 #pragma once
 #include <hip/hip_runtime.h>
@@ -33,6 +33,7 @@ struct DevInts {
     const double *Xj;
     const double *Jm;
     const double *Km;
+    const double *JK;  // Jm - Km: same-spin pair interaction
 };
 
 __device__ __forceinline__ int64_t qtri(int64_t a, int64_t b) { return b * (b + 1) / 2 + a; }
@@ -238,7 +239,16 @@ struct SweepArgs {
     const int64_t *coff;      // [n_det+1], by rank
     const CoarseEnt *cent;
     int64_t n_items;
+    int q_per_gen;            // work items per generator
     unsigned int *item_counter;
+    // fast kernel: buffer capacities and the deferred-batch list
+    int rscap, cscap;
+    int def_mode;             // general kernel: items are the deferred batches
+    uint32_t *def_g, *def_b;  // deferred (generator rank, batch)
+    int *def_next;            // per-generator linked list of deferred batches
+    int *def_head;            // [n_det], -1 terminated
+    unsigned long long *def_count;
+    int64_t def_cap;
     int flags;                // bit0 fingerprint, bit1 backward
     // per-item partials (deterministic reduction later)
     double *eps_item;         // [n_items][ns]
@@ -266,3 +276,9 @@ struct SweepArgs {
 
 template <int NINT, int NS, bool BWD>
 void launch_sweep(const SweepArgs &a, int grid, hipStream_t st);
+template <int NINT, int NS, bool BWD>
+int sweep_occupancy(int n);
+template <int NINT, int NS, bool BWD>
+void launch_fast(const SweepArgs &a, int grid, hipStream_t st);
+template <int NINT, int NS, bool BWD>
+int fast_occupancy(int n, int rscap, int cscap);

@@ -4,835 +4,887 @@
 // Work decomposition (sec. "CIPSI selection and PT2 energy", appendix on the
 // selection implementation): generators I in order of decreasing sum_k c_Ik^2;
 // for each I the external determinants alpha = I - H + P are enumerated by
-// hole set H (|H| = 1 or 2, exact holes) and particle set P (virtual orbitals
-// of I of matching spins), so each (I, alpha) pair appears exactly once.  A
-// batch is one hole set; its cells are the particle sets.  A work item is
-// (generator, first hole h1): the single batch {h1} plus every double batch
-// {h1, h2} with h2 after h1 in spin-orbital order.  A persistent grid takes
-// items from an atomic counter.
+// hole set H (|H| = 1 or 2, the exact holes) and particle set P (virtual
+// orbitals of I with matching spins), so each (I, alpha) pair appears once.
+// A batch is one hole set; its cells are the particle sets.
 //
-// Per batch:
-//   * the generator's own element <I|H|alpha> is a closed form per cell: a
-//     separable phase (hole part x row part x column part) times one coalesced
-//     read of the per-hole-pair integral block (X for opposite spins, Y for
-//     same spin) or a Fock element of I (singles);
-//   * the diagonal <alpha|H|alpha> is the ionised-determinant energy plus two
-//     per-particle Fock terms plus one pair term (Fock-diagonal update of the
-//     same appendix);
-//   * other internal determinants J within degree 4 of I (coarse list) that
-//     pass the fine filter m = |(I-H) \ J| <= 2 touch only the cells with
-//     |P \ J| <= 2 - m: all cells (m = 0), rows/columns (m = 1) or a few
-//     cells (m = 2).  They are scattered into an LDS tile: J earlier in the
-//     generator order bans the cell (alpha belongs to an earlier generator),
-//     J = alpha bans it (alpha is internal), otherwise c_J <J|H|alpha> is
-//     added.  Batches without such J skip the tile entirely.
-//   * finalise: e_k = A_k^2 / (E0_k - D), partial sums, selection candidates
-//     above the running global threshold.
+// One workgroup is one wavefront.  A work item is (generator, q): every Q-th
+// batch of the generator starting at q.  Inside a batch the cells form a
+// row x column grid (opposite spins: the two virtual lists; same spin: the
+// triangle p1 < p2 folded into rows of full width; singles: one row).  Lanes
+// run over the contiguous column index and the loop runs over rows, so
+// row-dependent quantities are wavefront-uniform and every integral read is a
+// coalesced row of a per-hole-pair block.
+//
+// Per cell:  <I|H|alpha> = phase * block element (or a Fock element of I for
+// singles); H_alpha,alpha = E(I - H) + F(p1) + F(p2) + pair(p1, p2), the
+// Fock-diagonal update of the same appendix; e_k = A_k^2 / (E0_k - D).
+//
+// Other internal determinants J within degree 4 of I (coarse list) pass the
+// fine filter m = |(I - H) \ J| <= 2 and touch only cells with
+// |P \ J| <= 2 - m.  They are corrections: a J earlier in generator order
+// bans the cell (alpha belongs to an earlier generator), J = alpha bans it,
+// otherwise c_J <J|H|alpha> is added.  Their elements are evaluated with all
+// lanes busy: m = 2 cells in a per-batch list, the column part of m = 1 in a
+// per-batch column buffer (lanes over rows); the row part of m = 1 and m = 0
+// entries are evaluated while their row is processed ("inline").
 #include "qp_dev.h"
 
 namespace {
 
-struct FineEnt {
-    int j;
-    int m;
-    int earlier;
-    uint16_t E[4];
-};
+constexpr int WAVE = 64;
+constexpr int FCAP = 64;     // fine entries kept per batch
+constexpr int L2CAP = 64;    // m = 2 cells per batch
+constexpr int CSCAP = 2;     // column segments per batch
+constexpr int ICAP = 16;     // inline entries per batch
 
-#define FCAP 64
+struct FineE {
+    int32_t j;
+    uint8_t m, earlier, ner, nec;   // ner / nec: particles of E on the row / column spin
+    uint32_t er;                    // row-spin virtual indices of E = J \ I, one per byte
+    uint32_t ec;                    // column-spin virtual indices of E (opposite spins)
+};
 
 struct Batch {
-    int type;       // BT_*
-    int s1, h1;     // first hole (spin, orbital)
-    int s2, h2;     // second hole (double batches)
-    int rs, cs;     // row / column spin (OS); SS and SINGLE use rs only
-    int nr, nc;     // rows / columns (OS); V for SS and SINGLE
-    int64_t ncell;
-    int sH;         // hole part of the phase (0/1)
-    double D0;      // energy of the ionised determinant I - H
-    const double *blk;  // integral block base (X or Y row)
+    int type;        // BT_*
+    int s1, h1, s2, h2;
+    int rs, cs;      // row / column spins
+    int nr, nc;      // OS: rows, columns; SS and SINGLE: V
+    int sH;          // hole part of the phase
+    double D0;       // energy of I - H
+    const double *blk;
 };
 
-__device__ __forceinline__ void wg_barrier() { __syncthreads(); }
+__device__ __forceinline__ double fast_rcp(double d)
+{
+    // reciprocal to about one ulp: hardware estimate and two Newton steps
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    return d == 0.0 ? copysign(__builtin_inf(), d) : r;
+}
 
-// decode SS triangle index c -> (i1 < i2), c = i2(i2-1)/2 + i1
-__device__ __forceinline__ void tri_decode(int64_t c, int &i1, int &i2)
+__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ void tri_decode(int c, int &i1, int &i2)
 {
     int t = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)c)) * 0.5f);
-    while ((int64_t)t * (t - 1) / 2 > c) --t;
-    while ((int64_t)(t + 1) * t / 2 <= c) ++t;
+    while (t * (t - 1) / 2 > c) --t;
+    while ((t + 1) * t / 2 <= c) ++t;
     i2 = t;
-    i1 = (int)(c - (int64_t)t * (t - 1) / 2);
+    i1 = c - t * (t - 1) / 2;
+}
+
+// carve a typed array out of the dynamic LDS block: offset arithmetic only,
+// so the compiler keeps the LDS address space (ds_* instead of flat_*)
+template <typename T>
+__device__ __forceinline__ T *carve(unsigned char *base, unsigned &off, int count)
+{
+    off = (off + 15u) & ~15u;
+    T *r = reinterpret_cast<T *>(base + off);
+    off += (unsigned)(sizeof(T) * (unsigned)count);
+    return r;
+}
+
+// is x among the first nv bytes of v
+__device__ __forceinline__ bool has(uint32_t v, int nv, int x)
+{
+    bool r = false;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) r |= (t < nv) && ((int)((v >> (8 * t)) & 255u) == x);
+    return r;
+}
+__device__ __forceinline__ int byte_at(uint32_t v, int t) { return (int)((v >> (8 * t)) & 255u); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
 }
 
 }  // namespace
 
-template <int NINT, int NS, bool BWD>
-__global__ __launch_bounds__(QPD_WG) void sweep_kernel(SweepArgs a)
+// generic <J|H|alpha>, alpha = I with the holes removed and the particles
+// added; out of line so the dense loop keeps a small register budget
+template <int NINT>
+__device__ __noinline__ double corr_element(const DevInts I, const uint64_t *Ibits, int h0, int h1c, int pa,
+                                            int sa, int pb, int sb, const uint64_t *J, int *deg, int *sgl)
 {
-    constexpr int SLAB = (BWD ? 2048 : 3072) / NS;
-    constexpr int NWAVE = QPD_WG / 64;
+    uint64_t al[2 * NINT];
+#pragma unroll
+    for (int w = 0; w < 2 * NINT; ++w) al[w] = Ibits[w];
+    al[(h0 >> 8) * NINT + ((h0 & 255) >> 6)] ^= 1ull << (h0 & 63);
+    if (h1c >= 0) al[(h1c >> 8) * NINT + ((h1c & 255) >> 6)] ^= 1ull << (h1c & 63);
+    al[sa * NINT + (pa >> 6)] ^= 1ull << (pa & 63);
+    if (pb >= 0) al[sb * NINT + (pb >> 6)] ^= 1ull << (pb & 63);
+    uint64_t Jb[2 * NINT];
+#pragma unroll
+    for (int w = 0; w < 2 * NINT; ++w) Jb[w] = J[w];
+    return sc_offdiag<NINT>(I, al, Jb, deg, sgl);
+}
 
-    __shared__ double s_F[2][QPD_MAX_ORB];
-    __shared__ double s_G[2][QPD_MAX_ORB];
-    __shared__ uint8_t s_sg[2][QPD_MAX_ORB];
-    __shared__ uint8_t s_occ[2][QPD_MAX_ORB];
-    __shared__ uint8_t s_virt[2][QPD_MAX_ORB];
-    __shared__ uint8_t s_cnt[2][QPD_MAX_ORB];
-    __shared__ uint16_t s_vidx[2][QPD_MAX_ORB];
-    __shared__ uint64_t s_I[2 * NINT];
-    __shared__ double s_tile[NS * SLAB];
-    __shared__ double s_vt[BWD ? SLAB : 1];
-    __shared__ double s_dhd[BWD ? QPD_MAX_ORB : 1];
-    __shared__ double s_dhrow[BWD ? QPD_MAX_ORB : 1];
-    __shared__ uint32_t s_ban[(SLAB + 31) / 32];
-    __shared__ FineEnt s_fine[FCAP];
-    __shared__ double s_fc[FCAP][NS];
-    __shared__ int s_nfine;
-    __shared__ int64_t s_fpos;
-    __shared__ int s_item_ok;
-    __shared__ unsigned int s_item;
-    __shared__ int s_appended;
-    __shared__ uint64_t s_tau_key;
-    __shared__ double s_red[NWAVE][2 * NS + 2];
-    __shared__ uint64_t s_redu[NWAVE][3];
-    __shared__ double s_HII;
-    __shared__ double s_vtot;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
+template <int NINT, int NS, bool BWD>
+__global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     const int n = a.n;
+    const int lane = threadIdx.x;
     const int64_t n2 = (int64_t)n * n;
-    const int nel = a.nel;
     const int P2 = n * (n - 1) / 2;
+    const int nel = a.nel;
+    const int nb = nel + nel * (nel - 1) / 2;
+    const int Q = a.q_per_gen;
     const bool want_fp = (a.flags & 1) != 0;
     const bool want_sel = a.n_select > 0;
 
-    double cI[NS], E0[NS], gup[NS];
+    // ----------------------------------------------------------- LDS layout
+    unsigned lo_ = 0;
+    double *sF = carve<double>(lds_raw, lo_, 2 * n);                   // Fock diagonal of I [spin][p]
+    double *sRG = carve<double>(lds_raw, lo_, QPD_MAX_ORB);            // row vector: diagonal offset
+    double *sCB = carve<double>(lds_raw, lo_, CSCAP * QPD_MAX_ORB);    // column-segment elements
+    double *sFC = carve<double>(lds_raw, lo_, FCAP * NS);              // c_Jk of fine entries
+    double *sL2H = carve<double>(lds_raw, lo_, L2CAP);                 // m = 2 cell elements
+    double *sDCF = carve<double>(lds_raw, lo_, BWD ? FCAP * NS : 1);   // adjoint: dE/dc_J per entry
+    double *sDHD = carve<double>(lds_raw, lo_, BWD ? n : 1);           // adjoint: diagonal of dE/dh
+    uint64_t *sI = carve<uint64_t>(lds_raw, lo_, 2 * NINT);
+    FineE *sFine = carve<FineE>(lds_raw, lo_, FCAP);
+    uint32_t *sL2 = carve<uint32_t>(lds_raw, lo_, L2CAP);              // i1 | i2 << 8 | fine << 16 | ban << 24
+    int32_t *sCS = carve<int32_t>(lds_raw, lo_, CSCAP);                // fine | col << 8
+    uint8_t *sIL = carve<uint8_t>(lds_raw, lo_, ICAP);                 // inline fine entries
+    uint16_t *sVidx = carve<uint16_t>(lds_raw, lo_, 2 * n);
+    uint8_t *sOcc = carve<uint8_t>(lds_raw, lo_, 2 * QPD_MAX_ORB);
+    uint8_t *sVirt = carve<uint8_t>(lds_raw, lo_, 2 * QPD_MAX_ORB);
+    uint8_t *sCnt = carve<uint8_t>(lds_raw, lo_, 2 * n);
+    uint8_t *sRS = carve<uint8_t>(lds_raw, lo_, QPD_MAX_ORB);          // row vector: phase bit
+    uint64_t *sRowBits = carve<uint64_t>(lds_raw, lo_, 4);             // rows holding m = 2 cells
+
+    double E0[NS], gup[NS], cI[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) { E0[k] = a.E0[k]; gup[k] = BWD ? a.gup[k] : 0.0; }
 
+    const int64_t n_def = a.def_mode ? (int64_t)(*a.def_count < (unsigned long long)a.def_cap ? *a.def_count
+                                                                                            : (unsigned long long)a.def_cap)
+                                     : 0;
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(a.item_counter, 1u);
-        wg_barrier();
-        const int64_t item = s_item;
-        if (item >= a.n_items) break;
-        const int ih = (int)(item / a.n_det);
-        const int64_t g = item - (int64_t)ih * a.n_det;
-        const int64_t slot = g * nel + ih;
+        int item0 = 0;
+        if (lane == 0) item0 = (int)atomicAdd(a.item_counter, 1u);
+        const int64_t item = (int64_t)(unsigned)rdlane(item0, 0);
+        int q, bstride;
+        int64_t g, slot;
+        if (a.def_mode) {
+            // one deferred batch per item; partials go to the item's own slot
+            if (item >= n_def) break;
+            g = a.def_g[item];
+            q = (int)a.def_b[item];
+            bstride = nb;
+            slot = item;
+        } else {
+            if (item >= a.n_items) break;
+            q = (int)(item / a.n_det);
+            g = item - (int64_t)q * a.n_det;
+            bstride = Q;
+            slot = g * Q + q;
+        }
         const int det = a.perm[g];
 
-        // ---------------------------------------------------------- generator
-        if (tid < 2 * NINT) s_I[tid] = a.dets[(int64_t)det * 2 * NINT + tid];
-        if (tid == 0) { s_HII = a.HII[g]; s_appended = 0; }
-        wg_barrier();
-        for (int x = tid; x < 2 * n; x += QPD_WG) {
-            int s = x / n, p = x - s * n;
-            const uint64_t *w = s_I + s * NINT;
+        // ------------------------------------------------------ generator data
+        uint64_t Ib[2 * NINT];
+#pragma unroll
+        for (int w = 0; w < 2 * NINT; ++w) Ib[w] = a.dets[(int64_t)det * 2 * NINT + w];
+        if (lane < 2 * NINT) sI[lane] = a.dets[(int64_t)det * 2 * NINT + lane];
+        for (int x = lane; x < 2 * n; x += WAVE) {
+            const int s = x >= n ? 1 : 0, p = x - s * n;
+            const uint64_t *w = Ib + s * NINT;
             int c = 0;
 #pragma unroll
-            for (int q = 0; q < NINT; ++q) {
-                if (64 * q + 63 < p) c += popc64(w[q]);
-                else if (64 * q <= p) c += popc64(w[q] & ((1ull << (p - 64 * q)) - 1ull));
+            for (int qq = 0; qq < NINT; ++qq) {
+                if (64 * qq + 63 < p) c += popc64(w[qq]);
+                else if (64 * qq <= p) c += popc64(w[qq] & ((1ull << (p - 64 * qq)) - 1ull));
             }
-            int occ = (int)((w[p >> 6] >> (p & 63)) & 1ull);
-            s_cnt[s][p] = (uint8_t)c;
-            if (occ) { s_occ[s][c] = (uint8_t)p; s_vidx[s][p] = 0xFFFF; }
-            else { s_virt[s][p - c] = (uint8_t)p; s_vidx[s][p] = (uint16_t)(p - c); }
-            s_F[s][p] = a.F[(g * 2 + s) * n + p];
-            if (BWD) { if (s == 0) s_dhd[p] = 0.0; }
+            const bool occ = (w[p >> 6] >> (p & 63)) & 1ull;
+            sCnt[x] = (uint8_t)c;
+            if (occ) { sOcc[s * QPD_MAX_ORB + c] = (uint8_t)p; sVidx[x] = 0xFFFF; }
+            else { sVirt[s * QPD_MAX_ORB + p - c] = (uint8_t)p; sVidx[x] = (uint16_t)(p - c); }
+            sF[x] = a.F[(g * 2) * n + x];
+            if (BWD && s == 0) sDHD[p] = 0.0;
         }
 #pragma unroll
         for (int k = 0; k < NS; ++k) cI[k] = a.coefs[(int64_t)k * a.n_det + det];
-        wg_barrier();
-
-        const int nup = a.nup, ndn = a.ndn;
-        const int nv0 = n - nup, nv1 = n - ndn;
-        const int s1 = ih < nup ? 0 : 1;
-        const int h1 = ih < nup ? s_occ[0][ih] : s_occ[1][ih - nup];
+        const double HII = a.HII[g];
         const int64_t cbeg = a.coff[g], cend = a.coff[g + 1];
+        __syncthreads();
+
+        const int nup = a.nup;
+        const int nv0 = n - a.nup, nv1 = n - a.ndn;
 
         double esum[NS], ssum[NS], dcI[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) { esum[k] = 0.0; ssum[k] = 0.0; dcI[k] = 0.0; }
         uint32_t cnt = 0, conn = 0;
         uint64_t fpsum = 0;
-        double mind = __longlong_as_double(0x7ff0000000000000ll);
-        double vtot = 0.0;   // BWD: sum over the item's alpha of v (for n_p(I))
+        double mind = __builtin_inf();
+        double vtot = 0.0;
 
-        const int nb = nel - ih;
-        for (int b = 0; b < nb; ++b) {
-            // ------------------------------------------------------ batch setup
+        for (int b = q; b < nb; b += bstride) {
+            // ---------------------------------------------------- batch setup
             Batch B;
-            B.s1 = s1; B.h1 = h1;
-            if (b == 0) {
-                B.type = BT_SINGLE; B.s2 = -1; B.h2 = -1;
-                B.rs = s1; B.cs = s1;
-                B.nr = s1 == 0 ? nv0 : nv1; B.nc = 1;
-                B.ncell = B.nr;
-                B.sH = 0;
-                B.D0 = s_HII - s_F[s1][h1];
-                B.blk = nullptr;
-            } else {
-                int i2 = ih + b;
-                B.s2 = i2 < nup ? 0 : 1;
-                B.h2 = i2 < nup ? s_occ[0][i2] : s_occ[1][i2 - nup];
-                if (B.s2 == s1) {
-                    B.type = BT_SS;
-                    B.rs = s1; B.cs = s1;
-                    B.nr = s1 == 0 ? nv0 : nv1; B.nc = B.nr;
-                    B.ncell = (int64_t)B.nr * (B.nr - 1) / 2;
-                    B.sH = (s_cnt[s1][B.h1] + s_cnt[s1][B.h2] - 1) & 1;
-                    B.D0 = s_HII - s_F[s1][B.h1] - s_F[s1][B.h2] + a.I.Jm[B.h1 * n + B.h2] -
-                           a.I.Km[B.h1 * n + B.h2];
-                    B.blk = a.I.Y + qtris(B.h1, B.h2) * (int64_t)P2;
-                } else {
-                    B.type = BT_OS;  // s1 = up, s2 = down
-                    if (B.h1 <= B.h2) { B.rs = 0; B.cs = 1; B.blk = a.I.X + qtri(B.h1, B.h2) * n2; }
-                    else { B.rs = 1; B.cs = 0; B.blk = a.I.X + qtri(B.h2, B.h1) * n2; }
-                    B.nr = B.rs == 0 ? nv0 : nv1;
-                    B.nc = B.cs == 0 ? nv0 : nv1;
-                    B.ncell = (int64_t)B.nr * B.nc;
-                    B.sH = (s_cnt[0][B.h1] + s_cnt[1][B.h2]) & 1;
-                    B.D0 = s_HII - s_F[0][B.h1] - s_F[1][B.h2] + a.I.Jm[B.h1 * n + B.h2];
-                }
-            }
-            // per-particle vectors: index 0 = row spin, 1 = column spin
             {
-                const int nvec = (B.type == BT_OS) ? 2 : 1;
-                for (int x = tid; x < nvec * QPD_MAX_ORB; x += QPD_WG) {
-                    int v = x / QPD_MAX_ORB, i = x - v * QPD_MAX_ORB;
-                    int sp = v == 0 ? B.rs : B.cs;
-                    int nvs = sp == 0 ? nv0 : nv1;
-                    if (i >= nvs) continue;
-                    int p = s_virt[sp][i];
-                    int par;
-                    double gv = s_F[sp][p];
-                    if (B.type == BT_SINGLE) {
-                        par = (s_cnt[sp][B.h1] + s_cnt[sp][p] - (B.h1 < p)) & 1;
-                        gv -= a.I.Jm[B.h1 * n + p] - a.I.Km[B.h1 * n + p];
-                    } else if (B.type == BT_SS) {
-                        par = (s_cnt[sp][p] - (B.h1 < p) - (B.h2 < p)) & 1;
-                        gv -= a.I.Jm[B.h1 * n + p] - a.I.Km[B.h1 * n + p];
-                        gv -= a.I.Jm[B.h2 * n + p] - a.I.Km[B.h2 * n + p];
-                    } else {
-                        int hs = sp == 0 ? B.h1 : B.h2;   // same-spin hole
-                        int ho = sp == 0 ? B.h2 : B.h1;   // opposite-spin hole
-                        par = (s_cnt[sp][p] - (hs < p)) & 1;
-                        gv -= a.I.Jm[hs * n + p] - a.I.Km[hs * n + p];
-                        gv -= a.I.Jm[ho * n + p];
-                    }
-                    s_sg[v][i] = (uint8_t)par;
-                    s_G[v][i] = gv;
-                }
-                if (BWD && B.type == BT_SINGLE)
-                    for (int x = tid; x < n; x += QPD_WG) s_dhrow[x] = 0.0;
-            }
-            if (want_sel && tid == 0) s_tau_key = bin_edge(__atomic_load_n(a.tau_bin, __ATOMIC_RELAXED));
-            wg_barrier();
-
-            const int rvs = B.rs, cvs = B.cs;
-            const uint8_t *rvirt = s_virt[rvs];
-            const uint8_t *cvirt = s_virt[cvs];
-
-            // particle orbitals (spin, orbital) of cell c
-            auto particles = [&](int64_t c, int &pa, int &sa, int &pb, int &sb, int &ra, int &rb) {
-                if (B.type == BT_SINGLE) {
-                    ra = (int)c; rb = -1;
-                    pa = rvirt[ra]; sa = rvs; pb = -1; sb = -1;
-                } else if (B.type == BT_SS) {
-                    int i1, i2;
-                    tri_decode(c, i1, i2);
-                    ra = i1; rb = i2;
-                    pa = rvirt[i1]; pb = rvirt[i2]; sa = rvs; sb = rvs;
+                int i1, i2 = -1;
+                if (b < nel) i1 = b;
+                else tri_decode(b - nel, i1, i2);
+                B.s1 = i1 < nup ? 0 : 1;
+                B.h1 = i1 < nup ? sOcc[i1] : sOcc[QPD_MAX_ORB + i1 - nup];
+                if (i2 < 0) {
+                    B.type = BT_SINGLE; B.s2 = -1; B.h2 = -1;
+                    B.rs = B.cs = B.s1; B.nr = B.nc = B.s1 == 0 ? nv0 : nv1;
+                    B.sH = 0; B.D0 = HII - sF[B.s1 * n + B.h1]; B.blk = nullptr;
                 } else {
-                    int r = (int)(c / B.nc);
-                    int col = (int)(c - (int64_t)r * B.nc);
-                    ra = r; rb = col;
-                    pa = rvirt[r]; sa = rvs; pb = cvirt[col]; sb = cvs;
-                }
-            };
-            // alpha bits of cell c
-            auto alpha_bits = [&](int pa, int sa, int pb, int sb, uint64_t *al) {
-#pragma unroll
-                for (int w = 0; w < 2 * NINT; ++w) al[w] = s_I[w];
-                al[B.s1 * NINT + (B.h1 >> 6)] ^= 1ull << (B.h1 & 63);
-                if (B.type != BT_SINGLE) al[B.s2 * NINT + (B.h2 >> 6)] ^= 1ull << (B.h2 & 63);
-                al[sa * NINT + (pa >> 6)] ^= 1ull << (pa & 63);
-                if (pb >= 0) al[sb * NINT + (pb >> 6)] ^= 1ull << (pb & 63);
-            };
-
-            // ---------------------------------------------- fine-filter round
-            // wave 0 fills s_fine with up to FCAP entries of the coarse list
-            // starting at s_fpos that pass m <= 2 for this hole set.
-            auto fine_round = [&](int64_t start) {
-                if (wave == 0) {
-                    int nf = 0;
-                    int64_t pos = start;
-                    while (pos < cend && nf < FCAP) {
-                        int64_t e = pos + lane;
-                        int keep = 0, m = 0;
-                        CoarseEnt ce;
-                        if (e < cend) {
-                            ce = a.cent[e];
-                            int dcount = 0, inH = 0;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                uint16_t d = ce.D[q];
-                                if (d == 0xFFFF) continue;
-                                dcount++;
-                                int ds = d >> 8, dp = d & 255;
-                                if (ds == B.s1 && dp == B.h1) inH++;
-                                else if (B.type != BT_SINGLE && ds == B.s2 && dp == B.h2) inH++;
-                            }
-                            m = dcount - inH;
-                            keep = m <= 2;
-                        }
-                        uint64_t mask = __ballot(keep);
-                        int before = __popcll(mask & ((1ull << lane) - 1ull));
-                        int tot = __popcll(mask);
-                        // take entries only while they fit
-                        int take = (nf + tot <= FCAP) ? tot : (FCAP - nf);
-                        // last lane index consumed
-                        int64_t consumed = 64;
-                        if (take < tot) {
-                            // find lane of the (take)-th kept entry: consume up to it
-                            uint64_t mm = mask;
-                            for (int q = 0; q < take; ++q) mm &= mm - 1;
-                            consumed = ctz64(mm);
-                        }
-                        if (keep && before < take) {
-                            FineEnt f;
-                            f.j = ce.j; f.m = m; f.earlier = ce.flags & 1;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) f.E[q] = ce.E[q];
-                            s_fine[nf + before] = f;
-#pragma unroll
-                            for (int k = 0; k < NS; ++k) s_fc[nf + before][k] = a.coefs[(int64_t)k * a.n_det + ce.j];
-                        }
-                        nf += take;
-                        pos += consumed < 64 ? consumed : 64;
-                        if (pos > cend) pos = cend;
+                    B.s2 = i2 < nup ? 0 : 1;
+                    B.h2 = i2 < nup ? sOcc[i2] : sOcc[QPD_MAX_ORB + i2 - nup];
+                    if (B.s2 == B.s1) {
+                        B.type = BT_SS;
+                        B.rs = B.cs = B.s1; B.nr = B.nc = B.s1 == 0 ? nv0 : nv1;
+                        B.sH = (sCnt[B.s1 * n + B.h1] + sCnt[B.s1 * n + B.h2] - 1) & 1;
+                        B.D0 = HII - sF[B.s1 * n + B.h1] - sF[B.s1 * n + B.h2] + a.I.JK[B.h1 * n + B.h2];
+                        B.blk = a.I.Y + qtris(B.h1, B.h2) * (int64_t)P2;
+                    } else {
+                        B.type = BT_OS;   // h1 up, h2 down
+                        if (B.h1 <= B.h2) { B.rs = 0; B.cs = 1; B.blk = a.I.X + qtri(B.h1, B.h2) * n2; }
+                        else { B.rs = 1; B.cs = 0; B.blk = a.I.X + qtri(B.h2, B.h1) * n2; }
+                        B.nr = B.rs == 0 ? nv0 : nv1; B.nc = B.cs == 0 ? nv0 : nv1;
+                        B.sH = (sCnt[B.h1] + sCnt[n + B.h2]) & 1;
+                        B.D0 = HII - sF[B.h1] - sF[n + B.h2] + a.I.Jm[B.h1 * n + B.h2];
                     }
-                    if (lane == 0) { s_nfine = nf; s_fpos = pos; }
                 }
-            };
+            }
+            const int hc0 = (B.s1 << 8) | B.h1;
+            const int hc1 = B.type == BT_SINGLE ? -1 : ((B.s2 << 8) | B.h2);
+            const uint8_t *rvirt = sVirt + B.rs * QPD_MAX_ORB;
+            const uint8_t *cvirt = sVirt + B.cs * QPD_MAX_ORB;
+            // same-spin and other-spin hole of the row spin
+            const int hrs = B.type == BT_OS ? (B.rs == 0 ? B.h1 : B.h2) : B.h1;
+            const int hro = B.type == BT_OS ? (B.rs == 0 ? B.h2 : B.h1) : (B.type == BT_SS ? B.h2 : -1);
 
-            // enumerate touched cells of fine entry f in [lo, hi) with all threads
-            // and call fn(c) for each
-            auto for_touched = [&](const FineEnt &f, int64_t lo, int64_t hi, auto &&fn) {
-                int er[4], ec[4], ner = 0, nec = 0;
+            // row vector: phase bit and diagonal offset per row-spin particle
+            for (int i = lane; i < B.nr; i += WAVE) {
+                const int p = rvirt[i];
+                int par = sCnt[B.rs * n + p] - (hrs < p);
+                double gv = sF[B.rs * n + p] - a.I.JK[hrs * n + p];
+                if (B.type == BT_SINGLE) par += sCnt[B.rs * n + B.h1];
+                else if (B.type == BT_SS) { par -= (hro < p); gv -= a.I.JK[hro * n + p]; }
+                else gv -= a.I.Jm[hro * n + p];
+                sRS[i] = (uint8_t)(par & 1);
+                sRG[i] = gv;
+            }
+
+            // ------------------------------------------------- fine filter
+            int nfine = 0;
+            for (int64_t base = cbeg; base < cend; base += WAVE) {
+                const int64_t e = base + lane;
+                bool keep = false;
+                CoarseEnt ce;
+                int m = 0;
+                if (e < cend) {
+                    ce = a.cent[e];
+                    int dc = 0, in = 0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    uint16_t e = f.E[q];
-                    if (e == 0xFFFF) continue;
-                    int es = e >> 8, ep = e & 255;
-                    int vi = s_vidx[es][ep];
-                    if (ep >= n || vi >= (es == 0 ? nv0 : nv1)) continue;   // not a particle of I
-                    if (es == rvs) er[ner++] = vi;
-                    else if (B.type == BT_OS && es == cvs) ec[nec++] = vi;
+                    for (int t = 0; t < 4; ++t) {
+                        const int d = ce.D[t];
+                        if (d == 0xFFFF) continue;
+                        dc++;
+                        in += (d == hc0) || (d == hc1);
+                    }
+                    m = dc - in;
+                    keep = m <= 2;
                 }
-                bool all = (f.m == 0) || (B.type == BT_SINGLE && f.m == 1);
-                if (all) {
-                    for (int64_t c = lo + tid; c < hi; c += QPD_WG) fn(c);
-                    return;
+                const uint64_t mask = __ballot(keep);
+                const int pos = nfine + __popcll(mask & ((1ull << lane) - 1ull));
+                if (keep && pos < FCAP) {
+                    FineE f;
+                    f.j = ce.j; f.m = (uint8_t)m; f.earlier = (uint8_t)(ce.flags & 1);
+                    int ner = 0, nec = 0;
+                    uint32_t er = 0xFFFFFFFFu, ec = 0xFFFFFFFFu;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int ecode = ce.E[t];
+                        if (ecode == 0xFFFF) continue;
+                        const int es = ecode >> 8, ep = ecode & 255;
+                        if (ep >= n) continue;
+                        const int vi = sVidx[es * n + ep];
+                        if (vi >= (es == 0 ? nv0 : nv1)) continue;
+                        if (es == B.rs) {
+                            er = (er & ~(255u << (8 * ner))) | ((uint32_t)vi << (8 * ner));
+                            ner++;
+                        } else if (B.type == BT_OS) {
+                            ec = (ec & ~(255u << (8 * nec))) | ((uint32_t)vi << (8 * nec));
+                            nec++;
+                        }
+                    }
+                    f.ner = (uint8_t)ner; f.nec = (uint8_t)nec; f.er = er; f.ec = ec;
+                    sFine[pos] = f;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) sFC[pos * NS + k] = a.coefs[(int64_t)k * a.n_det + ce.j];
                 }
-                if (f.m == 2) {
-                    // cells with P subset of E
-                    int64_t list[6];
-                    int nl = 0;
-                    if (B.type == BT_SINGLE) {
-                        for (int q = 0; q < ner; ++q) list[nl++] = er[q];
-                    } else if (B.type == BT_SS) {
-                        for (int q = 0; q < ner; ++q)
-                            for (int r = q + 1; r < ner; ++r) {
-                                int x = er[q] < er[r] ? er[q] : er[r], y = er[q] < er[r] ? er[r] : er[q];
-                                list[nl++] = (int64_t)y * (y - 1) / 2 + x;
+                nfine += __popcll(mask);
+            }
+            const bool fine_overflow = nfine > FCAP;
+            if (fine_overflow) nfine = FCAP;
+            __syncthreads();
+
+            // ----------- classify: m = 2 cells, column segments, inline entries
+            int nl2 = 0, ncs = 0, nil = 0;
+            bool slow = fine_overflow;
+            if (lane < 4) sRowBits[lane] = 0ull;
+            for (int f = 0; f < nfine; ++f) {
+                const FineE fe = sFine[f];
+                bool inl = false;
+                if (B.type == BT_SINGLE || fe.m == 0) inl = true;
+                else if (fe.m == 2) {
+                    if (B.type == BT_OS) {
+                        for (int x = 0; x < fe.ner; ++x)
+                            for (int y = 0; y < fe.nec; ++y) {
+                                if (nl2 < L2CAP && lane == 0)
+                                    sL2[nl2] = byte_at(fe.er, x) | (byte_at(fe.ec, y) << 8) | (f << 16) | ((uint32_t)fe.earlier << 24);
+                                nl2++;
                             }
                     } else {
-                        for (int q = 0; q < ner; ++q)
-                            for (int r = 0; r < nec; ++r) list[nl++] = (int64_t)er[q] * B.nc + ec[r];
+                        for (int x = 0; x < fe.ner; ++x)
+                            for (int y = x + 1; y < fe.ner; ++y) {
+                                const int i1 = byte_at(fe.er, x) < byte_at(fe.er, y) ? byte_at(fe.er, x) : byte_at(fe.er, y);
+                                const int i2 = byte_at(fe.er, x) < byte_at(fe.er, y) ? byte_at(fe.er, y) : byte_at(fe.er, x);
+                                if (nl2 < L2CAP && lane == 0)
+                                    sL2[nl2] = i1 | (i2 << 8) | (f << 16) | ((uint32_t)fe.earlier << 24);
+                                nl2++;
+                            }
                     }
-                    for (int q = tid; q < nl; q += QPD_WG)
-                        if (list[q] >= lo && list[q] < hi) fn(list[q]);
-                    return;
+                } else {   // m == 1: column part -> segments; row part -> inline
+                    const int nseg = B.type == BT_OS ? fe.nec : fe.ner;
+                    for (int x = 0; x < nseg; ++x) {
+                        const int col = B.type == BT_OS ? byte_at(fe.ec, x) : byte_at(fe.er, x);
+                        if (ncs < CSCAP && lane == 0) sCS[ncs] = f | (col << 8);
+                        ncs++;
+                    }
+                    inl = fe.ner > 0;
                 }
-                // m == 1
-                if (B.type == BT_OS) {
-                    int64_t nrow = (int64_t)ner * B.nc, tot = nrow + (int64_t)nec * B.nr;
-                    for (int64_t t = tid; t < tot; t += QPD_WG) {
-                        int64_t c;
-                        if (t < nrow) {
-                            int q = (int)(t / B.nc);
-                            c = (int64_t)er[q] * B.nc + (t - (int64_t)q * B.nc);
-                        } else {
-                            int64_t u = t - nrow;
-                            int q = (int)(u / B.nr);
-                            int r = (int)(u - (int64_t)q * B.nr);
-                            bool dup = false;
-                            for (int z = 0; z < ner; ++z) dup |= (er[z] == r);
-                            if (dup) continue;
-                            c = (int64_t)r * B.nc + ec[q];
+                if (inl) {
+                    if (nil < ICAP && lane == 0) sIL[nil] = (uint8_t)f;
+                    nil++;
+                }
+            }
+            if (nl2 > L2CAP || ncs > CSCAP || nil > ICAP) slow = true;
+            if (slow) {
+                // everything inline, touch rule evaluated per cell
+                nl2 = 0; ncs = 0;
+                nil = nfine;
+            }
+            __syncthreads();
+            if (!slow) {
+                // m = 2 cells: one lane each
+                if (lane < nl2) {
+                    const uint32_t e = sL2[lane];
+                    const int i1 = e & 255, i2 = (e >> 8) & 255, f = (e >> 16) & 255;
+                    double v = 0.0;
+                    if (!((e >> 24) & 1)) {
+                        int pa, sa, pb, sb;
+                        if (B.type == BT_OS) { pa = rvirt[i1]; sa = B.rs; pb = cvirt[i2]; sb = B.cs; }
+                        else { pa = rvirt[i1]; pb = rvirt[i2]; sa = sb = B.rs; }
+                        int deg;
+                        v = corr_element<NINT>(a.I, sI, hc0, hc1, pa, sa, pb, sb,
+                                               a.dets + (int64_t)sFine[f].j * 2 * NINT, &deg, nullptr);
+                        if (deg == 0) sL2[lane] = e | (1u << 24);   // alpha is internal
+                    }
+                    sL2H[lane] = v;
+                    const int br = B.type == BT_SS ? (i2 <= B.nr / 2 ? i2 : B.nr - i2) : i1;
+                    atomicOr((unsigned long long *)&sRowBits[br >> 6], 1ull << (br & 63));
+                }
+                // column segments: lanes over the rows of the segment
+                for (int s = 0; s < ncs; ++s) {
+                    const int f = sCS[s] & 255, col = sCS[s] >> 8;
+                    const FineE fe = sFine[f];
+                    if (fe.earlier) continue;
+                    for (int r = lane; r < B.nr; r += WAVE) {
+                        double v = 0.0;
+                        const bool use = B.type == BT_OS ? !has(fe.er, fe.ner, r) : (r > col && !has(fe.er, fe.ner, r));
+                        if (use) {
+                            int pa, sa, pb, sb;
+                            if (B.type == BT_OS) { pa = rvirt[r]; sa = B.rs; pb = cvirt[col]; sb = B.cs; }
+                            else { pa = rvirt[col]; pb = rvirt[r]; sa = sb = B.rs; }
+                            int deg;
+                            v = corr_element<NINT>(a.I, sI, hc0, hc1, pa, sa, pb, sb,
+                                                   a.dets + (int64_t)fe.j * 2 * NINT, &deg, nullptr);
                         }
-                        if (c >= lo && c < hi) fn(c);
-                    }
-                } else {  // BT_SS
-                    int V = B.nr;
-                    int64_t tot = (int64_t)ner * (V - 1);
-                    for (int64_t t = tid; t < tot; t += QPD_WG) {
-                        int q = (int)(t / (V - 1));
-                        int x = (int)(t - (int64_t)q * (V - 1));
-                        if (x >= er[q]) x++;
-                        bool dup = false;
-                        for (int z = 0; z < q; ++z) dup |= (er[z] == x);
-                        if (dup) continue;
-                        int i1 = x < er[q] ? x : er[q], i2 = x < er[q] ? er[q] : x;
-                        int64_t c = (int64_t)i2 * (i2 - 1) / 2 + i1;
-                        if (c >= lo && c < hi) fn(c);
+                        sCB[s * QPD_MAX_ORB + r] = v;
                     }
                 }
+            }
+            if (BWD) for (int x = lane; x < FCAP * NS; x += WAVE) sDCF[x] = 0.0;
+            __syncthreads();
+
+            const uint64_t tau_key = want_sel ? bin_edge(__atomic_load_n(a.tau_bin, __ATOMIC_RELAXED)) : 0ull;
+            const double tau_val = __longlong_as_double((long long)tau_key) * (1.0 - 1e-12);
+            bool appended = false;
+            double vbatch = 0.0;
+
+            // touch rule of an inline entry for the cell (i1, i2)
+            auto inline_touch = [&](const FineE &fe, int i1, int i2) -> bool {
+                if (B.type == BT_SINGLE) return fe.m <= 1 || has(fe.er, fe.ner, i1);
+                if (fe.m == 0) return true;
+                if (B.type == BT_OS) {
+                    const bool inR = has(fe.er, fe.ner, i1), inC = has(fe.ec, fe.nec, i2);
+                    if (fe.m == 1) return slow ? (inR || inC) : inR;
+                    return slow && inR && inC;
+                }
+                const bool in1 = has(fe.er, fe.ner, i1), in2 = has(fe.er, fe.ner, i2);
+                if (fe.m == 1) return slow ? (in1 || in2) : in2;
+                return slow && in1 && in2;
             };
 
-            // does this batch have any fine entry?
-            fine_round(cbeg);
-            wg_barrier();
-            const bool has_tile = BWD ? true : (s_nfine > 0);
-            const bool any_fine = s_nfine > 0;
-
-            for (int64_t lo = 0; lo < B.ncell; lo += SLAB) {
-                const int64_t hi = (lo + SLAB < B.ncell) ? lo + SLAB : B.ncell;
-                const int sn = (int)(hi - lo);
-                if (has_tile) {
-                    for (int x = tid; x < NS * SLAB; x += QPD_WG) s_tile[x] = 0.0;
-                    for (int x = tid; x < (SLAB + 31) / 32; x += QPD_WG) s_ban[x] = 0u;
-                    if (lo > 0 && any_fine) {  // refill the first fine round for this slab
-                        wg_barrier();
-                        fine_round(cbeg);
-                    }
-                    wg_barrier();
-                    if (any_fine) {
-                        for (;;) {
-                            const int nf = s_nfine;
-                            for (int fi = 0; fi < nf; ++fi) {
-                                const FineEnt f = s_fine[fi];
-                                uint64_t Jb[2 * NINT];
-#pragma unroll
-                                for (int w = 0; w < 2 * NINT; ++w) Jb[w] = a.dets[(int64_t)f.j * 2 * NINT + w];
-                                for_touched(f, lo, hi, [&](int64_t c) {
-                                    int loc = (int)(c - lo);
-                                    if (f.earlier) { atomicOr(&s_ban[loc >> 5], 1u << (loc & 31)); return; }
-                                    int pa, sa, pb, sb, ra, rb;
-                                    particles(c, pa, sa, pb, sb, ra, rb);
-                                    uint64_t al[2 * NINT];
-                                    alpha_bits(pa, sa, pb, sb, al);
-                                    int deg;
-                                    double v = sc_offdiag<NINT>(a.I, al, Jb, &deg, nullptr);
-                                    if (deg == 0) { atomicOr(&s_ban[loc >> 5], 1u << (loc & 31)); return; }
-                                    conn++;
-#pragma unroll
-                                    for (int k = 0; k < NS; ++k) s_tile[k * SLAB + loc] += s_fc[fi][k] * v;
-                                });
-                                wg_barrier();
-                            }
-                            if (s_fpos >= cend) break;
-                            wg_barrier();
-                            fine_round(s_fpos);
-                            wg_barrier();
-                        }
-                    }
+            // --------------------------------------------------- dense pass
+            const int nrow = B.type == BT_OS ? B.nr : (B.type == BT_SS ? B.nr / 2 : 1);
+            const int ncolv = B.type == BT_OS ? B.nc : B.nr;
+            for (int c0 = 0; c0 < ncolv; c0 += WAVE) {
+                const int l = c0 + lane;
+                const bool lane_ok = l < ncolv;
+                int pcol = 0, csg = 0;
+                double cbase = 0.0, colacc = 0.0;
+                if (B.type == BT_OS && lane_ok) {
+                    pcol = cvirt[l];
+                    const int hcs = B.cs == 0 ? B.h1 : B.h2, hco = B.cs == 0 ? B.h2 : B.h1;
+                    csg = (B.sH + sCnt[B.cs * n + pcol] - (hcs < pcol)) & 1;
+                    cbase = B.D0 + sF[B.cs * n + pcol] - a.I.JK[hcs * n + pcol] - a.I.Jm[hco * n + pcol];
                 }
-
-                // ------------------------------------------------ cell pass
-                const int iters = (sn + QPD_WG - 1) / QPD_WG;
-                for (int it = 0; it < iters; ++it) {
-                    const int loc = it * QPD_WG + tid;
-                    const bool active = loc < sn;
-                    const int64_t c = lo + loc;
+                for (int rr = 0; rr < nrow; ++rr) {
+                    const int r = B.type == BT_SS ? rr + 1 : rr;
+                    bool act = lane_ok;
+                    int i1, i2;
+                    int pa = 0, sa = B.rs, pb = -1, sb = B.cs;
                     double Hval = 0.0, D = 0.0;
-                    int pa = -1, pb = -1, sa = 0, sb = 0, ra = 0, rb = 0;
-                    bool banned = false;
-                    if (active) {
-                        particles(c, pa, sa, pb, sb, ra, rb);
-                        if (B.type == BT_SINGLE) {
-                            double f = fock_offdiag<NINT>(a.I, s_I, B.s1, B.h1, pa);
-                            Hval = s_sg[0][ra] ? -f : f;
-                            D = B.D0 + s_G[0][ra];
-                        } else if (B.type == BT_SS) {
-                            double x = B.blk[qtris(pa, pb)];
-                            Hval = (B.sH ^ s_sg[0][ra] ^ s_sg[0][rb]) ? -x : x;
-                            D = B.D0 + s_G[0][ra] + s_G[0][rb] + a.I.Jm[pa * n + pb] - a.I.Km[pa * n + pb];
-                        } else {
-                            double x = B.blk[(int64_t)pa * n + pb];
-                            Hval = (B.sH ^ s_sg[0][ra] ^ s_sg[1][rb]) ? -x : x;
-                            D = B.D0 + s_G[0][ra] + s_G[1][rb] + a.I.Jm[pa * n + pb];
+                    if (B.type == BT_OS) {
+                        i1 = r; i2 = l;
+                        pa = rvirt[r]; pb = pcol;
+                        if (act) {
+                            const double x = B.blk[(int64_t)pa * n + pb];
+                            const double jj = a.I.Jm[(int64_t)pa * n + pb];
+                            Hval = (csg ^ sRS[r]) ? -x : x;
+                            D = cbase + sRG[r] + jj;
                         }
-                        if (has_tile) banned = (s_ban[loc >> 5] >> (loc & 31)) & 1u;
+                    } else if (B.type == BT_SS) {
+                        const bool partA = l < r;
+                        i1 = partA ? l : l - r;
+                        i2 = partA ? r : B.nr - r;
+                        act = act && (partA || (B.nr - r > r));
+                        pa = rvirt[act ? i1 : 0]; pb = rvirt[act ? i2 : 0]; sb = B.rs;
+                        if (act) {
+                            const double x = B.blk[qtris(pa, pb)];
+                            const double jk = a.I.JK[(int64_t)pb * n + pa];
+                            Hval = (B.sH ^ sRS[i1] ^ sRS[i2]) ? -x : x;
+                            D = B.D0 + sRG[i1] + sRG[i2] + jk;
+                        }
+                    } else {
+                        i1 = l; i2 = 0;
+                        pa = rvirt[act ? l : 0];
+                        if (act) {
+                            const double f = fock_offdiag<NINT>(a.I, Ib, B.s1, B.h1, pa);
+                            Hval = sRS[l] ? -f : f;
+                            D = B.D0 + sRG[l];
+                        }
                     }
-                    const bool live = active && !banned;
-                    double ek[NS];
-                    double tsel = 0.0;
-                    double vsum = 0.0;
+                    double A[NS];
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hval;
+                    bool banned = false;
+                    int ncorr = 0;
+
+                    // ---------------------------------------- corrections
+                    const bool rowhit = nl2 > 0 && ((sRowBits[r >> 6] >> (r & 63)) & 1ull);
+                    if (rowhit) {
+                        for (int t = 0; t < nl2; ++t) {
+                            const uint32_t e = sL2[t];
+                            if (act && (int)(e & 255) == i1 && (int)((e >> 8) & 255) == i2) {
+                                if ((e >> 24) & 1) banned = true;
+                                else {
+                                    const int f = (e >> 16) & 255;
+                                    ncorr++;
+#pragma unroll
+                                    for (int k = 0; k < NS; ++k) A[k] += sFC[f * NS + k] * sL2H[t];
+                                }
+                            }
+                        }
+                    }
+                    for (int s = 0; s < ncs; ++s) {
+                        const int f = sCS[s] & 255, col = sCS[s] >> 8;
+                        const FineE fe = sFine[f];
+                        const int rowi = B.type == BT_OS ? i1 : i2;
+                        const bool hit = act && (B.type == BT_OS ? i2 : i1) == col && !has(fe.er, fe.ner, rowi);
+                        if (hit) {
+                            if (fe.earlier) banned = true;
+                            else {
+                                ncorr++;
+                                const double v = sCB[s * QPD_MAX_ORB + rowi];
+#pragma unroll
+                                for (int k = 0; k < NS; ++k) A[k] += sFC[f * NS + k] * v;
+                            }
+                        }
+                    }
+                    for (int t = 0; t < nil; ++t) {
+                        const int f = slow ? t : sIL[t];
+                        const FineE fe = sFine[f];
+                        const bool touch = act && inline_touch(fe, i1, i2);
+                        if (__ballot(touch) == 0ull) continue;
+                        if (touch) {
+                            if (fe.earlier) banned = true;
+                            else {
+                                int deg;
+                                const double v = corr_element<NINT>(a.I, sI, hc0, hc1, pa, sa, pb, sb,
+                                                                    a.dets + (int64_t)fe.j * 2 * NINT, &deg, nullptr);
+                                if (deg == 0) banned = true;
+                                else {
+                                    ncorr++;
+#pragma unroll
+                                    for (int k = 0; k < NS; ++k) A[k] += sFC[f * NS + k] * v;
+                                }
+                            }
+                        }
+                    }
+                    if (fine_overflow) {
+                        // coarse entries beyond the first FCAP fine ones
+                        int seen = 0;
+                        for (int64_t e = cbeg; e < cend; ++e) {
+                            const CoarseEnt ce = a.cent[e];
+                            int dc = 0, in = 0;
+                            for (int t = 0; t < 4; ++t) {
+                                const int d = ce.D[t];
+                                if (d == 0xFFFF) continue;
+                                dc++;
+                                in += (d == hc0) || (d == hc1);
+                            }
+                            if (dc - in > 2) continue;
+                            if (seen++ < FCAP) continue;
+                            if (!act) continue;
+                            int deg;
+                            const double v = corr_element<NINT>(a.I, sI, hc0, hc1, pa, sa, pb, sb,
+                                                                a.dets + (int64_t)ce.j * 2 * NINT, &deg, nullptr);
+                            if (deg > 2) continue;
+                            if ((ce.flags & 1) || deg == 0) { banned = true; continue; }
+                            ncorr++;
+#pragma unroll
+                            for (int k = 0; k < NS; ++k) A[k] += a.coefs[(int64_t)k * a.n_det + ce.j] * v;
+                        }
+                    }
+
+                    // ------------------------------------------------ finalise
+                    const bool live = act && !banned;
+                    double ek[NS], rk[NS];
+                    double tsel = 0.0, vsum = 0.0;
 #pragma unroll
                     for (int k = 0; k < NS; ++k) {
-                        double A = cI[k] * Hval + (has_tile && active ? s_tile[k * SLAB + loc] : 0.0);
-                        double delta = E0[k] - D;
-                        double r = 1.0 / delta;
-                        double e = (A * A) * r;
-                        ek[k] = e;
+                        const double delta = E0[k] - D;
+                        const double rc = fast_rcp(delta);
+                        const double e = (A[k] * A[k]) * rc;
+                        ek[k] = e; rk[k] = rc;
                         if (live) {
                             esum[k] += e;
-                            ssum[k] += e * r;
-                            double ad = fabs(delta);
-                            mind = ad < mind ? ad : mind;
-                            tsel += e * a.inv_maxc2[k];
-                            if (BWD) {
-                                double w = 2.0 * gup[k] * A * r;
-                                dcI[k] += w * Hval;
-                                vsum += gup[k] * e * r;
-                                s_tile[k * SLAB + loc] = w;    // w_k for the sparse-J pass
-                            }
-                        }
-                    }
-                    if (BWD && active) {
-                        s_vt[loc] = live ? vsum : 0.0;
-                        if (!live) {
-#pragma unroll
-                            for (int k = 0; k < NS; ++k) s_tile[k * SLAB + loc] = 0.0;
-                        }
-                        if (B.type == BT_SINGLE && live) {
-                            double gsum = 0.0;
-#pragma unroll
-                            for (int k = 0; k < NS; ++k) gsum += s_tile[k * SLAB + loc] * cI[k];
-                            // d<I|H|alpha>/dh_{h p} = phase
-                            s_dhrow[pa] += 0.5 * (s_sg[0][ra] ? -gsum : gsum);
+                            ssum[k] = fma(e, rc, ssum[k]);
+                            mind = fmin(mind, fabs(delta));
+                            tsel = fma(e, a.inv_maxc2[k], tsel);
+                            if (BWD) vsum += gup[k] * e * rc;
                         }
                     }
                     if (live) {
                         cnt++;
+                        conn += ncorr;
                         if (want_fp) {
                             uint64_t al[2 * NINT];
-                            alpha_bits(pa, sa, pb, sb, al);
+#pragma unroll
+                            for (int w = 0; w < 2 * NINT; ++w) al[w] = Ib[w];
+                            al[(hc0 >> 8) * NINT + ((hc0 & 255) >> 6)] ^= 1ull << (hc0 & 63);
+                            if (hc1 >= 0) al[(hc1 >> 8) * NINT + ((hc1 & 255) >> 6)] ^= 1ull << (hc1 & 63);
+                            al[sa * NINT + (pa >> 6)] ^= 1ull << (pa & 63);
+                            if (pb >= 0) al[sb * NINT + (pb >> 6)] ^= 1ull << (pb & 63);
                             fpsum += det_fold<NINT>(al);
                         }
                     }
                     if (want_sel) {
+                        bool cand = live && fabs(tsel) >= tau_val;
                         uint64_t key = 0;
-                        bool cand = false;
-                        if (live && fabs(tsel) >= __longlong_as_double(s_tau_key) * (1.0 - 1e-12)) {
+                        if (cand) {
                             double t = 0.0;
 #pragma unroll
                             for (int k = 0; k < NS; ++k) t += ek[k] / a.maxc2[k];
                             key = (uint64_t)__double_as_longlong(fabs(t));
-                            cand = key >= s_tau_key;
+                            cand = key >= tau_key;
                         }
-                        uint64_t mask = __ballot(cand);
+                        const uint64_t mask = __ballot(cand);
                         if (mask) {
+                            const int leader = ctz64(mask);
                             unsigned long long base = 0;
-                            int tot = __popcll(mask);
-                            if (lane == ctz64(mask)) base = atomicAdd(a.cand_count, (unsigned long long)tot);
-                            base = __shfl(base, ctz64(mask));
+                            if (lane == leader) base = atomicAdd(a.cand_count, (unsigned long long)__popcll(mask));
+                            base = __shfl(base, leader);
+                            appended = true;
                             if (cand) {
-                                unsigned long long slotc = base + __popcll(mask & ((1ull << lane) - 1ull));
+                                const unsigned long long sc = base + __popcll(mask & ((1ull << lane) - 1ull));
                                 atomicAdd(&a.hist[key_bin(key)], 1u);
-                                if ((int64_t)slotc < a.cand_cap) {
+                                if ((int64_t)sc < a.cand_cap) {
                                     Cand cd;
                                     cd.key = key;
-                                    int up = B.type == BT_OS ? (sa == 0 ? pa : pb) : pa;
-                                    int dn = B.type == BT_OS ? (sa == 0 ? pb : pa) : pb;
-                                    cd.code = pack_code(B.type, B.s1, B.h1, B.h2 < 0 ? 0 : B.h2, up, dn < 0 ? 0 : dn);
+                                    const int up = (B.type == BT_OS) ? (sa == 0 ? pa : pb) : pa;
+                                    const int dn = (B.type == BT_OS) ? (sa == 0 ? pb : pa) : (pb < 0 ? 0 : pb);
+                                    cd.code = pack_code(B.type, B.s1, B.h1, B.h2 < 0 ? 0 : B.h2, up, dn);
                                     cd.g = (uint32_t)g;
                                     cd.pad = 0;
 #pragma unroll
                                     for (int k = 0; k < QPD_MAX_STATES; ++k) cd.e[k] = k < NS ? ek[k] : 0.0;
-                                    a.cand[slotc] = cd;
+                                    a.cand[sc] = cd;
                                 } else {
                                     atomicOr(a.overflow, 1ull);
                                 }
                             }
-                            if (lane == ctz64(mask)) s_appended = 1;
                         }
                     }
-                }
 
-                if (BWD) {
-                    wg_barrier();
-                    // ------------------------------------ dh diagonal: particles
-                    // sum of v over the slab's cells per particle orbital; one
-                    // thread per row / column, so no two threads share an address
-                    if (B.type == BT_SINGLE) {
-                        for (int loc = tid; loc < sn; loc += QPD_WG) {
-                            s_dhd[rvirt[lo + loc]] += s_vt[loc];
-                            vtot += s_vt[loc];
-                        }
-                        wg_barrier();
-                    } else if (B.type == BT_OS) {
-                        int r0 = (int)(lo / B.nc), r1 = (int)((hi - 1) / B.nc);
-                        for (int r = r0 + tid; r <= r1; r += QPD_WG) {
-                            double sr = 0.0;
-                            for (int col = 0; col < B.nc; ++col) {
-                                int64_t c = (int64_t)r * B.nc + col;
-                                if (c >= lo && c < hi) sr += s_vt[c - lo];
-                            }
-                            s_dhd[rvirt[r]] += sr;
-                            vtot += sr;
-                        }
-                        wg_barrier();
-                        for (int col = tid; col < B.nc; col += QPD_WG) {
-                            double sc = 0.0;
-                            for (int r = r0; r <= r1; ++r) {
-                                int64_t c = (int64_t)r * B.nc + col;
-                                if (c >= lo && c < hi) sc += s_vt[c - lo];
-                            }
-                            s_dhd[cvirt[col]] += sc;
-                        }
-                        wg_barrier();
-                    } else {
-                        int j0, j1, k0, k1;
-                        tri_decode(lo, j0, k0);
-                        tri_decode(hi - 1, j1, k1);
-                        // rows i2 in [k0, k1]: cells (i1 < i2)
-                        for (int i2 = k0 + tid; i2 <= k1; i2 += QPD_WG) {
-                            double sr = 0.0;
-                            for (int i1 = 0; i1 < i2; ++i1) {
-                                int64_t c = (int64_t)i2 * (i2 - 1) / 2 + i1;
-                                if (c >= lo && c < hi) sr += s_vt[c - lo];
-                            }
-                            s_dhd[rvirt[i2]] += sr;
-                            vtot += sr;
-                        }
-                        wg_barrier();
-                        for (int i1 = tid; i1 < B.nr; i1 += QPD_WG) {
-                            double sc = 0.0;
-                            for (int i2 = (i1 + 1 > k0 ? i1 + 1 : k0); i2 <= k1; ++i2) {
-                                int64_t c = (int64_t)i2 * (i2 - 1) / 2 + i1;
-                                if (c >= lo && c < hi) sc += s_vt[c - lo];
-                            }
-                            s_dhd[rvirt[i1]] += sc;
-                        }
-                        wg_barrier();
-                    }
-                    // holes: n_p(I - H) = n_p(I) - [p in H]; subtract the slab total
-                    {
-                        double vs = 0.0;
-                        for (int loc = tid; loc < sn; loc += QPD_WG) vs += s_vt[loc];
-                        for (int off = 32; off > 0; off >>= 1) vs += __shfl_xor(vs, off);
-                        if (lane == 0) s_red[wave][0] = vs;
-                        wg_barrier();
-                        if (tid == 0) {
-                            double t = 0.0;
-                            for (int q = 0; q < NWAVE; ++q) t += s_red[q][0];
-                            s_dhd[B.h1] -= t;
-                            if (B.type != BT_SINGLE) s_dhd[B.h2] -= t;
-                        }
-                        wg_barrier();
-                    }
-                    // ------------------------------- sparse J: dc_J and dh
-                    if (any_fine) {
-                        fine_round(cbeg);
-                        wg_barrier();
-                        for (;;) {
-                            const int nf = s_nfine;
-                            for (int fi = 0; fi < nf; ++fi) {
-                                const FineEnt f = s_fine[fi];
-                                if (f.earlier) continue;
-                                uint64_t Jb[2 * NINT];
+                    // ------------------------------------------------ adjoint
+                    if (BWD) {
+                        double w[NS];
 #pragma unroll
-                                for (int w = 0; w < 2 * NINT; ++w) Jb[w] = a.dets[(int64_t)f.j * 2 * NINT + w];
-                                double acc[NS];
+                        for (int k = 0; k < NS; ++k) {
+                            w[k] = live ? 2.0 * gup[k] * A[k] * rk[k] : 0.0;
+                            dcI[k] += w[k] * Hval;
+                        }
+                        const double v = live ? vsum : 0.0;
+                        vbatch += v;
+                        // diagonal of dE/dh from the particles' occupations
+                        if (B.type == BT_OS) {
+                            const double rsum = wave_sum(v);
+                            if (lane == 0 && rsum != 0.0) sDHD[rvirt[r]] += rsum;
+                            colacc += v;
+                        } else if (B.type == BT_SS) {
+                            // part A shares i2 = r, part B shares i2 = V - r
+                            const bool partA = l < r;
+                            const double sA = wave_sum(partA ? v : 0.0), sB = wave_sum(partA ? 0.0 : v);
+                            if (lane == 0) {
+                                if (sA != 0.0) sDHD[rvirt[r]] += sA;
+                                if (sB != 0.0 && B.nr - r > r) sDHD[rvirt[B.nr - r]] += sB;
+                            }
+                            if (v != 0.0) atomicAdd(&sDHD[pa], v);
+                        } else if (live) {
+                            atomicAdd(&sDHD[pa], v);
+                            // single excitation of I: d<I|H|alpha>/dh_{h p} = phase
+                            double gs = 0.0;
 #pragma unroll
-                                for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-                                for_touched(f, lo, hi, [&](int64_t c) {
-                                    int loc = (int)(c - lo);
-                                    if ((s_ban[loc >> 5] >> (loc & 31)) & 1u) return;
-                                    int pa, sa, pb, sb, ra, rb;
-                                    particles(c, pa, sa, pb, sb, ra, rb);
-                                    uint64_t al[2 * NINT];
-                                    alpha_bits(pa, sa, pb, sb, al);
-                                    int deg, sgl[4];
-                                    double v = sc_offdiag<NINT>(a.I, al, Jb, &deg, sgl);
-                                    if (deg == 0) return;
-                                    double gsum = 0.0;
+                            for (int k = 0; k < NS; ++k) gs += w[k] * cI[k];
+                            if (a.dh && gs != 0.0) {
+                                const double gg = 0.5 * (sRS[l] ? -gs : gs);
+                                atomicAdd(&a.dh[(int64_t)B.h1 * n + pa], gg);
+                                atomicAdd(&a.dh[(int64_t)pa * n + B.h1], gg);
+                            }
+                        }
+                        // corrections: dE/dc_J += w <J|H|alpha>; single
+                        // excitations J -> alpha also feed dE/dh
+                        if (rowhit && live) {
+                            for (int t = 0; t < nl2; ++t) {
+                                const uint32_t e = sL2[t];
+                                if ((int)(e & 255) == i1 && (int)((e >> 8) & 255) == i2 && !((e >> 24) & 1)) {
+                                    const int f = (e >> 16) & 255;
 #pragma unroll
-                                    for (int k = 0; k < NS; ++k) {
-                                        double w = s_tile[k * SLAB + loc];
-                                        acc[k] += w * v;
-                                        gsum += w * s_fc[fi][k];
-                                    }
-                                    if (deg == 1 && a.dh) {
-                                        double gg = 0.5 * gsum * sgl[3];
-                                        atomicAdd(&a.dh[(int64_t)sgl[0] * n + sgl[1]], gg);
-                                        atomicAdd(&a.dh[(int64_t)sgl[1] * n + sgl[0]], gg);
-                                    }
-                                });
-#pragma unroll
-                                for (int k = 0; k < NS; ++k) {
-                                    double v = acc[k];
-                                    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-                                    if (lane == 0 && v != 0.0 && a.dc) atomicAdd(&a.dc[(int64_t)k * a.n_det + f.j], v);
+                                    for (int k = 0; k < NS; ++k) atomicAdd(&sDCF[f * NS + k], w[k] * sL2H[t]);
                                 }
                             }
-                            if (s_fpos >= cend) break;
-                            wg_barrier();
-                            fine_round(s_fpos);
-                            wg_barrier();
                         }
-                    }
-                    wg_barrier();
-                } else if (has_tile) {
-                    wg_barrier();
-                }
-            }  // slab
-
-            if (BWD && B.type == BT_SINGLE) {
-                wg_barrier();
-                if (a.dh)
-                    for (int x = tid; x < n; x += QPD_WG) {
-                        double v = s_dhrow[x];
-                        if (v != 0.0) {
-                            atomicAdd(&a.dh[(int64_t)B.h1 * n + x], v);
-                            atomicAdd(&a.dh[(int64_t)x * n + B.h1], v);
-                        }
-                    }
-            }
-            // raise the global selection threshold from the candidate histogram
-            if (want_sel) {
-                wg_barrier();
-                if (s_appended && wave == 0) {
-                    uint32_t loc[QP_HIST_BINS / 64];
-                    uint64_t tot = 0;
+                        for (int s = 0; s < ncs; ++s) {
+                            const int f = sCS[s] & 255, col = sCS[s] >> 8;
+                            const FineE fe = sFine[f];
+                            if (fe.earlier) continue;
+                            const int rowi = B.type == BT_OS ? i1 : i2;
+                            const bool hit = live && (B.type == BT_OS ? i2 : i1) == col && !has(fe.er, fe.ner, rowi);
+                            if (hit) {
+                                const double hv = sCB[s * QPD_MAX_ORB + rowi];
 #pragma unroll
-                    for (int q = 0; q < QP_HIST_BINS / 64; ++q) {
-                        loc[q] = __atomic_load_n(&a.hist[lane * (QP_HIST_BINS / 64) + q], __ATOMIC_RELAXED);
-                        tot += loc[q];
+                                for (int k = 0; k < NS; ++k) atomicAdd(&sDCF[f * NS + k], w[k] * hv);
+                            }
+                        }
+                        for (int t = 0; t < nil; ++t) {
+                            const int f = slow ? t : sIL[t];
+                            const FineE fe = sFine[f];
+                            if (fe.earlier) continue;
+                            const bool touch = live && inline_touch(fe, i1, i2);
+                            if (__ballot(touch) == 0ull) continue;
+                            double hv = 0.0;
+                            int deg = 0, sgl[4] = {-1, -1, 0, 0};
+                            if (touch)
+                                hv = corr_element<NINT>(a.I, sI, hc0, hc1, pa, sa, pb, sb,
+                                                        a.dets + (int64_t)fe.j * 2 * NINT, &deg, sgl);
+                            const bool ok = touch && deg >= 1 && deg <= 2;
+#pragma unroll
+                            for (int k = 0; k < NS; ++k) {
+                                const double s_ = wave_sum(ok ? w[k] * hv : 0.0);
+                                if (lane == 0 && s_ != 0.0) sDCF[f * NS + k] += s_;
+                            }
+                            if (ok && deg == 1 && a.dh) {
+                                double gs = 0.0;
+#pragma unroll
+                                for (int k = 0; k < NS; ++k) gs += w[k] * sFC[f * NS + k];
+                                const double gg = 0.5 * gs * sgl[3];
+                                atomicAdd(&a.dh[(int64_t)sgl[0] * n + sgl[1]], gg);
+                                atomicAdd(&a.dh[(int64_t)sgl[1] * n + sgl[0]], gg);
+                            }
+                        }
+                        if (fine_overflow && live) {
+                            int seen = 0;
+                            for (int64_t e = cbeg; e < cend; ++e) {
+                                const CoarseEnt ce = a.cent[e];
+                                int dc = 0, in = 0;
+                                for (int t = 0; t < 4; ++t) {
+                                    const int d = ce.D[t];
+                                    if (d == 0xFFFF) continue;
+                                    dc++;
+                                    in += (d == hc0) || (d == hc1);
+                                }
+                                if (dc - in > 2) continue;
+                                if (seen++ < FCAP) continue;
+                                if (ce.flags & 1) continue;
+                                int deg, sgl[4];
+                                const double hv = corr_element<NINT>(a.I, sI, hc0, hc1, pa, sa, pb, sb,
+                                                                     a.dets + (int64_t)ce.j * 2 * NINT, &deg, sgl);
+                                if (deg < 1 || deg > 2) continue;
+                                double gs = 0.0;
+#pragma unroll
+                                for (int k = 0; k < NS; ++k) {
+                                    const double cj = a.coefs[(int64_t)k * a.n_det + ce.j];
+                                    if (a.dc) atomicAdd(&a.dc[(int64_t)k * a.n_det + ce.j], w[k] * hv);
+                                    gs += w[k] * cj;
+                                }
+                                if (deg == 1 && a.dh) {
+                                    const double gg = 0.5 * gs * sgl[3];
+                                    atomicAdd(&a.dh[(int64_t)sgl[0] * n + sgl[1]], gg);
+                                    atomicAdd(&a.dh[(int64_t)sgl[1] * n + sgl[0]], gg);
+                                }
+                            }
+                        }
                     }
-                    // sum over lanes above this one
-                    uint64_t above = 0;
-                    for (int q = 1; q < 64; ++q) {
-                        uint64_t v = __shfl(tot, (lane + q) & 63);
-                        if (lane + q < 64) above += v;
-                    }
-                    int best = -1;
-                    uint64_t cum = above;
-                    for (int q = QP_HIST_BINS / 64 - 1; q >= 0; --q) {
-                        cum += loc[q];
-                        if (cum >= (uint64_t)a.n_select) { best = lane * (QP_HIST_BINS / 64) + q; break; }
-                    }
-                    for (int off = 32; off > 0; off >>= 1) {
-                        int o = __shfl_xor(best, off);
-                        best = o > best ? o : best;
-                    }
-                    if (lane == 0 && best > 0) atomicMax(a.tau_bin, best);
+                }  // rows
+                if (BWD && B.type == BT_OS && lane_ok && colacc != 0.0) atomicAdd(&sDHD[pcol], colacc);
+            }  // column chunks
+
+            if (want_sel && __ballot(appended)) {
+                // raise the global threshold from the candidate histogram: the
+                // highest bin b with at least n_select candidates at or above b
+                constexpr int PER = QP_HIST_BINS / WAVE;
+                uint32_t loc[PER];
+                uint64_t tot = 0;
+#pragma unroll
+                for (int t = 0; t < PER; ++t) {
+                    loc[t] = __atomic_load_n(&a.hist[lane * PER + t], __ATOMIC_RELAXED);
+                    tot += loc[t];
                 }
-                if (tid == 0) s_appended = 0;
+                uint64_t incl = tot;   // sum over lanes >= this lane
+                for (int off = 1; off < WAVE; off <<= 1) {
+                    const uint64_t v = __shfl_down(incl, off);
+                    if (lane + off < WAVE) incl += v;
+                }
+                uint64_t cum = incl - tot;
+                int best = -1;
+                for (int t = PER - 1; t >= 0; --t) {
+                    cum += loc[t];
+                    if (cum >= (uint64_t)a.n_select) { best = lane * PER + t; break; }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const int o = __shfl_xor(best, off);
+                    best = o > best ? o : best;
+                }
+                if (lane == 0 && best > 0) atomicMax(a.tau_bin, best);
             }
-            wg_barrier();
+            if (BWD) {
+                // holes: n_p(I - H) = n_p(I) - [p in H]
+                const double vb = wave_sum(vbatch);
+                __syncthreads();
+                if (lane == 0) {
+                    sDHD[B.h1] -= vb;
+                    if (B.type != BT_SINGLE) sDHD[B.h2] -= vb;
+                }
+                vtot += vbatch;
+                __syncthreads();
+                for (int x = lane; x < nfine * NS; x += WAVE) {
+                    const double v = sDCF[x];
+                    if (v != 0.0 && a.dc) atomicAdd(&a.dc[(int64_t)(x % NS) * a.n_det + sFine[x / NS].j], v);
+                }
+            }
+            __syncthreads();
         }  // batch
 
-        // ------------------------------------------------ item reduction
-        {
-            double vals[2 * NS + 1];
+        // ------------------------------------------------- item reduction
 #pragma unroll
-            for (int k = 0; k < NS; ++k) { vals[k] = esum[k]; vals[NS + k] = BWD ? dcI[k] : ssum[k]; }
-            vals[2 * NS] = mind;
-            double sS[NS];
+        for (int k = 0; k < NS; ++k) {
+            esum[k] = wave_sum(esum[k]);
+            ssum[k] = wave_sum(ssum[k]);
+            if (BWD) dcI[k] = wave_sum(dcI[k]);
+        }
+        uint64_t cc = cnt, ff = fpsum, cn = conn;
+        for (int off = 32; off > 0; off >>= 1) {
+            cc += __shfl_xor(cc, off);
+            ff += __shfl_xor(ff, off);
+            cn += __shfl_xor(cn, off);
+            mind = fmin(mind, __shfl_xor(mind, off));
+        }
+        vtot = wave_sum(vtot);
+        if (lane == 0) {
 #pragma unroll
-            for (int k = 0; k < NS; ++k) sS[k] = ssum[k];
-#pragma unroll
-            for (int q = 0; q < 2 * NS; ++q)
-                for (int off = 32; off > 0; off >>= 1) vals[q] += __shfl_xor(vals[q], off);
-            for (int off = 32; off > 0; off >>= 1) {
-                double o = __shfl_xor(vals[2 * NS], off);
-                vals[2 * NS] = o < vals[2 * NS] ? o : vals[2 * NS];
+            for (int k = 0; k < NS; ++k) {
+                a.eps_item[slot * NS + k] = esum[k];
+                a.S_item[slot * NS + k] = ssum[k];
+                if (BWD) a.dc_item[slot * NS + k] = dcI[k];
             }
-            uint64_t cc = cnt, ff = fpsum, cn = conn;
-            for (int off = 32; off > 0; off >>= 1) {
-                cc += __shfl_xor(cc, off);
-                ff += __shfl_xor(ff, off);
-                cn += __shfl_xor(cn, off);
-            }
-            double vt = vtot;
-            for (int off = 32; off > 0; off >>= 1) vt += __shfl_xor(vt, off);
-            if (BWD) {
-#pragma unroll
-                for (int k = 0; k < NS; ++k)
-                    for (int off = 32; off > 0; off >>= 1) sS[k] += __shfl_xor(sS[k], off);
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int q = 0; q < 2 * NS + 1; ++q) s_red[wave][q] = vals[q];
-                s_red[wave][2 * NS + 1] = vt;
-                s_redu[wave][0] = cc; s_redu[wave][1] = ff; s_redu[wave][2] = cn;
-            }
-            wg_barrier();
-            if (tid == 0) {
-                double out[2 * NS + 2];
-#pragma unroll
-                for (int q = 0; q < 2 * NS + 2; ++q) out[q] = s_red[0][q];
-                uint64_t oc = s_redu[0][0], of = s_redu[0][1], on = s_redu[0][2];
-                for (int w = 1; w < NWAVE; ++w) {
-#pragma unroll
-                    for (int q = 0; q < 2 * NS; ++q) out[q] += s_red[w][q];
-                    out[2 * NS] = s_red[w][2 * NS] < out[2 * NS] ? s_red[w][2 * NS] : out[2 * NS];
-                    out[2 * NS + 1] += s_red[w][2 * NS + 1];
-                    oc += s_redu[w][0]; of += s_redu[w][1]; on += s_redu[w][2];
-                }
-#pragma unroll
-                for (int k = 0; k < NS; ++k) {
-                    a.eps_item[slot * NS + k] = out[k];
-                    if (BWD) a.dc_item[slot * NS + k] = out[NS + k];
-                    else a.S_item[slot * NS + k] = out[NS + k];
-                }
-                a.cnt_item[slot] = (uint32_t)oc;
-                if (a.fp_item) a.fp_item[slot] = of;
-                if (on) atomicAdd(a.conn_total, (unsigned long long)on);
-                unsigned long long mb = (unsigned long long)__double_as_longlong(out[2 * NS]);
-                atomicMin(a.min_delta_bits, mb);
-                s_vtot = out[2 * NS + 1];
-            }
-            if (BWD) {
-                // S per item for the E0 gradient (reduce the saved ssum)
-                wg_barrier();
-                if (lane == 0) {
-#pragma unroll
-                    for (int k = 0; k < NS; ++k) s_red[wave][k] = sS[k];
-                }
-                wg_barrier();
-                if (tid == 0) {
-#pragma unroll
-                    for (int k = 0; k < NS; ++k) {
-                        double t = 0.0;
-                        for (int w = 0; w < NWAVE; ++w) t += s_red[w][k];
-                        a.S_item[slot * NS + k] = t;
-                    }
-                }
-                wg_barrier();
+            a.cnt_item[slot] = (uint32_t)cc;
+            if (a.fp_item) a.fp_item[slot] = ff;
+            if (cn) atomicAdd((unsigned long long *)a.conn_total, (unsigned long long)cn);
+            atomicMin(a.min_delta_bits, (unsigned long long)__double_as_longlong(mind));
+        }
+        if (BWD && a.dh) {
+            __syncthreads();
+            for (int x = lane; x < n; x += WAVE) {
+                const int np = (int)((Ib[x >> 6] >> (x & 63)) & 1ull) + (int)((Ib[NINT + (x >> 6)] >> (x & 63)) & 1ull);
+                const double v = sDHD[x] + np * vtot;
+                if (v != 0.0) atomicAdd(&a.dh[(int64_t)x * n + x], v);
             }
         }
-        if (BWD) {
-            // n_p(I) part of the diagonal gradient, then flush the item's
-            // per-orbital accumulator
-            wg_barrier();
-            if (a.dh)
-                for (int x = tid; x < n; x += QPD_WG) {
-                    int np = (int)((s_I[x >> 6] >> (x & 63)) & 1ull) + (int)((s_I[NINT + (x >> 6)] >> (x & 63)) & 1ull);
-                    double v = s_dhd[x] + np * s_vtot;
-                    if (v != 0.0) atomicAdd(&a.dh[(int64_t)x * n + x], v);
-                }
-        }
-        wg_barrier();
+        __syncthreads();
     }
+}
+
+size_t sweep_lds_bytes(int n, int ns, bool bwd)
+{
+    size_t b = 0;
+    auto add = [&](size_t bytes) { b = ((b + 15) & ~(size_t)15) + bytes; };
+    add(8 * 2 * n); add(8 * QPD_MAX_ORB); add(8 * CSCAP * QPD_MAX_ORB); add(8 * FCAP * ns); add(8 * L2CAP);
+    add(8 * (bwd ? FCAP * ns : 1)); add(8 * (bwd ? n : 1)); add(8 * 2 * QPD_MAX_NINT); add(sizeof(FineE) * FCAP);
+    add(4 * L2CAP); add(4 * CSCAP); add(ICAP); add(2 * 2 * n); add(2 * QPD_MAX_ORB); add(2 * QPD_MAX_ORB); add(2 * n);
+    add(QPD_MAX_ORB); add(8 * 4);
+    return b + 16;
 }
 
 template <int NINT, int NS, bool BWD>
 void launch_sweep(const SweepArgs &a, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((sweep_kernel<NINT, NS, BWD>), dim3(grid), dim3(QPD_WG), 0, st, a);
+    const size_t lds = sweep_lds_bytes(a.n, NS, BWD);
+    hipLaunchKernelGGL((sweep_kernel<NINT, NS, BWD>), dim3(grid), dim3(WAVE), lds, st, a);
 }
 
-#define QP_INST(NI, NS)                                                        \
-    template void launch_sweep<NI, NS, false>(const SweepArgs &, int, hipStream_t); \
-    template void launch_sweep<NI, NS, true>(const SweepArgs &, int, hipStream_t);
+template <int NINT, int NS, bool BWD>
+int sweep_occupancy(int n)
+{
+    int blocks = 0;
+    const size_t lds = sweep_lds_bytes(n, NS, BWD);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sweep_kernel<NINT, NS, BWD>, WAVE, lds) != hipSuccess)
+        return 8;
+    return blocks > 0 ? blocks : 1;
+}
+
+#define QP_INST(NI, NS)                                                              \
+    template void launch_sweep<NI, NS, false>(const SweepArgs &, int, hipStream_t);  \
+    template void launch_sweep<NI, NS, true>(const SweepArgs &, int, hipStream_t);   \
+    template int sweep_occupancy<NI, NS, false>(int);                                 \
+    template int sweep_occupancy<NI, NS, true>(int);
 QP_INST(1, 1) QP_INST(1, 2) QP_INST(1, 3) QP_INST(1, 4)
 QP_INST(2, 1) QP_INST(2, 2) QP_INST(2, 3) QP_INST(2, 4)
 QP_INST(3, 1) QP_INST(3, 2) QP_INST(3, 3) QP_INST(3, 4)
