@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqp_pt2.so")
-SOURCES = ["qp_core.hip", "qp_sweep.hip", "qp_fast.hip"]
+SOURCES = ["qp_core.hip", "qp_sweep.hip", "qp_fast_fwd.hip", "qp_fast_bwd.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

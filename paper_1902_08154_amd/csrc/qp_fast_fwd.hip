@@ -1,0 +1,7 @@
+// Forward instantiations of the dense sweep kernel (qp_fast_impl.h).
+#include "qp_fast_impl.h"
+
+QPF_INST(1, 1, false) QPF_INST(1, 2, false) QPF_INST(1, 3, false) QPF_INST(1, 4, false)
+QPF_INST(2, 1, false) QPF_INST(2, 2, false) QPF_INST(2, 3, false) QPF_INST(2, 4, false)
+QPF_INST(3, 1, false) QPF_INST(3, 2, false) QPF_INST(3, 3, false) QPF_INST(3, 4, false)
+QPF_INST(4, 1, false) QPF_INST(4, 2, false) QPF_INST(4, 3, false) QPF_INST(4, 4, false)
