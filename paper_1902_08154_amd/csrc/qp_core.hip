@@ -864,24 +864,24 @@ int sweep_grid(qp_ctx *c, int nint, int ns, bool bwd)
 }
 
 template <int NINT>
-int focc_ns(int n, int ns, bool bwd, int rc, int cc)
+int focc_ns(int n, int nvm, int ns, bool bwd, int rc, int cc)
 {
     switch (ns) {
-    case 1: return bwd ? fast_occupancy<NINT, 1, true>(n, rc, cc) : fast_occupancy<NINT, 1, false>(n, rc, cc);
-    case 2: return bwd ? fast_occupancy<NINT, 2, true>(n, rc, cc) : fast_occupancy<NINT, 2, false>(n, rc, cc);
-    case 3: return bwd ? fast_occupancy<NINT, 3, true>(n, rc, cc) : fast_occupancy<NINT, 3, false>(n, rc, cc);
-    default: return bwd ? fast_occupancy<NINT, 4, true>(n, rc, cc) : fast_occupancy<NINT, 4, false>(n, rc, cc);
+    case 1: return bwd ? fast_occupancy<NINT, 1, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 1, false>(n, nvm, rc, cc);
+    case 2: return bwd ? fast_occupancy<NINT, 2, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 2, false>(n, nvm, rc, cc);
+    case 3: return bwd ? fast_occupancy<NINT, 3, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 3, false>(n, nvm, rc, cc);
+    default: return bwd ? fast_occupancy<NINT, 4, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 4, false>(n, nvm, rc, cc);
     }
 }
 
-int fast_grid(qp_ctx *c, int nint, int ns, bool bwd, int rc, int cc)
+int fast_grid(qp_ctx *c, int nint, int ns, bool bwd, int nvm, int rc, int cc)
 {
     int per_cu = 8;
     switch (nint) {
-    case 1: per_cu = focc_ns<1>(c->n, ns, bwd, rc, cc); break;
-    case 2: per_cu = focc_ns<2>(c->n, ns, bwd, rc, cc); break;
-    case 3: per_cu = focc_ns<3>(c->n, ns, bwd, rc, cc); break;
-    default: per_cu = focc_ns<4>(c->n, ns, bwd, rc, cc); break;
+    case 1: per_cu = focc_ns<1>(c->n, nvm, ns, bwd, rc, cc); break;
+    case 2: per_cu = focc_ns<2>(c->n, nvm, ns, bwd, rc, cc); break;
+    case 3: per_cu = focc_ns<3>(c->n, nvm, ns, bwd, rc, cc); break;
+    default: per_cu = focc_ns<4>(c->n, nvm, ns, bwd, rc, cc); break;
     }
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
@@ -936,7 +936,7 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     if (!eps_item || !S_item || !cnt_item || !fp_item || (bwd && !dc_item) || !eps_g || !S_g || !cnt_g || !fp_g || !hist)
         return fail(c, QP_E_OOM, "device allocation failed (sweep buffers)");
     const int rscap = n <= 128 ? 4 : 2, cscap = n <= 128 ? 4 : 2;
-    const int fgrid = fast_grid(c, nint, ns, bwd, rscap, cscap);
+    const int fgrid = fast_grid(c, nint, ns, bwd, n - std::min(P.nup, P.ndn), rscap, cscap);
     const int ggrid = sweep_grid(c, nint, ns, bwd);
     const int grid = std::max(fgrid, ggrid);
     // batches the fast kernel hands to the general kernel

@@ -66,15 +66,55 @@ __device__ __forceinline__ uint64_t between_mask(int w, int lo, int hi)
     return up & (~0ull << a);
 }
 
-// parity of the number of set bits of one spin string strictly between x and y
+// Private arrays are indexed only by compile-time constants here (loops are
+// unrolled and runtime choices are selects): a runtime index would place the
+// array in scratch memory.
+
+// word q of spin s of a bit string
 template <int NINT>
-__device__ __forceinline__ int between_parity(const uint64_t *s, int x, int y)
+__device__ __forceinline__ uint64_t spin_word(const uint64_t *d, int s, int q)
 {
-    int lo = x < y ? x : y, hi = x < y ? y : x;
+    uint64_t r = 0;
+#pragma unroll
+    for (int w = 0; w < NINT; ++w)
+        if (w == q) r = s ? d[NINT + w] : d[w];
+    return r;
+}
+
+// occupation of spin-orbital (s, p)
+template <int NINT>
+__device__ __forceinline__ int occ_bit(const uint64_t *d, int s, int p)
+{
+    return (int)((spin_word<NINT>(d, s, p >> 6) >> (p & 63)) & 1ull);
+}
+
+// parity of the number of set bits of spin s of d strictly between x and y
+template <int NINT>
+__device__ __forceinline__ int between_parity(const uint64_t *d, int s, int x, int y)
+{
+    const int lo = x < y ? x : y, hi = x < y ? y : x;
     int c = 0;
 #pragma unroll
-    for (int w = 0; w < NINT; ++w) c += popc64(s[w] & between_mask(w, lo, hi));
+    for (int w = 0; w < NINT; ++w) c += popc64((s ? d[NINT + w] : d[w]) & between_mask(w, lo, hi));
     return c & 1;
+}
+
+// word w of alpha = I - holes + particles; each hole or particle is given as
+// (spin, orbital); hc = spin << 8 | orbital, -1 when absent, pb < 0 when absent
+template <int NINT>
+__device__ __forceinline__ uint64_t alpha_word(const uint64_t *Ib, int w, int hc0, int hc1, int pa, int sa, int pb,
+                                               int sb)
+{
+    uint64_t x = Ib[w];
+    const int base = 64 * (w % NINT), sp = w / NINT;
+    auto tog = [&](int s_, int p_) {
+        if (s_ == sp && p_ - base >= 0 && p_ - base < 64) x ^= 1ull << (p_ - base);
+    };
+    tog(hc0 >> 8, hc0 & 255);
+    if (hc1 >= 0) tog(hc1 >> 8, hc1 & 255);
+    tog(sa, pa);
+    if (pb >= 0) tog(sb, pb);
+    return x;
 }
 
 // splitmix64 output function (Steele, Lea & Flood 2014)
@@ -117,6 +157,19 @@ __device__ double fock_offdiag(const DevInts &I, const uint64_t *J, int s, int p
     return v;
 }
 
+// merge the two lowest set bits of m (bit positions offset by base) into the
+// ascending pair (a, b), -1 marking an empty place; value selects only
+__device__ __forceinline__ void low2_merge(uint64_t m, int base, int &a, int &b)
+{
+    const int x1 = m ? base + ctz64(m) : -1;
+    const uint64_t m2 = m & (m - 1);
+    const int x2 = m2 ? base + ctz64(m2) : -1;
+    const bool na = a < 0;
+    const int nb = na ? x2 : (b < 0 ? x1 : b);
+    a = na ? x1 : a;
+    b = nb;
+}
+
 // Generic Slater-Condon element <bra|H|ket> for 1 <= degree <= 2 (returns 0
 // otherwise).  Phase: product of single-excitation phases, the second one on
 // the intermediate determinant (same spin) or per spin (opposite spins).
@@ -126,56 +179,48 @@ template <int NINT>
 __device__ double sc_offdiag(const DevInts &I, const uint64_t *bra, const uint64_t *ket,
                              int *deg_out, int *sgl)
 {
-    int dsp[2];
-    int deg = 0;
+    int c0 = 0, c1 = 0;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        int c = 0;
-#pragma unroll
-        for (int w = 0; w < NINT; ++w) c += popc64(bra[s * NINT + w] ^ ket[s * NINT + w]);
-        dsp[s] = c >> 1;
-        deg += c >> 1;
+    for (int w = 0; w < NINT; ++w) {
+        c0 += popc64(bra[w] ^ ket[w]);
+        c1 += popc64(bra[NINT + w] ^ ket[NINT + w]);
     }
+    const int d0 = c0 >> 1, d1 = c1 >> 1, deg = d0 + d1;
     if (deg_out) *deg_out = deg;
     if (deg == 0 || deg > 2) return 0.0;
-    // holes (in ket) and particles (in bra), per spin, ascending
-    int hl[2][2], pt[2][2], nh[2] = {0, 0}, np[2] = {0, 0};
+    // the (at most two) holes in ket and particles in bra of each spin, ascending
+    int h0a = -1, h0b = -1, p0a = -1, p0b = -1, h1a = -1, h1b = -1, p1a = -1, p1b = -1;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-#pragma unroll
-        for (int w = 0; w < NINT; ++w) {
-            uint64_t x = bra[s * NINT + w] ^ ket[s * NINT + w];
-            uint64_t hh = x & ket[s * NINT + w], pp = x & bra[s * NINT + w];
-            while (hh) { if (nh[s] < 2) hl[s][nh[s]] = 64 * w + ctz64(hh); nh[s]++; hh &= hh - 1; }
-            while (pp) { if (np[s] < 2) pt[s][np[s]] = 64 * w + ctz64(pp); np[s]++; pp &= pp - 1; }
-        }
+    for (int w = 0; w < NINT; ++w) {
+        const uint64_t x0 = bra[w] ^ ket[w], x1 = bra[NINT + w] ^ ket[NINT + w];
+        low2_merge(x0 & ket[w], 64 * w, h0a, h0b);
+        low2_merge(x0 & bra[w], 64 * w, p0a, p0b);
+        low2_merge(x1 & ket[NINT + w], 64 * w, h1a, h1b);
+        low2_merge(x1 & bra[NINT + w], 64 * w, p1a, p1b);
     }
     if (deg == 1) {
-        int s = dsp[0] == 1 ? 0 : 1;
-        int h = hl[s][0], p = pt[s][0];
-        int sg = between_parity<NINT>(ket + s * NINT, h, p);
-        double v = fock_offdiag<NINT>(I, ket, s, h, p);
+        const int s = d0 == 1 ? 0 : 1;
+        const int h = s ? h1a : h0a, p = s ? p1a : p0a;
+        const int sg = between_parity<NINT>(ket, s, h, p);
+        const double v = fock_offdiag<NINT>(I, ket, s, h, p);
         if (sgl) { sgl[0] = h; sgl[1] = p; sgl[2] = s; sgl[3] = sg ? -1 : 1; }
         return sg ? -v : v;
     }
     if (sgl) sgl[0] = -1;
-    if (dsp[0] == 1) {
+    if (d0 == 1) {
         // opposite spins
-        int sg = between_parity<NINT>(ket, hl[0][0], pt[0][0]) ^
-                 between_parity<NINT>(ket + NINT, hl[1][0], pt[1][0]);
-        double v = eri_x(I, hl[0][0], pt[0][0], hl[1][0], pt[1][0]);
+        const int sg = between_parity<NINT>(ket, 0, h0a, p0a) ^ between_parity<NINT>(ket, 1, h1a, p1a);
+        const double v = eri_x(I, h0a, p0a, h1a, p1a);
         return sg ? -v : v;
     }
-    int s = dsp[0] == 2 ? 0 : 1;
-    int h1 = hl[s][0], h2 = hl[s][1], p1 = pt[s][0], p2 = pt[s][1];
-    uint64_t mid[QPD_MAX_NINT];
-#pragma unroll
-    for (int w = 0; w < NINT; ++w) mid[w] = ket[s * NINT + w];
-    int sg = between_parity<NINT>(mid, h1, p1);
-    mid[h1 >> 6] ^= 1ull << (h1 & 63);
-    mid[p1 >> 6] ^= 1ull << (p1 & 63);
-    sg ^= between_parity<NINT>(mid, h2, p2);
-    double v = eri_x(I, h1, p1, h2, p2) - eri_x(I, h1, p2, h2, p1);
+    const int s = d0 == 2 ? 0 : 1;
+    const int h1 = s ? h1a : h0a, h2 = s ? h1b : h0b, p1 = s ? p1a : p0a, p2 = s ? p1b : p0b;
+    // second excitation acts on ket with h1 -> p1 applied: h1 leaves and p1
+    // enters the range strictly between h2 and p2
+    const int lo = h2 < p2 ? h2 : p2, hi = h2 < p2 ? p2 : h2;
+    const int sg = between_parity<NINT>(ket, s, h1, p1) ^ between_parity<NINT>(ket, s, h2, p2) ^
+                   (int)(lo < h1 && h1 < hi) ^ (int)(lo < p1 && p1 < hi);
+    const double v = eri_x(I, h1, p1, h2, p2) - eri_x(I, h1, p2, h2, p1);
     return sg ? -v : v;
 }
 
@@ -281,4 +326,4 @@ int sweep_occupancy(int n);
 template <int NINT, int NS, bool BWD>
 void launch_fast(const SweepArgs &a, int grid, hipStream_t st);
 template <int NINT, int NS, bool BWD>
-int fast_occupancy(int n, int rscap, int cscap);
+int fast_occupancy(int n, int nvm, int rscap, int cscap);

@@ -30,6 +30,7 @@
 // exact and leaves the minimum |delta| untouched.
 #pragma once
 #include "qp_dev.h"
+#include "qp_fast_caps.h"
 
 namespace qpfast {
 
@@ -131,29 +132,23 @@ __device__ __forceinline__ double celem(const DevInts &I, const uint64_t *Ib, in
     uint64_t al[2 * NINT], jb[2 * NINT];
 #pragma unroll
     for (int w = 0; w < 2 * NINT; ++w) {
-        uint64_t x = Ib[w];
-        const int base = 64 * (w % NINT), sp = w / NINT;
-        if ((hc0 >> 8) == sp && (hc0 & 255) - base >= 0 && (hc0 & 255) - base < 64) x ^= 1ull << ((hc0 & 255) - base);
-        if (hc1 >= 0 && (hc1 >> 8) == sp && (hc1 & 255) - base >= 0 && (hc1 & 255) - base < 64)
-            x ^= 1ull << ((hc1 & 255) - base);
-        if (sa == sp && pa - base >= 0 && pa - base < 64) x ^= 1ull << (pa - base);
-        if (pb >= 0 && sb == sp && pb - base >= 0 && pb - base < 64) x ^= 1ull << (pb - base);
-        al[w] = x;
+        al[w] = alpha_word<NINT>(Ib, w, hc0, hc1, pa, sa, pb, sb);
         jb[w] = J[w];
     }
     return sc_offdiag<NINT>(I, al, jb, deg, sgl);
 }
 
-inline size_t lds_bytes(int n, int ns, bool bwd, int rscap, int cscap)
+// LDS of one workgroup; nvm = largest number of virtual orbitals of a spin.
+// Kept small on purpose: it bounds how many one-wave workgroups a CU holds.
+inline size_t lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap)
 {
     size_t b = 0;
     auto add = [&](size_t bytes) { b = ((b + 15) & ~(size_t)15) + bytes; };
-    add(8 * 2 * n);                 // F
-    add(16 * n);                    // row-spin particle table
-    add(16 * n);                    // column-spin particle table
-    add(8 * rscap * n);             // row buffers
-    add(4 * (bwd ? rscap * n : 1)); // row buffer single-excitation info (adjoint)
-    add(8 * cscap * n);             // column buffers
+    add(16 * nvm);                    // row-spin particle table
+    add(16 * nvm);                    // column-spin particle table
+    add(8 * rscap * nvm);             // row buffers
+    add(4 * (bwd ? rscap * nvm : 1)); // row buffer single-excitation info (adjoint)
+    add(8 * cscap * nvm);             // column buffers
     add(8 * FCAP * ns);             // fine coefficients
     add(8 * L2CAP);                 // list values
     add(8 * (bwd ? FCAP * ns : 1)); // adjoint per-entry accumulators
@@ -163,15 +158,16 @@ inline size_t lds_bytes(int n, int ns, bool bwd, int rscap, int cscap)
     add(4 * rscap);
     add(4 * cscap);
     add(2 * 2 * n);                 // vidx
-    add(2 * QPD_MAX_ORB);           // occ
-    add(2 * QPD_MAX_ORB);           // virt
+    add(2 * n);                     // occ
+    add(2 * n);                     // virt
     add(2 * n);                     // cnt
     return b + 16;
 }
 
-// waves per SIMD the register allocation aims for (spills stay out of the cell loops)
+// waves per SIMD the register allocation aims for: the highest target at
+// which the kernel needs no spill memory (see qp_fast_caps.h)
 template <int NINT, int NS, bool BWD>
-constexpr int waves_target() { return (NS <= 2 && NINT <= 2 && !BWD) ? 6 : 5; }
+constexpr int waves_target() { return qpf_caps[BWD ? 1 : 0][NINT - 1][NS - 1]; }
 
 template <int NINT, int NS, bool BWD, bool FP>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_target<NINT, NS, BWD>(), 8)))
@@ -187,14 +183,14 @@ void fast_kernel(SweepArgs a)
     const int Q = a.q_per_gen;
     const int RSCAP = a.rscap, CSCAP = a.cscap;
     const bool want_sel = a.n_select > 0;
+    const int nvm = n - (a.nup < a.ndn ? a.nup : a.ndn);
 
     unsigned off = 0;
-    double *sF = carve<double>(lds, off, 2 * n);
-    PEnt *sRT = carve<PEnt>(lds, off, n);
-    PEnt *sCT = carve<PEnt>(lds, off, n);
-    double *sRB = carve<double>(lds, off, RSCAP * n);
-    uint32_t *sRI = carve<uint32_t>(lds, off, BWD ? RSCAP * n : 1);
-    double *sCB = carve<double>(lds, off, CSCAP * n);
+    PEnt *sRT = carve<PEnt>(lds, off, nvm);
+    PEnt *sCT = carve<PEnt>(lds, off, nvm);
+    double *sRB = carve<double>(lds, off, RSCAP * nvm);
+    uint32_t *sRI = carve<uint32_t>(lds, off, BWD ? RSCAP * nvm : 1);
+    double *sCB = carve<double>(lds, off, CSCAP * nvm);
     double *sFC = carve<double>(lds, off, FCAP * NS);
     double *sLH = carve<double>(lds, off, L2CAP);
     double *sDCF = carve<double>(lds, off, BWD ? FCAP * NS : 1);
@@ -204,8 +200,8 @@ void fast_kernel(SweepArgs a)
     uint32_t *sRSg = carve<uint32_t>(lds, off, RSCAP); // row | f << 16 | ban << 24
     uint32_t *sCSg = carve<uint32_t>(lds, off, CSCAP); // col | f << 16 | ban << 24
     uint16_t *sVidx = carve<uint16_t>(lds, off, 2 * n);
-    uint8_t *sOcc = carve<uint8_t>(lds, off, 2 * QPD_MAX_ORB);
-    uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * QPD_MAX_ORB);
+    uint8_t *sOcc = carve<uint8_t>(lds, off, 2 * n);
+    uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
     uint8_t *sCnt = carve<uint8_t>(lds, off, 2 * n);
 
     double E0[NS], gup[NS], cI[NS], invm[NS];
@@ -234,20 +230,20 @@ void fast_kernel(SweepArgs a)
             int c = 0;
 #pragma unroll
             for (int qq = 0; qq < NINT; ++qq) {
-                const uint64_t wv = Ib[s * NINT + qq];
+                const uint64_t wv = s ? Ib[NINT + qq] : Ib[qq];
                 if (64 * qq + 63 < p) c += popc64(wv);
                 else if (64 * qq <= p) c += popc64(wv & ((1ull << (p - 64 * qq)) - 1ull));
             }
-            const bool occ = (Ib[s * NINT + (p >> 6)] >> (p & 63)) & 1ull;
+            const bool occ = occ_bit<NINT>(Ib, s, p) != 0;
             sCnt[x] = (uint8_t)c;
-            if (occ) { sOcc[s * QPD_MAX_ORB + c] = (uint8_t)p; sVidx[x] = 0xFFFF; }
-            else { sVirt[s * QPD_MAX_ORB + p - c] = (uint8_t)p; sVidx[x] = (uint16_t)(p - c); }
-            sF[x] = a.F[(g * 2) * n + x];
+            if (occ) { sOcc[s * n + c] = (uint8_t)p; sVidx[x] = 0xFFFF; }
+            else { sVirt[s * n + p - c] = (uint8_t)p; sVidx[x] = (uint16_t)(p - c); }
             if (BWD && s == 0) sDHD[p] = 0.0;
         }
 #pragma unroll
         for (int k = 0; k < NS; ++k) cI[k] = a.coefs[(int64_t)k * a.n_det + det];
         const double HII = a.HII[g];
+        const double *Fg = a.F + g * 2 * n;   // Fock diagonal of the generator, both spins
         const int64_t cbeg = a.coff[g], cend = a.coff[g + 1];
         __syncthreads();
 
@@ -271,17 +267,17 @@ void fast_kernel(SweepArgs a)
                 if (b < nel) i1 = b;
                 else tdec(b - nel, i1, i2);
                 s1 = i1 < nup ? 0 : 1;
-                h1 = i1 < nup ? sOcc[i1] : sOcc[QPD_MAX_ORB + i1 - nup];
+                h1 = i1 < nup ? sOcc[i1] : sOcc[n + i1 - nup];
                 if (i2 < 0) {
                     type = BT_SINGLE; rs = cs = s1; nr = nc = s1 == 0 ? nv0 : nv1; sH = 0;
-                    D0 = HII - sF[s1 * n + h1];
+                    D0 = HII - Fg[s1 * n + h1];
                 } else {
                     s2 = i2 < nup ? 0 : 1;
-                    h2 = i2 < nup ? sOcc[i2] : sOcc[QPD_MAX_ORB + i2 - nup];
+                    h2 = i2 < nup ? sOcc[i2] : sOcc[n + i2 - nup];
                     if (s2 == s1) {
                         type = BT_SS; rs = cs = s1; nr = nc = s1 == 0 ? nv0 : nv1;
                         sH = (sCnt[s1 * n + h1] + sCnt[s1 * n + h2] - 1) & 1;
-                        D0 = HII - sF[s1 * n + h1] - sF[s1 * n + h2] + a.I.JK[h1 * n + h2];
+                        D0 = HII - Fg[s1 * n + h1] - Fg[s1 * n + h2] + a.I.JK[h1 * n + h2];
                         blk = a.I.Y + qtris(h1, h2) * (int64_t)P2;
                     } else {
                         type = BT_OS;
@@ -289,14 +285,14 @@ void fast_kernel(SweepArgs a)
                         else { rs = 1; cs = 0; blk = a.I.X + qtri(h2, h1) * n2; }
                         nr = rs == 0 ? nv0 : nv1; nc = cs == 0 ? nv0 : nv1;
                         sH = (sCnt[h1] + sCnt[n + h2]) & 1;
-                        D0 = HII - sF[h1] - sF[n + h2] + a.I.Jm[h1 * n + h2];
+                        D0 = HII - Fg[h1] - Fg[n + h2] + a.I.Jm[h1 * n + h2];
                     }
                 }
             }
             const int hc0 = (s1 << 8) | h1;
             const int hc1 = type == BT_SINGLE ? -1 : ((s2 << 8) | h2);
-            const uint8_t *rvirt = sVirt + rs * QPD_MAX_ORB;
-            const uint8_t *cvirt = sVirt + cs * QPD_MAX_ORB;
+            const uint8_t *rvirt = sVirt + rs * n;
+            const uint8_t *cvirt = sVirt + cs * n;
             const int hrs = type == BT_OS ? (rs == 0 ? h1 : h2) : h1;
             const int hro = type == BT_OS ? (rs == 0 ? h2 : h1) : (type == BT_SS ? h2 : -1);
 
@@ -304,7 +300,7 @@ void fast_kernel(SweepArgs a)
             for (int i = lane; i < nr; i += WAVE) {
                 const int p = rvirt[i];
                 int par = sCnt[rs * n + p] - (hrs < p);
-                double gv = sF[rs * n + p] - a.I.JK[hrs * n + p];
+                double gv = Fg[rs * n + p] - a.I.JK[hrs * n + p];
                 if (type == BT_SINGLE) par += sCnt[rs * n + h1];
                 else if (type == BT_SS) { par -= (hro < p); gv -= a.I.JK[hro * n + p]; }
                 else gv -= a.I.Jm[hro * n + p];
@@ -318,7 +314,7 @@ void fast_kernel(SweepArgs a)
                     const int p = cvirt[c];
                     const int csg = (sH + sCnt[cs * n + p] - (hcs < p)) & 1;
                     PEnt e;
-                    e.G = D0 + sF[cs * n + p] - a.I.JK[hcs * n + p] - a.I.Jm[hco * n + p];
+                    e.G = D0 + Fg[cs * n + p] - a.I.JK[hcs * n + p] - a.I.Jm[hco * n + p];
                     e.info = (uint32_t)p | (csg ? SGN : 0u); e.pad = 0;
                     sCT[c] = e;
                 }
@@ -483,8 +479,8 @@ void fast_kernel(SweepArgs a)
                     else { pa = rvirt[x]; sa = rs; }
                     int deg, sgl[4] = {-1, -1, 0, 0};
                     const double v = celem<NINT>(a.I, Ib, hc0, hc1, pa, sa, pb, sb, Jb, &deg, BWD ? sgl : nullptr);
-                    sRB[s * n + x] = v;
-                    if (BWD) sRI[s * n + x] = deg == 1 ? (uint32_t)(sgl[0] | (sgl[1] << 8) | ((sgl[3] < 0) << 16) | (1u << 17)) : 0u;
+                    sRB[s * nvm + x] = v;
+                    if (BWD) sRI[s * nvm + x] = deg == 1 ? (uint32_t)(sgl[0] | (sgl[1] << 8) | ((sgl[3] < 0) << 16) | (1u << 17)) : 0u;
                 }
             }
             for (int s = 0; s < ncs; ++s) {
@@ -504,7 +500,7 @@ void fast_kernel(SweepArgs a)
                         int deg;
                         v = celem<NINT>(a.I, Ib, hc0, hc1, pa, sa, pb, sb, Jb, &deg, nullptr);
                     }
-                    sCB[s * n + r] = v;
+                    sCB[s * nvm + r] = v;
                 }
             }
             if (BWD) for (int x = lane; x < FCAP * NS; x += WAVE) sDCF[x] = 0.0;
@@ -531,7 +527,7 @@ void fast_kernel(SweepArgs a)
                         if ((sg >> 24) & 1) banned = true;
                         else {
                             const int f = (sg >> 16) & 255;
-                            const double v = sRB[s * n + x_];
+                            const double v = sRB[s * nvm + x_];
                             nco++;
 #pragma unroll
                             for (int k = 0; k < NS; ++k) A[k] = fma(sFC[f * NS + k], v, A[k]);
@@ -546,7 +542,7 @@ void fast_kernel(SweepArgs a)
                     if (hit) {
                         if ((sg >> 24) & 1) banned = true;
                         else {
-                            const double v = sCB[s * n + rowi];
+                            const double v = sCB[s * nvm + rowi];
                             nco++;
 #pragma unroll
                             for (int k = 0; k < NS; ++k) A[k] = fma(sFC[f * NS + k], v, A[k]);
@@ -577,10 +573,10 @@ void fast_kernel(SweepArgs a)
                     const bool hit = type == BT_OS ? row == i1 : (type == BT_SS ? row == i2 : true);
                     const int x_ = type == BT_OS ? i2 : i1;
                     if (!hit) continue;
-                    const double hv = sRB[s * n + x_];
+                    const double hv = sRB[s * nvm + x_];
 #pragma unroll
                     for (int k = 0; k < NS; ++k) atomicAdd(&sDCF[f * NS + k], w[k] * hv);
-                    const uint32_t inf = sRI[s * n + x_];
+                    const uint32_t inf = sRI[s * nvm + x_];
                     if (((inf >> 17) & 1u) && a.dh) {
                         double gs = 0.0;
 #pragma unroll
@@ -597,7 +593,7 @@ void fast_kernel(SweepArgs a)
                     const int col = sg & 0xFFFF, f = (sg >> 16) & 255;
                     const int rowi = type == BT_OS ? i1 : i2;
                     if ((type == BT_OS ? i2 : i1) == col && !has(sFine[f].er, sFine[f].ner, rowi)) {
-                        const double hv = sCB[s * n + rowi];
+                        const double hv = sCB[s * nvm + rowi];
 #pragma unroll
                         for (int k = 0; k < NS; ++k) atomicAdd(&sDCF[f * NS + k], w[k] * hv);
                     }
@@ -671,11 +667,7 @@ void fast_kernel(SweepArgs a)
             auto fold = [&](int pa, int pb) {
                 uint64_t al[2 * NINT];
 #pragma unroll
-                for (int w = 0; w < 2 * NINT; ++w) al[w] = Ib[w];
-                al[(hc0 >> 8) * NINT + ((hc0 & 255) >> 6)] ^= 1ull << (hc0 & 63);
-                if (hc1 >= 0) al[(hc1 >> 8) * NINT + ((hc1 & 255) >> 6)] ^= 1ull << (hc1 & 63);
-                al[rs * NINT + (pa >> 6)] ^= 1ull << (pa & 63);
-                if (pb >= 0) al[cs * NINT + (pb >> 6)] ^= 1ull << (pb & 63);
+                for (int w = 0; w < 2 * NINT; ++w) al[w] = alpha_word<NINT>(Ib, w, hc0, hc1, pa, rs, pb, cs);
                 return det_fold<NINT>(al);
             };
 
@@ -952,7 +944,7 @@ void fast_kernel(SweepArgs a)
         if (BWD && a.dh) {
             __syncthreads();
             for (int x = lane; x < n; x += WAVE) {
-                const int np = (int)((Ib[x >> 6] >> (x & 63)) & 1ull) + (int)((Ib[NINT + (x >> 6)] >> (x & 63)) & 1ull);
+                const int np = occ_bit<NINT>(Ib, 0, x) + occ_bit<NINT>(Ib, 1, x);
                 const double v = sDHD[x] + np * vtot;
                 if (v != 0.0) atomicAdd(&a.dh[(int64_t)x * n + x], v);
             }
@@ -966,7 +958,8 @@ void fast_kernel(SweepArgs a)
 template <int NINT, int NS, bool BWD>
 void launch_fast(const SweepArgs &a, int grid, hipStream_t st)
 {
-    const size_t lds = qpfast::lds_bytes(a.n, NS, BWD, a.rscap, a.cscap);
+    const int nvm = a.n - (a.nup < a.ndn ? a.nup : a.ndn);
+    const size_t lds = qpfast::lds_bytes(a.n, nvm, NS, BWD, a.rscap, a.cscap);
     if (a.flags & 1)
         hipLaunchKernelGGL((qpfast::fast_kernel<NINT, NS, BWD, true>), dim3(grid), dim3(qpfast::WAVE), lds, st, a);
     else
@@ -974,10 +967,10 @@ void launch_fast(const SweepArgs &a, int grid, hipStream_t st)
 }
 
 template <int NINT, int NS, bool BWD>
-int fast_occupancy(int n, int rscap, int cscap)
+int fast_occupancy(int n, int nvm, int rscap, int cscap)
 {
     int blocks = 0;
-    const size_t lds = qpfast::lds_bytes(n, NS, BWD, rscap, cscap);
+    const size_t lds = qpfast::lds_bytes(n, nvm, NS, BWD, rscap, cscap);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, qpfast::fast_kernel<NINT, NS, BWD, false>, qpfast::WAVE,
                                                      lds) != hipSuccess)
         return 8;
@@ -986,4 +979,4 @@ int fast_occupancy(int n, int rscap, int cscap)
 
 #define QPF_INST(NI, NS, B)                                                     \
     template void launch_fast<NI, NS, B>(const SweepArgs &, int, hipStream_t); \
-    template int fast_occupancy<NI, NS, B>(int, int, int);
+    template int fast_occupancy<NI, NS, B>(int, int, int, int);

@@ -107,18 +107,14 @@ __device__ __forceinline__ double wave_sum(double v)
 }  // namespace
 
 // generic <J|H|alpha>, alpha = I with the holes removed and the particles
-// added; out of line so the dense loop keeps a small register budget
+// added
 template <int NINT>
-__device__ __noinline__ double corr_element(const DevInts I, const uint64_t *Ibits, int h0, int h1c, int pa,
+__device__ __forceinline__ double corr_element(const DevInts I, const uint64_t *Ibits, int h0, int h1c, int pa,
                                             int sa, int pb, int sb, const uint64_t *J, int *deg, int *sgl)
 {
     uint64_t al[2 * NINT];
 #pragma unroll
-    for (int w = 0; w < 2 * NINT; ++w) al[w] = Ibits[w];
-    al[(h0 >> 8) * NINT + ((h0 & 255) >> 6)] ^= 1ull << (h0 & 63);
-    if (h1c >= 0) al[(h1c >> 8) * NINT + ((h1c & 255) >> 6)] ^= 1ull << (h1c & 63);
-    al[sa * NINT + (pa >> 6)] ^= 1ull << (pa & 63);
-    if (pb >= 0) al[sb * NINT + (pb >> 6)] ^= 1ull << (pb & 63);
+    for (int w = 0; w < 2 * NINT; ++w) al[w] = alpha_word<NINT>(Ibits, w, h0, h1c, pa, sa, pb, sb);
     uint64_t Jb[2 * NINT];
 #pragma unroll
     for (int w = 0; w < 2 * NINT; ++w) Jb[w] = J[w];
@@ -196,14 +192,14 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs a)
         if (lane < 2 * NINT) sI[lane] = a.dets[(int64_t)det * 2 * NINT + lane];
         for (int x = lane; x < 2 * n; x += WAVE) {
             const int s = x >= n ? 1 : 0, p = x - s * n;
-            const uint64_t *w = Ib + s * NINT;
             int c = 0;
 #pragma unroll
             for (int qq = 0; qq < NINT; ++qq) {
-                if (64 * qq + 63 < p) c += popc64(w[qq]);
-                else if (64 * qq <= p) c += popc64(w[qq] & ((1ull << (p - 64 * qq)) - 1ull));
+                const uint64_t wv = s ? Ib[NINT + qq] : Ib[qq];
+                if (64 * qq + 63 < p) c += popc64(wv);
+                else if (64 * qq <= p) c += popc64(wv & ((1ull << (p - 64 * qq)) - 1ull));
             }
-            const bool occ = (w[p >> 6] >> (p & 63)) & 1ull;
+            const bool occ = occ_bit<NINT>(Ib, s, p) != 0;
             sCnt[x] = (uint8_t)c;
             if (occ) { sOcc[s * QPD_MAX_ORB + c] = (uint8_t)p; sVidx[x] = 0xFFFF; }
             else { sVirt[s * QPD_MAX_ORB + p - c] = (uint8_t)p; sVidx[x] = (uint16_t)(p - c); }
@@ -598,11 +594,7 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs a)
                         if (want_fp) {
                             uint64_t al[2 * NINT];
 #pragma unroll
-                            for (int w = 0; w < 2 * NINT; ++w) al[w] = Ib[w];
-                            al[(hc0 >> 8) * NINT + ((hc0 & 255) >> 6)] ^= 1ull << (hc0 & 63);
-                            if (hc1 >= 0) al[(hc1 >> 8) * NINT + ((hc1 & 255) >> 6)] ^= 1ull << (hc1 & 63);
-                            al[sa * NINT + (pa >> 6)] ^= 1ull << (pa & 63);
-                            if (pb >= 0) al[sb * NINT + (pb >> 6)] ^= 1ull << (pb & 63);
+                            for (int w = 0; w < 2 * NINT; ++w) al[w] = alpha_word<NINT>(Ib, w, hc0, hc1, pa, sa, pb, sb);
                             fpsum += det_fold<NINT>(al);
                         }
                     }
@@ -843,7 +835,7 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs a)
         if (BWD && a.dh) {
             __syncthreads();
             for (int x = lane; x < n; x += WAVE) {
-                const int np = (int)((Ib[x >> 6] >> (x & 63)) & 1ull) + (int)((Ib[NINT + (x >> 6)] >> (x & 63)) & 1ull);
+                const int np = occ_bit<NINT>(Ib, 0, x) + occ_bit<NINT>(Ib, 1, x);
                 const double v = sDHD[x] + np * vtot;
                 if (v != 0.0) atomicAdd(&a.dh[(int64_t)x * n + x], v);
             }
