@@ -32,15 +32,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_ops(stats, ns, nint):
-    """Method-intrinsic lane operations of one sweep: a ban test per candidate
-    cell (3), the per-state FP64 work of each external determinant (15: the
-    element's phase and scaling, the diagonal update, the denominator, the
-    energy and its two accumulations, the selection test) and, per connection
-    to a non-generator J, the excitation analysis on 2*n_int words (12 per word)
-    plus 2 FP64 per state."""
-    return (3.0 * stats["n_cells"] + 15.0 * ns * stats["n_alpha"]
-            + (12.0 * nint + 2.0 * ns) * stats["n_connections"])
+def ops_per_alpha(stats, ns, nint):
+    """Method-intrinsic lane operations per external determinant: the ban test
+    (3), the per-state FP64 work (15: the element's phase and scaling, the
+    diagonal update, the denominator, the energy and its two accumulations, the
+    selection test) and, for each connection to a non-generator J, the
+    excitation analysis on 2*n_int words (12 per word) plus 2 FP64 per state
+    (connections per alpha averaged over the sweep)."""
+    conn = stats["n_connections"] / max(stats["n_alpha"], 1)
+    return 3.0 + 15.0 * ns + (12.0 * nint + 2.0 * ns) * conn
 
 
 def cpu_baseline(s, E0, n_gen):
@@ -51,7 +51,8 @@ def cpu_baseline(s, E0, n_gen):
     t0 = time.perf_counter()
     r = oracle.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, pick)
     dt = time.perf_counter() - t0
-    return dict(value=float(r.count.sum()) / dt, unit="alpha/s", cores=int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))),
+    return dict(value=float(r.count.sum()) / dt, unit="alpha/s",
+                cores=int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))),
                 kind="oracle",
                 sample=f"{n_gen} generators evenly spaced in generator order ({int(r.count.sum())} alpha, {dt:.1f} s)")
 
@@ -64,6 +65,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bwd-steps", type=int, default=2)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the steps, copy MIB MiB device to device once: a transfer of known size "
+                         "against which the HBM traffic counters of the sweep are scaled")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (see the sharding note in the "
@@ -103,26 +107,32 @@ def main():
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
-        log(f"warmup {i}: sweep {ctx.qp_last_timing()[0]:.2f} ms")
-    sweep_ms = []
+        tm = ctx.qp_last_timing()
+        log(f"warmup {i}: dense kernel {tm[0]:.2f} ms, general kernel {tm[1]:.2f} ms, call {tm[2]:.2f} ms")
+    timings = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
-        sweep_ms.append(ctx.qp_last_timing()[0])
+        timings.append(ctx.qp_last_timing())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     from paper_1902_08154_amd.api import stats_to_dict
     stats = stats_to_dict(st, ns)
     ms_per_step = 1e3 * elapsed / args.steps
     value = stats["n_alpha"] * args.steps / elapsed
-    kern_s = float(np.mean(sweep_ms)) * 1e-3
-    ops = algorithmic_ops(stats, ns, nint)
-    log(f"E_PT2 = {e_out.cpu().numpy()}  |A| = {stats['n_alpha']}  cells = {stats['n_cells']}  "
-        f"step {ms_per_step:.2f} ms  sweep kernel {1e3 * kern_s:.2f} ms")
+    # the dominant kernel: the dense sweep, timed with HIP events on its stream
+    kern_s = float(np.mean([t[0] for t in timings])) * 1e-3
+    gen_ms = float(np.mean([t[1] for t in timings]))
+    alpha_dense = stats["n_alpha"] - stats["n_alpha_general"]
+    per_alpha = ops_per_alpha(stats, ns, nint)
+    ops = alpha_dense * per_alpha
+    log(f"E_PT2 = {e_out.cpu().numpy()}  |A| = {stats['n_alpha']} (general kernel {stats['n_alpha_general']})  "
+        f"cells = {stats['n_cells']}  step {ms_per_step:.2f} ms  dense kernel {1e3 * kern_s:.2f} ms  "
+        f"general kernel {gen_ms:.2f} ms")
 
     # forward + backward throughput
-    extra = {}
+    extra = {"general_kernel_ms": gen_ms, "alpha_general_kernel": stats["n_alpha_general"]}
     if args.bwd_steps > 0:
         gup = torch.ones(ns, dtype=torch.float64, device=dev)
         gc = torch.empty((ns, nd), dtype=torch.float64, device=dev)
@@ -140,10 +150,22 @@ def main():
         extra["fwd_bwd_ms_per_step"] = 1e3 * fb
         log(f"fwd+bwd {1e3 * fb:.2f} ms/step")
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
+        del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
-        ncores = len(os.sched_getaffinity(0))
-        cpu = cpu_baseline(s, E0.cpu().numpy(), max(8, min(ncores, 32)))
+        # the oracle's OpenMP team: OMP_NUM_THREADS if set, else every CPU of the affinity mask;
+        # about 12 generators per thread keep the sample near 15 s of CPU work
+        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        cpu = cpu_baseline(s, E0.cpu().numpy(), 12 * threads)
         log(f"cpu baseline: {cpu}")
 
     out = {
@@ -164,7 +186,8 @@ def main():
                    "n_alpha": stats["n_alpha"], "n_cells": stats["n_cells"]},
         "roofline": {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": ALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": ops / kern_s / ALU_PEAK_OPS, "traffic": None,
-                     "kernel": "sweep_kernel", "kernel_ms": 1e3 * kern_s, "ops_per_launch": ops},
+                     "kernel": "qpfast::fast_kernel", "kernel_ms": 1e3 * kern_s, "ops_per_launch": ops,
+                     "alpha_per_launch": alpha_dense, "ops_per_alpha": per_alpha},
         "cpu_baseline": cpu,
         "extra": extra,
     }

@@ -85,7 +85,8 @@ typedef struct {
     uint64_t overflow;       /* nonzero: candidate buffer overflowed (QP_E_OVERFLOW)*/
     uint64_t n_connections;  /* (alpha, J != generator) pairs with degree <= 2
                                 that contributed a matrix element                  */
-    uint64_t reserved;
+    uint64_t n_alpha_general; /* of n_alpha, those evaluated by the general kernel
+                                (batches the dense kernel hands over)             */
     double   S[QP_MAX_STATES];  /* sum_alpha N^2/(E0-H_aa)^2 = -dE_PT2/dE0 (rPT2) */
     double   min_abs_delta;     /* min over alpha, k of |E0_k - H_alpha,alpha|      */
     double   reserved_d[3];
@@ -181,11 +182,12 @@ int qp_energy(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_
 /*
  * qp_set_timing / qp_last_timing -- diagnostics.  When enabled, every
  * qp_pt2 / qp_pt2_backward call records HIP events on its stream around the
- * sweep kernel (the per-generator batch kernel, the dominant cost).
- * qp_last_timing waits for the last recorded event and writes
- * out_ms[0] = duration of the last sweep kernel, out_ms[1] = duration from the
- * call's first enqueued kernel to its last (ms).  Errors: QP_E_ARG when timing
- * is off or no call has been timed, QP_E_HIP.
+ * two sweep kernels (the per-generator batch kernels, the dominant cost).
+ * qp_last_timing waits for the last recorded event and writes, in ms:
+ * out_ms[0] = the dense sweep kernel, out_ms[1] = the general kernel on the
+ * batches handed over to it, out_ms[2] = the call's first enqueued kernel to
+ * its last.  out_ms must hold 3 doubles.  Errors: QP_E_ARG when timing is off
+ * or no call has been timed, QP_E_HIP.
  */
 int qp_set_timing(qp_ctx *ctx, int enable);
 int qp_last_timing(qp_ctx *ctx, double *out_ms);

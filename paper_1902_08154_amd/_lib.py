@@ -39,7 +39,7 @@ class Stats(ctypes.Structure):
         ("n_candidates", ctypes.c_uint64),
         ("overflow", ctypes.c_uint64),
         ("n_connections", ctypes.c_uint64),
-        ("reserved", ctypes.c_uint64),
+        ("n_alpha_general", ctypes.c_uint64),
         ("S", ctypes.c_double * QP_MAX_STATES),
         ("min_abs_delta", ctypes.c_double),
         ("reserved_d", ctypes.c_double * 3),

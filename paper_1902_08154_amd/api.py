@@ -96,10 +96,10 @@ class Context:
         self._check(self._lib.qp_set_timing(self._h, 1 if enable else 0))
 
     def qp_last_timing(self):
-        """(sweep kernel ms, whole call ms) of the last timed call."""
-        out = (ctypes.c_double * 2)()
+        """(dense sweep kernel ms, general kernel ms, whole call ms) of the last timed call."""
+        out = (ctypes.c_double * 3)()
         self._check(self._lib.qp_last_timing(self._h, out))
-        return float(out[0]), float(out[1])
+        return float(out[0]), float(out[1]), float(out[2])
 
     # ---------------------------------------------------------- conveniences
     def _inputs(self, dets, coefs, E0=None):
@@ -158,7 +158,8 @@ def stats_to_dict(st: torch.Tensor, ns: int) -> dict:
     s = _lib.Stats.from_buffer_copy(raw)
     return dict(n_alpha=int(s.n_alpha), n_cells=int(s.n_cells), fingerprint=int(s.fingerprint),
                 n_coarse=int(s.n_coarse), n_candidates=int(s.n_candidates), overflow=int(s.overflow),
-                n_connections=int(s.n_connections), S=[float(s.S[k]) for k in range(ns)],
+                n_connections=int(s.n_connections), n_alpha_general=int(s.n_alpha_general),
+                S=[float(s.S[k]) for k in range(ns)],
                 min_abs_delta=float(s.min_abs_delta))
 
 

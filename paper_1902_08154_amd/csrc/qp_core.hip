@@ -97,17 +97,14 @@ __device__ __forceinline__ int det_cmp_dev(const uint64_t *a, const uint64_t *b)
 }
 
 struct Scalars {
-    unsigned int item_counter;
+    unsigned int pad0;
     int tau_bin;
     unsigned long long cand_count;
     unsigned long long overflow;
     unsigned long long min_delta_bits;
-    unsigned long long conn_total;
     unsigned long long coarse_total;
     unsigned long long comp_count;
-    unsigned long long def_count;       // batches deferred to the general kernel
-    unsigned int item_counter2;         // general kernel's item counter
-    unsigned int pad2;
+    long long def_count;                // batches deferred to the general kernel
     int bad_bits;     // a bit set at >= n_orb
     int bad_elec;     // electron counts differ from det 0
     int dup;          // duplicate determinant
@@ -419,24 +416,71 @@ __global__ void make_coff(const int64_t *offs, int64_t n_det, int nchunk, const 
 // per generator: sum its items in order; eps_gen in the caller's index
 // Deferred partials of one generator, in increasing batch order (its list is
 // built by atomic pushes, so it is re-ordered here for a fixed summation order).
+// Batches the dense kernel handed to the general kernel, listed in (rank,
+// batch) order: generator g owns entries [off[g], off[g] + cnt[g]).
 struct DefParts {
-    const int *head, *next;
-    const uint32_t *b;
+    const int64_t *off;
+    const int32_t *cnt;
     const double *eps, *S, *dc;
-    const uint32_t *cnt;
+    const uint32_t *alpha, *conn;
     const uint64_t *fp;
 };
 
+// deferred batches per generator rank: popcount of its bitmap words
+__global__ void def_count(const uint32_t *bits, int64_t n_det, int nbw, int32_t *cnt)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n_det) return;
+    int c = 0;
+    for (int w = 0; w < nbw; ++w) c += __popc(bits[g * nbw + w]);
+    cnt[g] = c;
+}
+
+// list them at the scanned offsets, batches in increasing order
+__global__ void def_fill(const uint32_t *bits, int64_t n_det, int nbw, const int64_t *off, uint32_t *dg,
+                         uint32_t *db)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n_det) return;
+    int64_t o = off[g];
+    for (int w = 0; w < nbw; ++w) {
+        uint32_t x = bits[g * nbw + w];
+        while (x) {
+            dg[o] = (uint32_t)g;
+            db[o] = (uint32_t)(32 * w + __ffs(x) - 1);
+            ++o;
+            x &= x - 1;
+        }
+    }
+}
+
+// no batches at all (no electrons): every partial is zero
+__global__ void reduce_empty(int64_t n_det, int ns, const int32_t *perm, double *eps_g, double *S_g, uint64_t *cnt_g,
+                             uint64_t *fp_g, uint64_t *conn_g, uint64_t *defa_g, double *eps_gen)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= n_det) return;
+    for (int k = 0; k < ns; ++k) {
+        eps_g[g * ns + k] = 0.0;
+        S_g[g * ns + k] = 0.0;
+        if (eps_gen) eps_gen[k * n_det + perm[g]] = 0.0;
+    }
+    cnt_g[g] = 0; fp_g[g] = 0; conn_g[g] = 0; defa_g[g] = 0;
+}
+
+// per generator, in a fixed order: its dense-kernel items, then its deferred
+// batches in batch order
 __global__ void reduce_items(const double *eps_item, const double *S_item, const uint32_t *cnt_item,
-                             const uint64_t *fp_item, const double *dc_item, int64_t n_det, int nq, int ns,
-                             const int32_t *perm, double *eps_g, double *S_g, uint64_t *cnt_g, uint64_t *fp_g,
-                             double *eps_gen, double *dc, DefParts dp)
+                             const uint64_t *fp_item, const uint32_t *conn_item, const double *dc_item,
+                             int64_t n_det, int nq, int ns, const int32_t *perm, double *eps_g, double *S_g,
+                             uint64_t *cnt_g, uint64_t *fp_g, uint64_t *conn_g, uint64_t *defa_g, double *eps_gen,
+                             double *dc, DefParts dp)
 {
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= n_det) return;
     const int det = perm[g];
     double e[QPD_MAX_STATES] = {0, 0, 0, 0}, s[QPD_MAX_STATES] = {0, 0, 0, 0}, d[QPD_MAX_STATES] = {0, 0, 0, 0};
-    uint64_t c = 0, f = 0;
+    uint64_t c = 0, f = 0, cn = 0, cd = 0;
     for (int i = 0; i < nq; ++i) {
         const int64_t sl = g * nq + i;
         for (int k = 0; k < ns; ++k) {
@@ -445,61 +489,61 @@ __global__ void reduce_items(const double *eps_item, const double *S_item, const
             if (dc_item) d[k] += dc_item[sl * ns + k];
         }
         c += cnt_item[sl];
+        cn += conn_item[sl];
         if (fp_item) f += fp_item[sl];
     }
-    if (dp.head) {
-        int64_t last = -1;
-        for (;;) {
-            int best = -1;
-            int64_t bb = INT64_MAX;
-            for (int x = dp.head[g]; x >= 0; x = dp.next[x]) {
-                const int64_t bx = dp.b[x];
-                if (bx > last && bx < bb) { bb = bx; best = x; }
-            }
-            if (best < 0) break;
-            for (int k = 0; k < ns; ++k) {
-                e[k] += dp.eps[(int64_t)best * ns + k];
-                s[k] += dp.S[(int64_t)best * ns + k];
-                if (dc_item && dp.dc) d[k] += dp.dc[(int64_t)best * ns + k];
-            }
-            c += dp.cnt[best];
-            if (fp_item && dp.fp) f += dp.fp[best];
-            last = bb;
+    const int64_t x0 = dp.off[g], x1 = x0 + dp.cnt[g];
+    for (int64_t x = x0; x < x1; ++x) {
+        for (int k = 0; k < ns; ++k) {
+            e[k] += dp.eps[x * ns + k];
+            s[k] += dp.S[x * ns + k];
+            if (dc_item && dp.dc) d[k] += dp.dc[x * ns + k];
         }
+        cd += dp.alpha[x];
+        cn += dp.conn[x];
+        if (fp_item && dp.fp) f += dp.fp[x];
     }
+    c += cd;
     for (int k = 0; k < ns; ++k) {
         eps_g[g * ns + k] = e[k];
         S_g[g * ns + k] = s[k];
         if (eps_gen) eps_gen[k * n_det + det] = e[k];
         if (dc_item && dc) dc[k * n_det + det] += d[k];
     }
+    conn_g[g] = cn;
+    defa_g[g] = cd;
     cnt_g[g] = c;
     fp_g[g] = f;
 }
 
 // single block, fixed summation order
 __global__ void reduce_total(const double *eps_g, const double *S_g, const uint64_t *cnt_g, const uint64_t *fp_g,
-                             int64_t n_det, int ns, double *e_pt2, qp_pt2_stats *stats, const Scalars *sc,
-                             int64_t n_cells, const double *gup, double *grad_E0)
+                             const uint64_t *conn_g, const uint64_t *defa_g, int64_t n_det, int ns, double *e_pt2,
+                             qp_pt2_stats *stats, const Scalars *sc, int64_t n_cells, const double *gup,
+                             double *grad_E0)
 {
     __shared__ double se[256][QPD_MAX_STATES], ss[256][QPD_MAX_STATES];
-    __shared__ uint64_t sc_[256], sf[256];
+    __shared__ uint64_t sc_[256], sf[256], sn[256], sd[256];
     const int t = threadIdx.x;
     double e[QPD_MAX_STATES] = {0, 0, 0, 0}, s[QPD_MAX_STATES] = {0, 0, 0, 0};
-    uint64_t c = 0, f = 0;
+    uint64_t c = 0, f = 0, cn = 0, cd = 0;
     for (int64_t g = t; g < n_det; g += 256) {
         for (int k = 0; k < ns; ++k) { e[k] += eps_g[g * ns + k]; s[k] += S_g[g * ns + k]; }
         c += cnt_g[g];
         f += fp_g[g];
+        cn += conn_g[g];
+        cd += defa_g[g];
     }
     for (int k = 0; k < QPD_MAX_STATES; ++k) { se[t][k] = e[k]; ss[t][k] = s[k]; }
-    sc_[t] = c; sf[t] = f;
+    sc_[t] = c; sf[t] = f; sn[t] = cn; sd[t] = cd;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if (t < st) {
             for (int k = 0; k < QPD_MAX_STATES; ++k) { se[t][k] += se[t + st][k]; ss[t][k] += ss[t + st][k]; }
             sc_[t] += sc_[t + st];
             sf[t] += sf[t + st];
+            sn[t] += sn[t + st];
+            sd[t] += sd[t + st];
         }
         __syncthreads();
     }
@@ -515,8 +559,8 @@ __global__ void reduce_total(const double *eps_g, const double *S_g, const uint6
             stats->n_coarse = sc->coarse_total;
             stats->n_candidates = sc->cand_count;
             stats->overflow = sc->overflow;
-            stats->n_connections = sc->conn_total;
-            stats->reserved = 0;
+            stats->n_connections = sn[0];
+            stats->n_alpha_general = sd[0];
             for (int k = 0; k < QPD_MAX_STATES; ++k) stats->S[k] = k < ns ? ss[0][k] : 0.0;
             stats->min_abs_delta = __longlong_as_double((long long)sc->min_delta_bits);
             for (int k = 0; k < 3; ++k) stats->reserved_d[k] = 0.0;
@@ -640,7 +684,8 @@ struct qp_ctx {
     uint64_t *host_det0 = nullptr;
     bool timing = false;
     bool timed = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // call start, sweep start, sweep end, call end
+    // call start, dense sweep start, general kernel start, sweep end, call end
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -648,7 +693,8 @@ namespace {
 enum BufId {
     B_W, B_IDX, B_RANK, B_F, B_HII, B_COUNTS, B_OFFS, B_BSUM, B_COFF, B_CENT, B_EPSI, B_SI, B_CNTI, B_FPI,
     B_DCI, B_EPSG, B_SG, B_CNTG, B_FPG, B_SC, B_HIST, B_CAND, B_COMP, B_SKEY, B_SBITS, B_SIDX, B_MAXC2,
-    B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFN, B_DEFH, B_DEFE, B_DEFS, B_DEFC, B_DEFF, B_DEFD, B_COUNT
+    B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFN, B_DEFE, B_DEFS, B_DEFC, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
+    B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_COUNT
 };
 
 int fail(qp_ctx *c, int code, const std::string &msg)
@@ -906,7 +952,22 @@ void fast_dispatch(const SweepArgs &a, int grid, bool bwd, hipStream_t st)
     }
 }
 
-constexpr int Q_PER_GEN = 4;
+// work items per generator: the forward sweep splits each generator's batches
+// over 16 items (batch b goes to item b mod 16) so that the persistent grid
+// stays balanced; the adjoint keeps 4, because each item ends with atomic
+// updates of the n x n one-electron gradient.  Items are dealt round-robin,
+// without a shared counter.
+constexpr int Q_FORWARD = 16;
+constexpr int Q_ADJOINT = 4;
+constexpr int64_t MAX_ITEMS = int64_t(1) << 25;
+
+int items_per_generator(int64_t n_det, int nb, bool bwd)
+{
+    int q = bwd ? Q_ADJOINT : Q_FORWARD;
+    if (nb > 0 && q > nb) q = nb;
+    while (q > 1 && n_det * q > MAX_ITEMS) q /= 2;
+    return std::max(q, 1);
+}
 
 int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int ns, const double *E0,
               int64_t n_select, int flags, bool bwd, const double *gup, double *e_pt2, uint64_t *sel_dets,
@@ -921,7 +982,7 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     int rc = prepare(c, nint, dets, coefs, n_det, ns, flags, st, P);
     if (rc != QP_OK) return rc;
     const int nel = P.nel;
-    const int Q = Q_PER_GEN;
+    const int Q = items_per_generator(n_det, nel + nel * (nel - 1) / 2, bwd);
     const int64_t n_items = n_det * Q;
     double *eps_item = (double *)scratch(c, B_EPSI, sizeof(double) * std::max<int64_t>(1, n_items) * ns);
     double *S_item = (double *)scratch(c, B_SI, sizeof(double) * std::max<int64_t>(1, n_items) * ns);
@@ -939,20 +1000,21 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     const int fgrid = fast_grid(c, nint, ns, bwd, n - std::min(P.nup, P.ndn), rscap, cscap);
     const int ggrid = sweep_grid(c, nint, ns, bwd);
     const int grid = std::max(fgrid, ggrid);
-    // batches the fast kernel hands to the general kernel
-    const int64_t def_cap = std::max<int64_t>(1 << 16, 16 * n_det);
-    uint32_t *def_g = (uint32_t *)scratch(c, B_DEFG, sizeof(uint32_t) * def_cap);
-    uint32_t *def_b = (uint32_t *)scratch(c, B_DEFB, sizeof(uint32_t) * def_cap);
-    int *def_next = (int *)scratch(c, B_DEFN, sizeof(int) * def_cap);
-    int *def_head = (int *)scratch(c, B_DEFH, sizeof(int) * n_det);
-    double *def_eps = (double *)scratch(c, B_DEFE, sizeof(double) * def_cap * ns);
-    double *def_S = (double *)scratch(c, B_DEFS, sizeof(double) * def_cap * ns);
-    uint32_t *def_cnt = (uint32_t *)scratch(c, B_DEFC, sizeof(uint32_t) * def_cap);
-    uint64_t *def_fp = (uint64_t *)scratch(c, B_DEFF, sizeof(uint64_t) * def_cap);
-    double *def_dc = bwd ? (double *)scratch(c, B_DEFD, sizeof(double) * def_cap * ns) : nullptr;
-    if (!def_g || !def_b || !def_next || !def_head || !def_eps || !def_S || !def_cnt || !def_fp || (bwd && !def_dc))
+    // batches the dense kernel hands to the general kernel: one bit per
+    // (generator rank, batch), then a list in (rank, batch) order
+    const int nb = nel + nel * (nel - 1) / 2;
+    const int nbw = std::max(1, (nb + 31) / 32);
+    uint32_t *conn_item = (uint32_t *)scratch(c, B_CONNI, sizeof(uint32_t) * std::max<int64_t>(1, n_items));
+    uint64_t *conn_g = (uint64_t *)scratch(c, B_CONNG, sizeof(uint64_t) * n_det);
+    uint64_t *defa_g = (uint64_t *)scratch(c, B_DEFAG, sizeof(uint64_t) * n_det);
+    uint32_t *def_bits = (uint32_t *)scratch(c, B_DEFBITS, sizeof(uint32_t) * n_det * nbw);
+    int32_t *def_cnt_g = (int32_t *)scratch(c, B_DEFCG, sizeof(int32_t) * n_det);
+    int64_t *def_off = (int64_t *)scratch(c, B_DEFOFF, sizeof(int64_t) * n_det);
+    const int64_t nsb = (n_det + 1023) / 1024;
+    int64_t *def_bsum = (int64_t *)scratch(c, B_DEFBS, sizeof(int64_t) * std::max<int64_t>(1, nsb));
+    if (!conn_item || !conn_g || !defa_g || !def_bits || !def_cnt_g || !def_off || !def_bsum)
         return fail(c, QP_E_OOM, "device allocation failed (deferred batches)");
-    HIPCHK(c, hipMemsetAsync(def_head, 0xFF, sizeof(int) * n_det, st));
+    HIPCHK(c, hipMemsetAsync(def_bits, 0, sizeof(uint32_t) * n_det * nbw, st));
     int64_t cand_cap = 0;
     Cand *cand = nullptr;
     if (n_select > 0) {
@@ -978,10 +1040,8 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     a.perm = P.perm; a.F = P.F; a.HII = P.HII; a.coff = P.coff; a.cent = P.cent;
     a.n_items = n_items;
     a.q_per_gen = Q;
-    a.item_counter = &P.sc->item_counter;
     a.flags = ((flags & QP_FLAG_FINGERPRINT) ? 1 : 0) | (bwd ? 2 : 0);
-    a.eps_item = eps_item; a.S_item = S_item; a.cnt_item = cnt_item; a.fp_item = fp_item;
-    a.conn_total = (uint64_t *)&P.sc->conn_total;
+    a.eps_item = eps_item; a.S_item = S_item; a.cnt_item = cnt_item; a.fp_item = fp_item; a.conn_item = conn_item;
     a.min_delta_bits = &P.sc->min_delta_bits;
     a.n_select = n_select;
     for (int k = 0; k < QPD_MAX_STATES; ++k) {
@@ -992,64 +1052,78 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     a.tau_bin = &P.sc->tau_bin; a.overflow = &P.sc->overflow;
     a.gup = gup; a.dc_item = dc_item; a.dc = grad_coefs; a.dh = grad_h;
     a.rscap = rscap; a.cscap = cscap;
+    a.def_bits = def_bits; a.nbw = nbw;
     a.def_mode = 0;
-    a.def_g = def_g; a.def_b = def_b; a.def_next = def_next; a.def_head = def_head;
-    a.def_count = &P.sc->def_count; a.def_cap = def_cap;
-    // the general kernel on the deferred batches: its own counter and slots
-    SweepArgs d = a;
-    d.def_mode = 1;
-    d.item_counter = &P.sc->item_counter2;
-    d.eps_item = def_eps; d.S_item = def_S; d.cnt_item = def_cnt; d.fp_item = def_fp; d.dc_item = def_dc;
 
-    bool deferred_used = true;
+    int64_t n_def = 0;
+    double *def_eps = nullptr, *def_S = nullptr, *def_dc = nullptr;
+    uint32_t *def_alpha = nullptr, *def_conn = nullptr;
+    uint64_t *def_fp = nullptr;
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], st));
     if (n_items > 0 && nel > 0) {
         switch (nint) {
-        case 1: fast_dispatch<1>(a, fgrid, bwd, st); sweep_dispatch<1>(d, ggrid, bwd, st); break;
-        case 2: fast_dispatch<2>(a, fgrid, bwd, st); sweep_dispatch<2>(d, ggrid, bwd, st); break;
-        case 3: fast_dispatch<3>(a, fgrid, bwd, st); sweep_dispatch<3>(d, ggrid, bwd, st); break;
-        default: fast_dispatch<4>(a, fgrid, bwd, st); sweep_dispatch<4>(d, ggrid, bwd, st); break;
+        case 1: fast_dispatch<1>(a, fgrid, bwd, st); break;
+        case 2: fast_dispatch<2>(a, fgrid, bwd, st); break;
+        case 3: fast_dispatch<3>(a, fgrid, bwd, st); break;
+        default: fast_dispatch<4>(a, fgrid, bwd, st); break;
         }
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(c->host_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(def_count, dim3(grid_for(n_det)), dim3(256), 0, st, def_bits, n_det, nbw, def_cnt_g);
+        hipLaunchKernelGGL(scan_block, dim3((unsigned)nsb), dim3(256), 0, st, def_cnt_g, n_det, def_off, def_bsum);
+        hipLaunchKernelGGL(scan_bsum, dim3(1), dim3(1), 0, st, def_bsum, nsb, (int64_t *)&P.sc->def_count);
+        hipLaunchKernelGGL(scan_add, dim3(grid_for(n_det, 256, 1 << 30)), dim3(256), 0, st, def_off, n_det, def_bsum);
+        HIPCHK(c, hipMemcpyAsync(&n_def, &P.sc->def_count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        if (c->host_sc->overflow & 2ull) {
-            // deferred list overflowed: redo everything with the general kernel
-            deferred_used = false;
-            HIPCHK(c, hipMemsetAsync(&P.sc->item_counter, 0, sizeof(unsigned int), st));
-            HIPCHK(c, hipMemsetAsync(&P.sc->cand_count, 0, sizeof(unsigned long long), st));
-            HIPCHK(c, hipMemsetAsync(&P.sc->overflow, 0, sizeof(unsigned long long), st));
-            HIPCHK(c, hipMemsetAsync(&P.sc->tau_bin, 0, sizeof(int), st));
-            HIPCHK(c, hipMemsetAsync(&P.sc->conn_total, 0, sizeof(unsigned long long), st));
-            HIPCHK(c, hipMemsetAsync(hist, 0, sizeof(unsigned int) * QP_HIST_BINS, st));
-            if (bwd) {
-                if (grad_coefs) HIPCHK(c, hipMemsetAsync(grad_coefs, 0, sizeof(double) * ns * n_det, st));
-                if (grad_h) HIPCHK(c, hipMemsetAsync(grad_h, 0, sizeof(double) * n * n, st));
-            }
+        HIPCHK(c, hipGetLastError());
+        const int64_t m = std::max<int64_t>(1, n_def);
+        uint32_t *def_g = (uint32_t *)scratch(c, B_DEFG, sizeof(uint32_t) * m);
+        uint32_t *def_b = (uint32_t *)scratch(c, B_DEFB, sizeof(uint32_t) * m);
+        def_eps = (double *)scratch(c, B_DEFE, sizeof(double) * m * ns);
+        def_S = (double *)scratch(c, B_DEFS, sizeof(double) * m * ns);
+        def_alpha = (uint32_t *)scratch(c, B_DEFC, sizeof(uint32_t) * m);
+        def_conn = (uint32_t *)scratch(c, B_DEFN, sizeof(uint32_t) * m);
+        def_fp = (uint64_t *)scratch(c, B_DEFF, sizeof(uint64_t) * m);
+        def_dc = bwd ? (double *)scratch(c, B_DEFD, sizeof(double) * m * ns) : nullptr;
+        if (!def_g || !def_b || !def_eps || !def_S || !def_alpha || !def_conn || !def_fp || (bwd && !def_dc))
+            return fail(c, QP_E_OOM, "device allocation failed (deferred batches)");
+        if (n_def > 0) {
+            hipLaunchKernelGGL(def_fill, dim3(grid_for(n_det)), dim3(256), 0, st, def_bits, n_det, nbw, def_off,
+                               def_g, def_b);
+            // the general kernel on the listed batches: its own slots
+            SweepArgs d = a;
+            d.def_mode = 1;
+            d.def_g = def_g; d.def_b = def_b; d.def_n = (const int64_t *)&P.sc->def_count;
+            d.eps_item = def_eps; d.S_item = def_S; d.cnt_item = def_alpha; d.fp_item = def_fp;
+            d.conn_item = def_conn; d.dc_item = def_dc;
+            const int dgrid = (int)std::min<int64_t>(ggrid, n_def);
             switch (nint) {
-            case 1: sweep_dispatch<1>(a, ggrid, bwd, st); break;
-            case 2: sweep_dispatch<2>(a, ggrid, bwd, st); break;
-            case 3: sweep_dispatch<3>(a, ggrid, bwd, st); break;
-            default: sweep_dispatch<4>(a, ggrid, bwd, st); break;
+            case 1: sweep_dispatch<1>(d, dgrid, bwd, st); break;
+            case 2: sweep_dispatch<2>(d, dgrid, bwd, st); break;
+            case 3: sweep_dispatch<3>(d, dgrid, bwd, st); break;
+            default: sweep_dispatch<4>(d, dgrid, bwd, st); break;
             }
             HIPCHK(c, hipGetLastError());
         }
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], st));
     } else {
-        HIPCHK(c, hipMemsetAsync(eps_item, 0, sizeof(double) * ns, st));
-        deferred_used = false;
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], st));
     }
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
     DefParts dp;
     memset(&dp, 0, sizeof(dp));
-    if (deferred_used) {
-        dp.head = def_head; dp.next = def_next; dp.b = def_b; dp.eps = def_eps; dp.S = def_S; dp.dc = def_dc;
-        dp.cnt = def_cnt; dp.fp = def_fp;
-    }
-    hipLaunchKernelGGL(reduce_items, dim3(grid_for(n_det)), dim3(256), 0, st, eps_item, S_item, cnt_item,
-                       (flags & QP_FLAG_FINGERPRINT) ? fp_item : (uint64_t *)nullptr, dc_item, n_det, Q, ns,
-                       P.perm, eps_g, S_g, cnt_g, fp_g, bwd ? nullptr : eps_gen, bwd ? grad_coefs : nullptr, dp);
+    dp.off = def_off; dp.cnt = def_cnt_g; dp.eps = def_eps; dp.S = def_S; dp.dc = def_dc;
+    dp.alpha = def_alpha; dp.conn = def_conn; dp.fp = def_fp;
+    if (n_items > 0 && nel > 0)
+        hipLaunchKernelGGL(reduce_items, dim3(grid_for(n_det)), dim3(256), 0, st, eps_item, S_item, cnt_item,
+                           (flags & QP_FLAG_FINGERPRINT) ? fp_item : (const uint64_t *)nullptr, conn_item, dc_item,
+                           n_det, Q, ns, P.perm, eps_g, S_g, cnt_g, fp_g, conn_g, defa_g, bwd ? nullptr : eps_gen,
+                           bwd ? grad_coefs : nullptr, dp);
+    else
+        hipLaunchKernelGGL(reduce_empty, dim3(grid_for(n_det)), dim3(256), 0, st, n_det, ns, P.perm, eps_g, S_g,
+                           cnt_g, fp_g, conn_g, defa_g, bwd ? nullptr : eps_gen);
     const int64_t n_cells = n_det * cells_per_generator(n, P.nup, P.ndn);
-    hipLaunchKernelGGL(reduce_total, dim3(1), dim3(256), 0, st, eps_g, S_g, cnt_g, fp_g, n_det, ns,
+    hipLaunchKernelGGL(reduce_total, dim3(1), dim3(256), 0, st, eps_g, S_g, cnt_g, fp_g, conn_g, defa_g, n_det, ns,
                        bwd ? nullptr : e_pt2, stats, P.sc, n_cells, gup, bwd ? grad_E0 : nullptr);
     HIPCHK(c, hipGetLastError());
 
@@ -1085,7 +1159,7 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
         HIPCHK(c, hipGetLastError());
     }
     if (c->timing) {
-        HIPCHK(c, hipEventRecord(c->ev[3], st));
+        HIPCHK(c, hipEventRecord(c->ev[4], st));
         c->timed = true;
     }
     return QP_OK;
@@ -1261,12 +1335,14 @@ int qp_last_timing(qp_ctx *c, double *out_ms)
 {
     if (!c || !out_ms) return QP_E_ARG;
     if (!c->timing || !c->timed) return fail(c, QP_E_ARG, "no timed call");
-    HIPCHK(c, hipEventSynchronize(c->ev[3]));
-    float a = 0.f, b = 0.f;
+    HIPCHK(c, hipEventSynchronize(c->ev[4]));
+    float a = 0.f, b = 0.f, t = 0.f;
     HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[2]));
-    HIPCHK(c, hipEventElapsedTime(&b, c->ev[0], c->ev[3]));
+    HIPCHK(c, hipEventElapsedTime(&b, c->ev[2], c->ev[3]));
+    HIPCHK(c, hipEventElapsedTime(&t, c->ev[0], c->ev[4]));
     out_ms[0] = a;
     out_ms[1] = b;
+    out_ms[2] = t;
     return QP_OK;
 }
 

@@ -283,24 +283,24 @@ struct SweepArgs {
     const double *HII;        // [rank]
     const int64_t *coff;      // [n_det+1], by rank
     const CoarseEnt *cent;
-    int64_t n_items;
+    int64_t n_items;          // dense kernel: n_det * q_per_gen; general kernel: see def_n
     int q_per_gen;            // work items per generator
-    unsigned int *item_counter;
-    // fast kernel: buffer capacities and the deferred-batch list
+    // dense kernel: buffer capacities; batches it hands over are marked in
+    // def_bits (nbw words per generator rank, bit b = batch b)
     int rscap, cscap;
-    int def_mode;             // general kernel: items are the deferred batches
-    uint32_t *def_g, *def_b;  // deferred (generator rank, batch)
-    int *def_next;            // per-generator linked list of deferred batches
-    int *def_head;            // [n_det], -1 terminated
-    unsigned long long *def_count;
-    int64_t def_cap;
+    uint32_t *def_bits;
+    int nbw;
+    // general kernel: its items are the marked batches, listed in (rank, batch) order
+    int def_mode;
+    const uint32_t *def_g, *def_b;
+    const int64_t *def_n;     // device: number of listed batches
     int flags;                // bit0 fingerprint, bit1 backward
     // per-item partials (deterministic reduction later)
     double *eps_item;         // [n_items][ns]
     double *S_item;           // [n_items][ns]
     uint32_t *cnt_item;       // [n_items]
     uint64_t *fp_item;        // [n_items]
-    uint64_t *conn_total;     // atomic
+    uint32_t *conn_item;      // [n_items]
     unsigned long long *min_delta_bits;
     // selection
     int64_t n_select;

@@ -212,11 +212,9 @@ void fast_kernel(SweepArgs a)
         gup[k] = BWD ? a.gup[k] : 0.0;
     }
 
-    for (;;) {
-        int it0 = 0;
-        if (lane == 0) it0 = (int)atomicAdd(a.item_counter, 1u);
-        const int64_t item = (int64_t)(unsigned)__builtin_amdgcn_readlane(it0, 0);
-        if (item >= a.n_items) break;
+    // items are dealt round-robin over the persistent grid: a shared counter
+    // would cost one contended device-scope atomic per item
+    for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
         const int q = (int)(item / a.n_det);
         const int64_t g = item - (int64_t)q * a.n_det;
         const int64_t slot = g * Q + q;
@@ -428,16 +426,7 @@ void fast_kernel(SweepArgs a)
             }
             if (slow) {
                 // the general kernel takes this batch
-                if (lane == 0) {
-                    const unsigned long long d = atomicAdd(a.def_count, 1ull);
-                    if ((int64_t)d < a.def_cap) {
-                        a.def_g[d] = (uint32_t)g;
-                        a.def_b[d] = (uint32_t)b;
-                        a.def_next[d] = atomicExch(&a.def_head[g], (int)d);
-                    } else {
-                        atomicOr(a.overflow, 2ull);
-                    }
-                }
+                if (lane == 0) atomicOr(&a.def_bits[g * a.nbw + (b >> 5)], 1u << (b & 31));
                 __syncthreads();
                 continue;
             }
@@ -683,16 +672,19 @@ void fast_kernel(SweepArgs a)
                     const int pcol = ce.info & 255;
                     double colacc = 0.0;
                     if (BWD || lok) {
-                        // integrals of the next row are loaded one row ahead
+                        // integrals of the next row are loaded one row ahead; each
+                        // generator starts at its own row so that waves sharing a
+                        // block do not all read the same lines at once
                         const unsigned uc = (unsigned)pcol;
-                        uint32_t rinfo = rfl(sRT[0].info);
+                        int r = (int)(g % nr);
+                        uint32_t rinfo = rfl(sRT[r].info);
                         double xn = (blk + (rinfo & 255) * n)[uc];
                         double xjn = (Jm + (rinfo & 255) * n)[uc];
-                        for (int r = 0; r < nr; ++r) {
+                        for (int t = 0; t < nr; ++t, r = r + 1 == nr ? 0 : r + 1) {
                             const double x = xn, xj = xjn;
                             const double Gr = rfl(sRT[r].G);
                             const uint32_t ri = rinfo;
-                            const int rn = r + 1 < nr ? r + 1 : r;
+                            const int rn = r + 1 == nr ? 0 : r + 1;
                             rinfo = rfl(sRT[rn].info);
                             xn = (blk + (rinfo & 255) * n)[uc];
                             xjn = (Jm + (rinfo & 255) * n)[uc];
@@ -750,7 +742,9 @@ void fast_kernel(SweepArgs a)
                     if (BWD || lok) {
                         // folded rows: row r holds cells (l, r) for l < r and
                         // (l - r, nr - r) for l >= r, so every row has nr cells
-                        for (int r = 1; r <= nr / 2; ++r) {
+                        const int nfr = nr / 2;
+                        int r = nfr > 0 ? 1 + (int)(g % nfr) : 1;
+                        for (int t = 0; t < nfr; ++t, r = r == nfr ? 1 : r + 1) {
                             const bool validB = nr - r > r;
                             const uint32_t ia = rfl(sRT[r].info), ib = rfl(sRT[nr - r].info);
                             const double DA = D0 + rfl(sRT[r].G), DB = D0 + rfl(sRT[nr - r].G);
@@ -938,8 +932,11 @@ void fast_kernel(SweepArgs a)
             }
             a.cnt_item[slot] = (uint32_t)cc;
             if (a.fp_item) a.fp_item[slot] = ff;
-            if (cn) atomicAdd((unsigned long long *)a.conn_total, (unsigned long long)cn);
-            atomicMin(a.min_delta_bits, (unsigned long long)__double_as_longlong(mind));
+            a.conn_item[slot] = (uint32_t)cn;
+            // non-negative doubles order like their bit patterns; most items
+            // cannot lower the minimum, so read before the atomic
+            const unsigned long long mb = (unsigned long long)__double_as_longlong(mind);
+            if (mb < __atomic_load_n(a.min_delta_bits, __ATOMIC_RELAXED)) atomicMin(a.min_delta_bits, mb);
         }
         if (BWD && a.dh) {
             __syncthreads();

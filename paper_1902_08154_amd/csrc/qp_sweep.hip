@@ -66,7 +66,6 @@ __device__ __forceinline__ double fast_rcp(double d)
     return d == 0.0 ? copysign(__builtin_inf(), d) : r;
 }
 
-__device__ __forceinline__ int rdlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 __device__ __forceinline__ void tri_decode(int c, int &i1, int &i2)
 {
@@ -160,24 +159,18 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs a)
 #pragma unroll
     for (int k = 0; k < NS; ++k) { E0[k] = a.E0[k]; gup[k] = BWD ? a.gup[k] : 0.0; }
 
-    const int64_t n_def = a.def_mode ? (int64_t)(*a.def_count < (unsigned long long)a.def_cap ? *a.def_count
-                                                                                            : (unsigned long long)a.def_cap)
-                                     : 0;
-    for (;;) {
-        int item0 = 0;
-        if (lane == 0) item0 = (int)atomicAdd(a.item_counter, 1u);
-        const int64_t item = (int64_t)(unsigned)rdlane(item0, 0);
+    // items are dealt round-robin over the persistent grid (no shared counter)
+    const int64_t n_work = a.def_mode ? *a.def_n : a.n_items;
+    for (int64_t item = blockIdx.x; item < n_work; item += gridDim.x) {
         int q, bstride;
         int64_t g, slot;
         if (a.def_mode) {
-            // one deferred batch per item; partials go to the item's own slot
-            if (item >= n_def) break;
+            // one listed batch per item; partials go to the item's own slot
             g = a.def_g[item];
             q = (int)a.def_b[item];
             bstride = nb;
             slot = item;
         } else {
-            if (item >= a.n_items) break;
             q = (int)(item / a.n_det);
             g = item - (int64_t)q * a.n_det;
             bstride = Q;
@@ -829,8 +822,11 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs a)
             }
             a.cnt_item[slot] = (uint32_t)cc;
             if (a.fp_item) a.fp_item[slot] = ff;
-            if (cn) atomicAdd((unsigned long long *)a.conn_total, (unsigned long long)cn);
-            atomicMin(a.min_delta_bits, (unsigned long long)__double_as_longlong(mind));
+            a.conn_item[slot] = (uint32_t)cn;
+            // non-negative doubles order like their bit patterns; most items
+            // cannot lower the minimum, so read before the atomic
+            const unsigned long long mb = (unsigned long long)__double_as_longlong(mind);
+            if (mb < __atomic_load_n(a.min_delta_bits, __ATOMIC_RELAXED)) atomicMin(a.min_delta_bits, mb);
         }
         if (BWD && a.dh) {
             __syncthreads();
