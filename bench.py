@@ -32,6 +32,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic of one dense-kernel launch, from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE) scaled by the same counters on a 1 GiB device copy.  Valid only for the kernel
+# sources it was measured on (SHA-256 of DENSE_SOURCES); reported as null otherwise.
+DENSE_SOURCES = ["qp_dev.h", "qp_fast_caps.h", "qp_fast_impl.h", "qp_fast_fwd.hip"]
+MEASURED_TRAFFIC = {
+    "c2_n64_10a10b_1e4det_top1000": {
+        "sources_sha256": "af2c51c9eed8cec8f31d3bfaae531c4489e0c945a14693ffe2b27defdd9b21ce",
+        "bytes": 42841786898 + 45178752,
+    },
+}
+
+
+def dense_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in DENSE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1902_08154_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def ops_per_alpha(stats, ns, nint):
     """Method-intrinsic lane operations per external determinant: the ban test
     (3), the per-state FP64 work (15: the element's phase and scaling, the
@@ -168,6 +189,9 @@ def main():
         cpu = cpu_baseline(s, E0.cpu().numpy(), 12 * threads)
         log(f"cpu baseline: {cpu}")
 
+    mt = MEASURED_TRAFFIC.get(s.name)
+    traffic = mt["bytes"] if mt and mt["sources_sha256"] == dense_sources_sha256() else None
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -185,7 +209,7 @@ def main():
                    "n_det": s.n_det, "n_states": ns, "n_select": nsel, "seed": s.seed,
                    "n_alpha": stats["n_alpha"], "n_cells": stats["n_cells"]},
         "roofline": {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": ops / kern_s / ALU_PEAK_OPS, "traffic": None,
+                     "unit": "Tops/s", "frac": ops / kern_s / ALU_PEAK_OPS, "traffic": traffic,
                      "kernel": "qpfast::fast_kernel", "kernel_ms": 1e3 * kern_s, "ops_per_launch": ops,
                      "alpha_per_launch": alpha_dense, "ops_per_alpha": per_alpha},
         "cpu_baseline": cpu,

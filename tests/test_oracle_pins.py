@@ -8,6 +8,8 @@ exact special cases, finite differences and exact identities.
 import itertools
 import math
 
+import os
+
 import numpy as np
 import pytest
 
@@ -70,21 +72,28 @@ def test_synthetic_eri_symmetry_and_psd():
 
 def test_worked_sign_example():
     """Sec. 'Internal representation of determinants': for i<j<k,
-    a+_j a+_k a+_ibar a+_i |0> reorders to - a+_i a+_j a+_k a+_ibar |0>."""
-    n = 5
-    i, j, k = 0, 2, 4
+    a+_j a+_k a+_ibar a+_i |0> reorders to - a+_i a+_j a+_k a+_ibar |0>
+    (fixture tests/golden/worked_sign_example.json)."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "worked_sign_example.json")) as fh:
+        ex = json.load(fh)
+    n = ex["n_orb"]
+    orb = ex["orbitals"]
+
+    def so(op):
+        return orb[op[0]] + (n if op[1] == "down" else 0)
+
     det, sign = 0, 1
-    # rightmost operator acts first
-    for so in (i, n + i, k, j):
-        s, det = sq._create(det, so)
+    for op in ex["operators_right_to_left"]:      # rightmost operator acts first
+        s, det = sq._create(det, so(op))
         sign *= s
     canonical, csign = 0, 1
-    for so in (n + i, k, j, i):
-        s, canonical = sq._create(canonical, so)
+    for op in ex["canonical_right_to_left"]:
+        s, canonical = sq._create(canonical, so(op))
         csign *= s
     assert det == canonical
     assert csign == 1          # creating right-to-left in canonical order gives +1
-    assert sign == -1
+    assert sign == ex["sign_of_operator_product_relative_to_canonical"]
 
 
 def _phase_counting(bits, h, p):
