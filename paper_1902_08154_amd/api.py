@@ -74,6 +74,16 @@ class Context:
         n = h.shape[0]
         self._check(self._lib.qp_set_integrals(self._h, _ptr(h), _ptr(eri_packed), n, _stream(self.device)))
         self.n_orb = n
+        self._ints_key = None
+
+    def ensure_integrals(self, h: torch.Tensor, eri_packed: torch.Tensor):
+        """qp_set_integrals unless these exact tensors (same storage, same
+        in-place version) were the last ones set."""
+        key = (h.data_ptr(), h._version, tuple(h.shape), eri_packed.data_ptr(), eri_packed._version,
+               eri_packed.numel())
+        if getattr(self, "_ints_key", None) != key:
+            self.qp_set_integrals(h.detach(), eri_packed.detach())
+            self._ints_key = key
 
     def qp_pt2(self, dets, coefs, E0, n_select=0, flags=0, e_pt2=None, sel_dets=None, sel_e=None,
                n_sel=None, stats=None, eps_gen=None):
@@ -151,6 +161,39 @@ class Context:
         out = torch.empty(coefs.shape[0], dtype=torch.float64, device=self.device)
         self.qp_energy(dets, coefs, out)
         return out
+
+
+class PT2Function(torch.autograd.Function):
+    """E_PT2 per state (eqs. e2, PT2) as a differentiable function of the
+    coefficients, E0 and the one-electron integrals h.
+
+    forward runs qp_pt2; backward runs qp_pt2_backward with the upstream
+    gradient, whose kernels recompute every numerator instead of storing them.
+    Gradients are the library's partial derivatives (E0 independent, the alpha
+    set fixed); dE/dh is the symmetric matrix G with dE = sum G_pq dh_pq for a
+    symmetric dh.  The context's integrals are (re)built from (h, eri_packed)
+    when either tensor changed since the last call.  Use through pt2_autograd().
+    """
+
+    @staticmethod
+    def forward(fctx, context, dets, coefs, E0, h, eri_packed):
+        context.ensure_integrals(h, eri_packed)
+        e = context.pt2(dets, coefs, E0)["e_pt2"]
+        fctx.context = context
+        fctx.save_for_backward(dets, coefs, E0)
+        return e
+
+    @staticmethod
+    def backward(fctx, grad_e):
+        dets, coefs, E0 = fctx.saved_tensors
+        want = tuple(name for name, need in zip(("coefs", "E0", "h"), fctx.needs_input_grad[2:5]) if need)
+        gc, gE, gh = fctx.context.pt2_backward(dets, coefs, E0, grad_e, want=want)
+        return None, None, gc, gE, gh, None
+
+
+def pt2_autograd(context, dets, coefs, E0, h, eri_packed):
+    """E_PT2 [n_states], differentiable in coefs, E0 and h (see PT2Function)."""
+    return PT2Function.apply(context, dets, coefs, E0, h, eri_packed)
 
 
 def stats_to_dict(st: torch.Tensor, ns: int) -> dict:

@@ -78,3 +78,34 @@ def test_backward_finite_differences_of_gpu_forward(ctx):
     # Euler identity: sum_J c_J dE/dc_J = 2 E
     e = energy(s.coefs.copy())
     assert abs(float(s.coefs[0] @ gc[0]) - 2 * e) <= 1e-9 * max(1.0, abs(e))
+
+
+def test_autograd_function_matches_oracle(ctx):
+    """PT2Function: torch.autograd through the HIP forward and adjoint sweeps,
+    for a weighted sum of the states' E_PT2, against the oracle's gradients."""
+    import torch
+    from paper_1902_08154_amd.api import pt2_autograd, to_device_dets
+    s = synth.make_system("ag_n24_4a3b", 4242, 24, 4, 3, 40, n_states=2)
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    w = np.array([0.8, -1.3])
+    o = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, grad_up=w)
+    dev = ctx.device
+    dets = to_device_dets(s.dets, dev)
+    coefs = torch.tensor(s.coefs, device=dev, requires_grad=True)
+    E0t = torch.tensor(E0, device=dev, requires_grad=True)
+    h = torch.tensor(s.h, device=dev, requires_grad=True)
+    eri = torch.tensor(s.eri, device=dev)
+    e = pt2_autograd(ctx, dets, coefs, E0t, h, eri)
+    loss = (e * torch.tensor(w, device=dev)).sum()
+    gc, gE, gh = torch.autograd.grad(loss, (coefs, E0t, h))
+    torch.cuda.synchronize()
+    gc, gE, gh = gc.cpu().numpy(), gE.cpu().numpy(), gh.cpu().numpy()
+    assert np.allclose(e.detach().cpu().numpy(), o.e_pt2, rtol=1e-9, atol=0)
+    assert np.abs(gc - o.dc).max() <= G_RTOL * np.abs(o.dc).max()
+    assert np.allclose(gE, o.dE0, rtol=G_RTOL, atol=0)
+    assert np.abs(gh - o.dh).max() <= G_RTOL * np.abs(o.dh).max()
+    # only the requested gradient: E0 alone
+    E0b = torch.tensor(E0, device=dev, requires_grad=True)
+    (gE2,) = torch.autograd.grad((pt2_autograd(ctx, dets, coefs.detach(), E0b, h.detach(), eri) *
+                                  torch.tensor(w, device=dev)).sum(), (E0b,))
+    assert np.allclose(gE2.cpu().numpy(), o.dE0, rtol=G_RTOL, atol=0)
