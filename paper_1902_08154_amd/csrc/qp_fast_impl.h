@@ -660,6 +660,41 @@ void fast_kernel(SweepArgs a)
                 return det_fold<NINT>(al);
             };
 
+            // one cell with all its corrections, outside the dense loops (the
+            // column pass): element x with phase bits sg, diagonal D
+            auto post_cell = [&](int i1, int i2, double x, uint32_t sg, double D, int pa, int pb) {
+                const double Hv = flip(x, sg);
+                double A[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
+                bool live = true;
+                uint32_t nco = 0;
+                if (gather(i1, i2, A, nco)) {
+                    live = false; D = DEAD_D; nban++;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) A[k] = 0.0;
+                } else {
+                    conn += nco;
+                }
+                double ek[NS], w[NS], vsum;
+                const double tsel = finish(A, D, ek, w, vsum);
+                if (FP && live) fpsum += fold(pa, pb);
+                {
+                    const bool c = live && fabs(tsel) >= tau_val;
+                    if (__ballot(c)) select(c, ek, pa, pb);
+                }
+                if (BWD) {
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) dcI[k] = fma(w[k], Hv, dcI[k]);
+                    vbatch += vsum;
+                    if (vsum != 0.0) {
+                        atomicAdd(&sDHD[pa], vsum);
+                        atomicAdd(&sDHD[pb], vsum);
+                    }
+                    if (live) gather_bwd(i1, i2, w);
+                }
+            };
+
             // --------------------------------------------------- dense pass
             if (type == BT_OS) {
                 if (lane == 0) cnt += (uint32_t)(nr * nc);
@@ -701,8 +736,10 @@ void fast_kernel(SweepArgs a)
 #pragma unroll
                                 for (int k = 0; k < NS; ++k) A[k] = 0.0;
                             }
-                            const bool flag = ((ri | ce.info) & (FR | FC)) != 0u;
-                            if (live && flag) {
+                            // a flagged row gathers its corrections here, all lanes at
+                            // once; a flagged column is finished by the column pass
+                            const bool rowf = (ri & FR) != 0u;
+                            if (live && rowf) {
                                 uint32_t nco = 0;
                                 if (gather(r, l, A, nco)) {
                                     live = false; D = DEAD_D; nban++;
@@ -711,6 +748,10 @@ void fast_kernel(SweepArgs a)
                                 } else {
                                     conn += nco;
                                 }
+                            } else if ((ce.info & FC) != 0u) {
+                                live = false; D = DEAD_D;
+#pragma unroll
+                                for (int k = 0; k < NS; ++k) A[k] = 0.0;
                             }
                             double ek[NS], w[NS], vsum;
                             const double tsel = finish(A, D, ek, w, vsum);
@@ -726,11 +767,29 @@ void fast_kernel(SweepArgs a)
                                 const double rsum = wsum(vsum);
                                 if (lane == 0 && rsum != 0.0) sDHD[pr] += rsum;
                                 colacc += vsum;
-                                if (live && flag) gather_bwd(r, l, w);
+                                if (live && rowf) gather_bwd(r, l, w);
                             }
                         }
                     }
                     if (BWD && lok && colacc != 0.0) atomicAdd(&sDHD[pcol], colacc);
+                }
+                // column pass: cells of flagged columns in unflagged rows
+                for (int s = 0; s < ncs; ++s) {
+                    const int col = sCSg[s] & 0xFFFF;
+                    bool seen = false;
+                    for (int t = 0; t < s; ++t) seen |= (int)(sCSg[t] & 0xFFFF) == col;
+                    if (seen) continue;
+                    const PEnt ce = sCT[col];
+                    const int pcol = ce.info & 255;
+                    for (int r0 = 0; r0 < nr; r0 += WAVE) {
+                        const int r = r0 + lane;
+                        const PEnt re = sRT[r < nr ? r : 0];
+                        if (r < nr && !(re.info & FR)) {
+                            const int pr = re.info & 255;
+                            const double xj = Jm[pr * n + pcol];
+                            post_cell(r, col, blk[pr * n + pcol], re.info ^ ce.info, (ce.G + re.G) + xj, pr, pcol);
+                        }
+                    }
                 }
             } else if (type == BT_SS) {
                 if (lane == 0) cnt += (uint32_t)(nr * (nr - 1) / 2);
@@ -770,8 +829,8 @@ void fast_kernel(SweepArgs a)
 #pragma unroll
                                     for (int k = 0; k < NS; ++k) A[k] = 0.0;
                                 }
-                                const bool flag = ((i2info & FR) | (e1.info & FC)) != 0u;
-                                if (live && flag) {
+                                const bool rowf = (i2info & FR) != 0u;
+                                if (live && rowf) {
                                     uint32_t nco = 0;
                                     if (gather(i1, i2, A, nco)) {
                                         live = false; D = DEAD_D; nban++;
@@ -780,6 +839,10 @@ void fast_kernel(SweepArgs a)
                                     } else {
                                         conn += nco;
                                     }
+                                } else if ((e1.info & FC) != 0u) {
+                                    live = false; D = DEAD_D;
+#pragma unroll
+                                    for (int k = 0; k < NS; ++k) A[k] = 0.0;
                                 }
                                 double ek[NS], w[NS], vsum;
                                 const double tsel = finish(A, D, ek, w, vsum);
@@ -798,9 +861,29 @@ void fast_kernel(SweepArgs a)
                                         if (sB != 0.0 && validB) sDHD[ib & 255] += sB;
                                     }
                                     if (vsum != 0.0) atomicAdd(&sDHD[p1], vsum);
-                                    if (live && flag) gather_bwd(i1, i2, w);
+                                    if (live && rowf) gather_bwd(i1, i2, w);
                                 }
                             }
+                        }
+                    }
+                }
+                // column pass: cells (ie, i2), i2 > ie, of flagged first indices in
+                // rows whose second index carries no flag
+                for (int s = 0; s < ncs; ++s) {
+                    const int ie = sCSg[s] & 0xFFFF;
+                    bool seen = false;
+                    for (int t = 0; t < s; ++t) seen |= (int)(sCSg[t] & 0xFFFF) == ie;
+                    if (seen) continue;
+                    const PEnt e1 = sRT[ie];
+                    const int p1 = e1.info & 255;
+                    for (int j0 = ie + 1; j0 < nr; j0 += WAVE) {
+                        const int i2 = j0 + lane;
+                        const PEnt e2 = sRT[i2 < nr ? i2 : ie];
+                        if (i2 < nr && !(e2.info & FR)) {
+                            const int p2 = e2.info & 255;
+                            const double xj = JK[p2 * n + p1];
+                            post_cell(ie, i2, blk[p2 * (p2 - 1) / 2 + p1], e1.info ^ e2.info ^ shb,
+                                      ((D0 + e2.G) + e1.G) + xj, p1, p2);
                         }
                     }
                 }
