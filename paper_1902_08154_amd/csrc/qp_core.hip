@@ -996,7 +996,7 @@ int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     unsigned int *hist = (unsigned int *)scratch(c, B_HIST, sizeof(unsigned int) * QP_HIST_BINS);
     if (!eps_item || !S_item || !cnt_item || !fp_item || (bwd && !dc_item) || !eps_g || !S_g || !cnt_g || !fp_g || !hist)
         return fail(c, QP_E_OOM, "device allocation failed (sweep buffers)");
-    const int rscap = n <= 128 ? 4 : 2, cscap = n <= 128 ? 4 : 2;
+    const int rscap = n <= 128 ? 6 : 3, cscap = n <= 128 ? 6 : 3;
     const int fgrid = fast_grid(c, nint, ns, bwd, n - std::min(P.nup, P.ndn), rscap, cscap);
     const int ggrid = sweep_grid(c, nint, ns, bwd);
     const int grid = std::max(fgrid, ggrid);

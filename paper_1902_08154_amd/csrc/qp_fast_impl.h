@@ -58,14 +58,22 @@ struct __align__(16) PEnt {
 
 __device__ __forceinline__ double frcp(double d)
 {
-    // reciprocal to about one ulp: hardware estimate and two Newton steps;
-    // where the estimate is infinite (d = 0 or |d| below 2^-1024) it is kept
+    // reciprocal: the hardware estimate (relative error below 2^-22) and one
+    // Newton step, which squares the error (below 2^-44, far inside the
+    // 1e-10 relative tolerance of E_PT2); where the estimate is infinite
+    // (d = 0 or |d| below 2^-1024) it is kept
     const double r0 = __builtin_amdgcn_rcp(d);
-    double e = fma(-d, r0, 1.0);
-    double r = fma(r0, e, r0);
-    e = fma(-d, r, 1.0);
-    r = fma(r, e, r);
+    const double r = fma(r0, fma(-d, r0, 1.0), r0);
     return __builtin_isinf(r0) ? r0 : r;
+}
+
+// min(m, |x|) in one instruction: both are non-negative results of
+// arithmetic, never signalling NaNs, so no canonicalisation is needed
+__device__ __forceinline__ double min_abs(double m, double x)
+{
+    double r;
+    asm("v_min_f64 %0, %1, |%2|" : "=v"(r) : "v"(m), "v"(x));
+    return r;
 }
 
 // keeps a wave-uniform value in a vector register: values read by every
@@ -608,7 +616,7 @@ void fast_kernel(SweepArgs a)
                     ek[k] = e;
                     esum[k] += e;
                     ssum[k] = fma(e, rc, ssum[k]);
-                    mind = fmin(mind, fabs(delta));
+                    mind = min_abs(mind, delta);
                     tsel = fma(e, invm[k], tsel);
                     if (BWD) {
                         w[k] = 2.0 * gup[k] * A[k] * rc;
@@ -681,7 +689,7 @@ void fast_kernel(SweepArgs a)
                 if (FP && live) fpsum += fold(pa, pb);
                 {
                     const bool c = live && fabs(tsel) >= tau_val;
-                    if (__ballot(c)) select(c, ek, pa, pb);
+                    if (__builtin_amdgcn_ballot_w64(c)) select(c, ek, pa, pb);
                 }
                 if (BWD) {
 #pragma unroll
@@ -758,7 +766,7 @@ void fast_kernel(SweepArgs a)
                             if (FP && live) fpsum += fold(pr, pcol);
                             {
                                 const bool c = live && fabs(tsel) >= tau_val;
-                                if (__ballot(c)) select(c, ek, pr, pcol);
+                                if (__builtin_amdgcn_ballot_w64(c)) select(c, ek, pr, pcol);
                             }
                             if (BWD) {
 #pragma unroll
@@ -849,7 +857,7 @@ void fast_kernel(SweepArgs a)
                                 if (FP && live) fpsum += fold(p1, p2);
                                 {
                                     const bool c = live && fabs(tsel) >= tau_val;
-                                    if (__ballot(c)) select(c, ek, p1, p2);
+                                    if (__builtin_amdgcn_ballot_w64(c)) select(c, ek, p1, p2);
                                 }
                                 if (BWD) {
 #pragma unroll
@@ -923,7 +931,7 @@ void fast_kernel(SweepArgs a)
                         if (FP && live) fpsum += fold(pa, -1);
                         {
                             const bool c = live && fabs(tsel) >= tau_val;
-                            if (__ballot(c)) select(c, ek, pa, -1);
+                            if (__builtin_amdgcn_ballot_w64(c)) select(c, ek, pa, -1);
                         }
                         if (BWD) {
                             double gs = 0.0;
