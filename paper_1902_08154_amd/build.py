@@ -87,6 +87,7 @@ def build(verbose: bool = False) -> str:
         caps = _read_caps()
         lowered = False
         bad = []
+        spilling = {}
         for src, (obj, scratch) in results.items():
             objs[src] = obj
             for fn, size in scratch.items():
@@ -96,12 +97,14 @@ def build(verbose: bool = False) -> str:
                 if m is None:
                     bad.append(f"{fn} ({size} bytes/lane)")
                     continue
-                ni, ns, bwd = int(m.group(1)), int(m.group(2)), int(m.group(3))
-                if caps[bwd][ni - 1][ns - 1] > 1:
-                    caps[bwd][ni - 1][ns - 1] -= 1
-                    lowered = True
-                else:
-                    bad.append(f"{fn} ({size} bytes/lane at the lowest occupancy target)")
+                spilling.setdefault((int(m.group(3)), int(m.group(1)), int(m.group(2))), []).append((fn, size))
+        # one occupancy target serves both fingerprint variants of an instantiation
+        for (bwd, ni, ns), fns in spilling.items():
+            if caps[bwd][ni - 1][ns - 1] > 1:
+                caps[bwd][ni - 1][ns - 1] -= 1
+                lowered = True
+            else:
+                bad += [f"{fn} ({size} bytes/lane at the lowest occupancy target)" for fn, size in fns]
         if bad:
             raise RuntimeError("kernels use scratch memory (register spills):\n  " + "\n  ".join(bad))
         if not lowered:

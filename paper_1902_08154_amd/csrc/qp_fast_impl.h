@@ -37,6 +37,7 @@ namespace qpfast {
 constexpr int WAVE = 64;
 constexpr int FCAP = 32;      // fine entries per batch
 constexpr int L2CAP = 64;     // m = 2 cells per batch
+constexpr int PCAP = 2;       // m = 0 entries (integral planes) per batch
 constexpr uint32_t FR = 1u << 8;    // row (OS) / second index (SS) carries a row or list correction
 constexpr uint32_t FC = 1u << 9;    // column (OS) / first index (SS) carries a column correction
 constexpr uint32_t SGN = 1u << 31;  // phase bit
@@ -44,7 +45,9 @@ constexpr double DEAD_D = -1e300;   // H_alpha,alpha of a cell that contributes 
 
 struct FE {
     int32_t j;
-    uint8_t m, earlier, ner, nec;
+    uint8_t m;
+    uint8_t earlier;   // bit 0: J precedes the generator; bits 1-2: holes of the batch in I \ J
+    uint8_t ner, nec;
     uint32_t er;   // row-spin virtual indices of E = J \ I (one per byte)
     uint32_t ec;   // column-spin virtual indices of E
 };
@@ -163,6 +166,7 @@ inline size_t lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap)
     add(8 * (bwd ? n : 1));         // adjoint diagonal of dE/dh
     add(sizeof(FE) * FCAP);
     add(4 * L2CAP);
+    add(4 * PCAP);                  // plane descriptors
     add(4 * rscap);
     add(4 * cscap);
     add(2 * 2 * n);                 // vidx
@@ -205,6 +209,7 @@ void fast_kernel(SweepArgs a)
     double *sDHD = carve<double>(lds, off, BWD ? n : 1);
     FE *sFine = carve<FE>(lds, off, FCAP);
     uint32_t *sL = carve<uint32_t>(lds, off, L2CAP);   // i1 | i2 << 8 | f << 16 | ban << 24
+    uint32_t *sPL = carve<uint32_t>(lds, off, PCAP);   // q1 | q2 << 8 | f << 16 | normal << 24
     uint32_t *sRSg = carve<uint32_t>(lds, off, RSCAP); // row | f << 16 | ban << 24
     uint32_t *sCSg = carve<uint32_t>(lds, off, CSCAP); // col | f << 16 | ban << 24
     uint16_t *sVidx = carve<uint16_t>(lds, off, 2 * n);
@@ -331,25 +336,23 @@ void fast_kernel(SweepArgs a)
             bool slow = false;
             for (int64_t base = cbeg; base < cend; base += WAVE) {
                 const int64_t e = base + lane;
-                bool keep = false, m0 = false;
+                bool keep = false;
                 CoarseEnt ce;
-                int m = 0;
+                int m = 0, inmask = 0;
                 if (e < cend) {
                     ce = a.cent[e];
-                    int dc = 0, in = 0;
+                    int dc = 0;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int d = ce.D[t];
                         if (d == 0xFFFF) continue;
                         dc++;
-                        in += (d == hc0) || (d == hc1);
+                        inmask |= (d == hc0 ? 1 : 0) | (d == hc1 ? 2 : 0);
                     }
-                    m = dc - in;
+                    m = dc - __popc(inmask);
                     keep = m <= 2;
-                    m0 = m == 0;
                 }
                 const uint64_t mask = __ballot(keep);
-                if (__ballot(m0)) slow = true;
                 const int pos = nfine + __popcll(mask & ((1ull << lane) - 1ull));
                 if (keep && pos < FCAP) {
                     int ner = 0, nec = 0;
@@ -366,7 +369,7 @@ void fast_kernel(SweepArgs a)
                         else if (type == BT_OS) { ec = (ec & ~(255u << (8 * nec))) | ((uint32_t)vi << (8 * nec)); nec++; }
                     }
                     FE f;
-                    f.j = ce.j; f.m = (uint8_t)m; f.earlier = (uint8_t)(ce.flags & 1);
+                    f.j = ce.j; f.m = (uint8_t)m; f.earlier = (uint8_t)((ce.flags & 1) | (inmask << 1));
                     f.ner = (uint8_t)ner; f.nec = (uint8_t)nec; f.er = er; f.ec = ec;
                     sFine[pos] = f;
 #pragma unroll
@@ -378,11 +381,56 @@ void fast_kernel(SweepArgs a)
             __syncthreads();
 
             // ------------------------------------------ classify corrections
-            int nl = 0, nrs = 0, ncs = 0;
+            int nl = 0, nrs = 0, ncs = 0, npl = 0;
+            bool allban = false;
             if (!slow) {
                 for (int f = 0; f < nfine; ++f) {
                     const FE fe = sFine[f];
-                    const uint32_t ban = fe.earlier ? (1u << 24) : 0u;
+                    const uint32_t ban = (fe.earlier & 1) ? (1u << 24) : 0u;
+                    if (fe.m == 0) {
+                        // J lacks only holes of this batch: it is connected to every
+                        // cell.  If it precedes the generator, it owns them all.
+                        if (fe.earlier & 1) { allban = true; break; }
+                        // the adjoint leaves integral planes to the general kernel
+                        if (BWD) { slow = true; break; }
+                        // J = I - H + E_J is itself a cell when it lacks both holes:
+                        // that cell is internal
+                        const bool caseA = (fe.ner + fe.nec) == (type == BT_SINGLE ? 1 : 2);
+                        if (caseA) {
+                            uint32_t cell;
+                            if (type == BT_SINGLE) cell = bat(fe.er, 0);
+                            else if (type == BT_OS) cell = bat(fe.er, 0) | (bat(fe.ec, 0) << 8);
+                            else {
+                                const int u = bat(fe.er, 0), v = bat(fe.er, 1);
+                                cell = (u < v ? u : v) | ((u < v ? v : u) << 8);
+                            }
+                            if (nl < L2CAP && lane == 0) sL[nl] = cell | (f << 16) | (1u << 24);
+                            nl++;
+                        }
+                        // cells sharing no particle with E_J are double excitations of
+                        // J: one integral block Q = (holes J keeps) + E_J, indexed by
+                        // the cell's particles (the integral plane)
+                        if (type != BT_SINGLE) {
+                            uint32_t desc;
+                            if (type == BT_OS) {
+                                // Q as (row-spin orbital, column-spin orbital)
+                                int qr, qc;
+                                if (caseA) { qr = rvirt[bat(fe.er, 0)]; qc = cvirt[bat(fe.ec, 0)]; }
+                                else if (fe.ner == 1) { qr = rvirt[bat(fe.er, 0)]; qc = hro; }
+                                else { qr = hrs; qc = cvirt[bat(fe.ec, 0)]; }
+                                desc = qr | (qc << 8) | (qr <= qc ? (1u << 24) : 0u);
+                            } else {
+                                const int qa = rvirt[bat(fe.er, 0)];
+                                // case B: the hole J keeps is the one not in I \ J
+                                const int qb = caseA ? rvirt[bat(fe.er, 1)] : (((fe.earlier >> 1) & 1) ? h2 : h1);
+                                desc = (qa < qb ? qa : qb) | ((qa < qb ? qb : qa) << 8);
+                            }
+                            if (npl < PCAP && lane == 0) sPL[npl] = desc | (f << 16);
+                            npl++;
+                        }
+                        // the cells sharing one particle with E_J: rows and columns,
+                        // as for m = 1 below
+                    }
                     if (type == BT_SINGLE) {
                         if (fe.m <= 1) {
                             if (nrs < RSCAP && lane == 0) sRSg[nrs] = 0u | (f << 16) | ban;
@@ -430,7 +478,12 @@ void fast_kernel(SweepArgs a)
                         }
                     }
                 }
-                if (nl > L2CAP || nrs > RSCAP || ncs > CSCAP) slow = true;
+                if (nl > L2CAP || nrs > RSCAP || ncs > CSCAP || npl > PCAP) slow = true;
+            }
+            if (allban) {
+                // every alpha of the batch belongs to an earlier generator
+                __syncthreads();
+                continue;
             }
             if (slow) {
                 // the general kernel takes this batch
@@ -458,6 +511,38 @@ void fast_kernel(SweepArgs a)
                 sLH[lane] = v;
                 // flag the cell's row (OS: first index; SS: second index; single: its particle)
                 atomicOr(&sRT[type == BT_SS ? i2 : i1].info, FR);
+            }
+            // integral planes: per particle index, the sign of J -> alpha on that
+            // index's spin and whether the index is a particle of J (such cells
+            // belong to rows/columns).  Bits 4k..4k+1: first index (sign, mask),
+            // 4k+2..4k+3: second index.
+            for (int k = 0; k < npl; ++k) {
+                const uint32_t desc = sPL[k];
+                const int q1 = desc & 255, q2 = (desc >> 8) & 255;
+                const FE fe = sFine[(desc >> 16) & 255];
+                const uint64_t *Jb = a.dets + (int64_t)fe.j * 2 * NINT;
+                if (type == BT_OS) {
+                    for (int i = lane; i < nr; i += WAVE) {
+                        const uint32_t sg = (uint32_t)between_parity<NINT>(Jb, rs, q1, rvirt[i]);
+                        sRT[i].pad |= (sg | (has(fe.er, fe.ner, i) ? 2u : 0u)) << (4 * k);
+                    }
+                    for (int c = lane; c < nc; c += WAVE) {
+                        const uint32_t sg = (uint32_t)between_parity<NINT>(Jb, cs, q2, cvirt[c]);
+                        sCT[c].pad |= (sg | (has(fe.ec, fe.nec, c) ? 2u : 0u)) << (4 * k + 2);
+                    }
+                } else {
+                    // same spin, q1 < q2, cell p1 < p2: the second excitation sees
+                    // q1 removed and p1 added, which moves the parity by
+                    // [q1 inside (q2, p2)] and [p1 > q2]
+                    for (int i = lane; i < nr; i += WAVE) {
+                        const int p = rvirt[i];
+                        const int lo = q2 < p ? q2 : p, hi = q2 < p ? p : q2;
+                        const uint32_t t1 = (uint32_t)between_parity<NINT>(Jb, rs, q1, p) ^ (p > q2 ? 1u : 0u);
+                        const uint32_t t2 = (uint32_t)between_parity<NINT>(Jb, rs, q2, p) ^ ((lo < q1 && q1 < hi) ? 1u : 0u);
+                        const uint32_t mk = has(fe.er, fe.ner, i) ? 2u : 0u;
+                        sRT[i].pad |= (t1 | mk | (t2 << 2) | (mk << 2)) << (4 * k);
+                    }
+                }
             }
             if (lane < nrs) atomicOr(&sRT[sRSg[lane] & 0xFFFF].info, FR);
             if (lane < ncs) atomicOr(type == BT_OS ? &sCT[sCSg[lane] & 0xFFFF].info : &sRT[sCSg[lane] & 0xFFFF].info, FC);
@@ -703,8 +788,118 @@ void fast_kernel(SweepArgs a)
                 }
             };
 
+            // blocks of the integral planes
+            const double *pblk[PCAP];
+#pragma unroll
+            for (int k = 0; k < PCAP; ++k) {
+                pblk[k] = a.I.Y;
+                if (k < npl) {
+                    const uint32_t desc = sPL[k];
+                    const int q1 = desc & 255, q2 = (desc >> 8) & 255;
+                    pblk[k] = type == BT_OS ? a.I.X + qtri(q1 < q2 ? q1 : q2, q1 < q2 ? q2 : q1) * n2
+                                            : a.I.Y + qtris(q1, q2) * (int64_t)P2;
+                }
+            }
+            // one cell of a batch with integral planes, evaluated exactly: u1/u2
+            // are the plane bits of its first/second index, o_norm/o_tran its
+            // offset in a plane block read as [first][second] or transposed
+            auto plane_cell = [&](int i1, int i2, double x, uint32_t sg, double D, int pa, int pb, uint32_t u1,
+                                  uint32_t u2, int o_norm, int o_tran, bool needg) {
+                const double Hv = flip(x, sg);
+                double A[NS], vv[PCAP];
+#pragma unroll
+                for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
+                uint32_t nco = 0;
+#pragma unroll
+                for (int k = 0; k < PCAP; ++k) {
+                    vv[k] = 0.0;
+                    const uint32_t b1 = u1 >> (4 * k), b2 = u2 >> (4 * k);
+                    if (k < npl && !((b1 & 2u) | (b2 & 8u))) {
+                        const uint32_t desc = sPL[k];
+                        const double v = pblk[k][((desc >> 24) & 1u) ? o_norm : o_tran];
+                        vv[k] = ((b1 ^ (b2 >> 2)) & 1u) ? -v : v;
+                        const int f = (desc >> 16) & 255;
+#pragma unroll
+                        for (int t = 0; t < NS; ++t) A[t] = fma(sFC[f * NS + t], vv[k], A[t]);
+                        nco++;
+                    }
+                }
+                bool live = true;
+                if (needg && gather(i1, i2, A, nco)) {
+                    live = false; D = DEAD_D; nban++;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) A[k] = 0.0;
+                }
+                if (live) conn += nco;
+                double ek[NS], w[NS], vsum;
+                const double tsel = finish(A, D, ek, w, vsum);
+                if (FP && live) fpsum += fold(pa, pb);
+                {
+                    const bool c = live && fabs(tsel) >= tau_val;
+                    if (__builtin_amdgcn_ballot_w64(c)) select(c, ek, pa, pb);
+                }
+                if (BWD) {
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) dcI[k] = fma(w[k], Hv, dcI[k]);
+                    vbatch += vsum;
+                    if (vsum != 0.0) {
+                        atomicAdd(&sDHD[pa], vsum);
+                        atomicAdd(&sDHD[pb], vsum);
+                    }
+                    if (live) {
+                        if (needg) gather_bwd(i1, i2, w);
+#pragma unroll
+                        for (int k = 0; k < PCAP; ++k) {
+                            if (vv[k] != 0.0) {
+                                const int f = (sPL[k] >> 16) & 255;
+#pragma unroll
+                                for (int t = 0; t < NS; ++t) atomicAdd(&sDCF[f * NS + t], w[t] * vv[k]);
+                            }
+                        }
+                    }
+                }
+            };
+
             // --------------------------------------------------- dense pass
-            if (type == BT_OS) {
+            if (!BWD && type == BT_OS && npl > 0) {
+                if (lane == 0) cnt += (uint32_t)(nr * nc);
+                const double *Jm = a.I.Jm;
+                for (int c0 = 0; c0 < nc; c0 += WAVE) {
+                    const int l = c0 + lane;
+                    if (l < nc) {
+                        const PEnt ce = sCT[l];
+                        const int pcol = ce.info & 255;
+                        for (int r = 0; r < nr; ++r) {
+                            const PEnt re = sRT[r];
+                            const int pr = re.info & 255;
+                            const double xj = Jm[pr * n + pcol];
+                            plane_cell(r, l, blk[pr * n + pcol], re.info ^ ce.info, (ce.G + re.G) + xj, pr, pcol,
+                                       re.pad, ce.pad, pr * n + pcol, pcol * n + pr,
+                                       ((re.info & FR) | (ce.info & FC)) != 0u);
+                        }
+                    }
+                }
+            } else if (!BWD && type == BT_SS && npl > 0) {
+                if (lane == 0) cnt += (uint32_t)(nr * (nr - 1) / 2);
+                const double *JK = a.I.JK;
+                const uint32_t shb = sH ? SGN : 0u;
+                const int nfr = nr / 2;
+                for (int c0 = 0; c0 < nr; c0 += WAVE) {
+                    const int l = c0 + lane;
+                    for (int r = 1; r <= nfr; ++r) {
+                        const bool pA = l < r;
+                        if (l < nr && (pA || nr - r > r)) {
+                            const int i1 = pA ? l : l - r, i2 = pA ? r : nr - r;
+                            const PEnt e1 = sRT[i1], e2 = sRT[i2];
+                            const int p1 = e1.info & 255, p2 = e2.info & 255;
+                            const int off = p2 * (p2 - 1) / 2 + p1;
+                            const double xj = JK[p2 * n + p1];
+                            plane_cell(i1, i2, blk[off], e1.info ^ e2.info ^ shb, ((D0 + e2.G) + e1.G) + xj, p1, p2,
+                                       e1.pad, e2.pad, off, off, ((e2.info & FR) | (e1.info & FC)) != 0u);
+                        }
+                    }
+                }
+            } else if (type == BT_OS) {
                 if (lane == 0) cnt += (uint32_t)(nr * nc);
                 const double *Jm = a.I.Jm;
                 for (int c0 = 0; c0 < nc; c0 += WAVE) {
