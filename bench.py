@@ -38,8 +38,8 @@ def log(*a):
 DENSE_SOURCES = ["qp_dev.h", "qp_fast_caps.h", "qp_fast_impl.h", "qp_fast_fwd.hip"]
 MEASURED_TRAFFIC = {
     "c2_n64_10a10b_1e4det_top1000": {
-        "sources_sha256": "af2c51c9eed8cec8f31d3bfaae531c4489e0c945a14693ffe2b27defdd9b21ce",
-        "bytes": 42841786898 + 45178752,
+        "sources_sha256": "5a9cfd85b8e2529d91f22a380679ce3831c732b4b1f1e011dd0e7ec90301e369",
+        "bytes": 45773635994 + 44932915,
     },
 }
 
