@@ -8,6 +8,12 @@ metric is external determinants (|A|) per second.  Besides the one JSON line
 on stdout, progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+Besides the headline forward sweep it reports, in "extra": the forward +
+adjoint throughput of the same workload, and the batched workload (64
+independent systems, n_orb in {32,48,64,96}, 4-12 electrons per spin,
+100-20,000 determinants, 1-3 states) run as one qp_pt2_batched call, forward
+and forward + adjoint, against one qp_pt2 call per system on the same GPU.
 """
 from __future__ import annotations
 
@@ -78,6 +84,66 @@ def cpu_baseline(s, E0, n_gen):
                 sample=f"{n_gen} generators evenly spaced in generator order ({int(r.count.sum())} alpha, {dt:.1f} s)")
 
 
+def batched_bench(ctx, dev, steps):
+    """The 64-system workload through qp_pt2_batched (forward, then forward +
+    adjoint in one adjoint sweep), and the same systems as one qp_pt2 call
+    each.  Integral layouts are built once, outside the timed region, as for
+    the single-system workload."""
+    import torch
+    from paper_1902_08154_amd import synth
+    from paper_1902_08154_amd.api import to_device_dets
+    t0 = time.perf_counter()
+    ws = synth.batched_workload()
+    log(f"batched workload: {len(ws)} systems, {sum(w.n_det for w in ws)} determinants "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    ins = []
+    for w in ws:
+        h = torch.from_numpy(w.h).to(dev)
+        eri = torch.from_numpy(w.eri).to(dev)
+        ctx.qp_set_integrals(h, eri)
+        dets = to_device_dets(w.dets, dev)
+        coefs = torch.from_numpy(w.coefs).to(dev)
+        ins.append(dict(h=h, eri_packed=eri, dets=dets, coefs=coefs, E0=ctx.energy(dets, coefs)))
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps, r
+
+    t_f, r_f = timed(lambda: ctx.pt2_batched(ins, reuse_integrals=True))
+    n_alpha = sum(x["stats"]["n_alpha"] for x in r_f)
+    n_cells = sum(x["stats"]["n_cells"] for x in r_f)
+    t_fb, _ = timed(lambda: ctx.pt2_batched(ins, with_backward=True, reuse_integrals=True))
+
+    def one_by_one():
+        # one forward call per system; each system's layouts are the context's,
+        # so they are rebuilt per call: that rebuild is timed on its own below
+        for y in ins:
+            ctx.qp_set_integrals(y["h"], y["eri_packed"])
+            ctx.pt2(y["dets"], y["coefs"], y["E0"])
+
+    def layouts_only():
+        for y in ins:
+            ctx.qp_set_integrals(y["h"], y["eri_packed"])
+
+    t_seq, _ = timed(one_by_one)
+    t_lay, _ = timed(layouts_only)
+    out = {"workload": "c4_64sys_n32-96_4-12e_100-20000det_1-3st", "n_systems": len(ws),
+           "n_det_total": int(sum(w.n_det for w in ws)), "n_alpha": n_alpha, "n_cells": n_cells,
+           "fwd_ms": 1e3 * t_f, "fwd_alpha_per_s": n_alpha / t_f,
+           "fwd_bwd_ms": 1e3 * t_fb, "fwd_bwd_alpha_per_s": n_alpha / t_fb,
+           "one_call_per_system_fwd_ms": 1e3 * (t_seq - t_lay),
+           "one_call_per_system_fwd_alpha_per_s": n_alpha / (t_seq - t_lay)}
+    log(f"batched: fwd {1e3 * t_f:.1f} ms, fwd+bwd {1e3 * t_fb:.1f} ms, one call per system "
+        f"{1e3 * (t_seq - t_lay):.1f} ms (+{1e3 * t_lay:.1f} ms of layout rebuilds), |A| = {n_alpha}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +152,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bwd-steps", type=int, default=2)
+    ap.add_argument("--batched-steps", type=int, default=2,
+                    help="timed repetitions of the 64-system batched workload (0: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, copy MIB MiB device to device once: a transfer of known size "
                          "against which the HBM traffic counters of the sweep are scaled")
@@ -95,8 +163,9 @@ def main():
               "design document)", file=sys.stderr)
         sys.exit(2)
 
+    import ctypes
     import torch
-    from paper_1902_08154_amd import synth
+    from paper_1902_08154_amd import _lib, synth
     from paper_1902_08154_amd.api import Context, to_device_dets
 
     idx = int(args.workload[1:])
@@ -119,7 +188,7 @@ def main():
     sd = torch.empty((max(nsel, 1), 2, nint), dtype=torch.int64, device=dev)
     se = torch.empty((max(nsel, 1), ns), dtype=torch.float64, device=dev)
     nsl = torch.zeros(1, dtype=torch.int64, device=dev)
-    st = torch.zeros(128, dtype=torch.uint8, device=dev)
+    st = torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev)
 
     def step():
         ctx.qp_pt2(dets, coefs, E0, nsel, 0, e_out, sd, se, nsl, st, None)
@@ -153,7 +222,8 @@ def main():
         f"general kernel {gen_ms:.2f} ms")
 
     # forward + backward throughput
-    extra = {"general_kernel_ms": gen_ms, "alpha_general_kernel": stats["n_alpha_general"]}
+    extra = {"general_kernel_ms": gen_ms, "alpha_general_kernel": stats["n_alpha_general"],
+             "e_pt2": e_out.cpu().tolist(), "rpt2_Z": stats["Z"], "e_rpt2": stats["e_rpt2"]}
     if args.bwd_steps > 0:
         gup = torch.ones(ns, dtype=torch.float64, device=dev)
         gc = torch.empty((ns, nd), dtype=torch.float64, device=dev)
@@ -170,6 +240,9 @@ def main():
         extra["fwd_bwd_alpha_per_s"] = stats["n_alpha"] / fb
         extra["fwd_bwd_ms_per_step"] = 1e3 * fb
         log(f"fwd+bwd {1e3 * fb:.2f} ms/step")
+
+    if args.batched_steps > 0:
+        extra["batched"] = batched_bench(ctx, dev, args.batched_steps)
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8

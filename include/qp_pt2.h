@@ -67,10 +67,15 @@ extern "C" {
 
 #define QP_MAX_STATES    4
 #define QP_MAX_ORB       256
+#define QP_MAX_SYSTEMS   4096
 
 /* qp_pt2 flags */
 #define QP_FLAG_FINGERPRINT  1  /* also compute stats.fingerprint of the alpha set */
 #define QP_FLAG_NOCHECK      2  /* skip input validation (duplicates, counts, bits) */
+#define QP_FLAG_REUSE_INTEGRALS 4 /* qp_pt2_batched: keep a system's integral layouts
+                                     from the previous batched call when its h and
+                                     eri_packed pointers and n_orb are the same, and
+                                     the caller has not changed their contents      */
 
 typedef struct qp_ctx qp_ctx;
 
@@ -89,7 +94,11 @@ typedef struct {
                                 (batches the dense kernel hands over)             */
     double   S[QP_MAX_STATES];  /* sum_alpha N^2/(E0-H_aa)^2 = -dE_PT2/dE0 (rPT2) */
     double   min_abs_delta;     /* min over alpha, k of |E0_k - H_alpha,alpha|      */
-    double   reserved_d[3];
+    /* renormalised PT2 (sec. "Renormalized PT2", eq. Z): the self-energy
+     * linearised about E0 has slope -S_k, so Z_k = 1/(1 + S_k) and the
+     * renormalised energy is E0_k + Z_k E_PT2,k                             */
+    double   Z[QP_MAX_STATES];
+    double   e_rpt2[QP_MAX_STATES];
 } qp_pt2_stats;
 /* fold(alpha): h = 0; for each word x of alpha (up words 0..n_int-1, then down
  * words 0..n_int-1): h = splitmix64_mix(h ^ x), where splitmix64_mix is the
@@ -170,6 +179,55 @@ int qp_pt2_backward(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int6
                     int n_states, const double *E0, const double *grad_e_pt2, int flags,
                     double *grad_coefs, double *grad_E0, double *grad_h,
                     qp_pt2_stats *stats, void *stream);
+
+/*
+ * qp_pt2_batched -- many independent wave functions in one sweep call: every
+ * system's (generator, batch) work items go into one work list, and each of
+ * the two sweep kernels runs as one persistent launch per (n_int, n_states)
+ * class over the items of all systems of that class (the generator
+ * decomposition of sec. "CIPSI selection and PT2 energy" applied system by
+ * system; each system is the computation of qp_pt2, or of qp_pt2_backward).
+ *   n_sys          number of systems, 0..QP_MAX_SYSTEMS
+ *   sys            host array [n_sys] of qp_system (below)
+ *   with_backward  0: the forward sweep (qp_pt2's outputs per system);
+ *                  1: the adjoint sweep, which yields E_PT2 and the gradients
+ *                  of qp_pt2_backward in one pass over the alpha (selection is
+ *                  then not available: n_select must be 0)
+ *   flags          QP_FLAG_* (FINGERPRINT, NOCHECK, REUSE_INTEGRALS)
+ * The context builds each system's integral layouts (as qp_set_integrals
+ * does) into storage of its own; it keeps them, and its other per-system
+ * scratch, until qp_destroy.  Results of a system are those qp_pt2 /
+ * qp_pt2_backward give for it alone.  The integrals set by qp_set_integrals
+ * are neither used nor changed.
+ * Host synchronisation: once per system with n_det > 0 (coarse-list sizes,
+ * validation), once after the dense kernel (sizes of the handed-over batch
+ * lists) and once before the selection sort.
+ * Errors: as qp_pt2; a message names the failing system.
+ */
+typedef struct {
+    int n_orb;                  /* 1..256                                           */
+    int n_states;               /* 1..4                                             */
+    int64_t n_det;              /* >= 0                                             */
+    const double *h;            /* device [n_orb][n_orb]                            */
+    const double *eri_packed;   /* device, packed as for qp_set_integrals           */
+    const uint64_t *dets;       /* device [n_det][2][n_int]                         */
+    const double *coefs;        /* device [n_states][n_det]                         */
+    const double *E0;           /* device [n_states]                                */
+    int64_t n_select;           /* forward only; 0 = no selection                   */
+    double *e_pt2;              /* out device [n_states] (required)                 */
+    uint64_t *sel_dets;         /* out device [n_select][2][n_int] (n_select > 0)   */
+    double *sel_e;              /* out device [n_select][n_states] (n_select > 0)   */
+    int64_t *n_sel;             /* out device [1] (n_select > 0)                    */
+    qp_pt2_stats *stats;        /* out device [1], optional                         */
+    double *eps_gen;            /* out device [n_states][n_det], optional, forward  */
+    const double *grad_e_pt2;   /* with_backward: device [n_states] (required)      */
+    double *grad_coefs;         /* with_backward: out [n_states][n_det], optional   */
+    double *grad_E0;            /* with_backward: out [n_states], optional          */
+    double *grad_h;             /* with_backward: out [n_orb][n_orb], optional      */
+} qp_system;
+
+int qp_pt2_batched(qp_ctx *ctx, int n_sys, const qp_system *sys, int with_backward, int flags,
+                   void *stream);
 
 /*
  * qp_energy -- variational energy E0_k = <Psi_k|H|Psi_k> / <Psi_k|Psi_k>

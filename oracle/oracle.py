@@ -176,6 +176,19 @@ def pt2_full(n_orb, h, eri, dets, coefs, E0, n_select=0, dump_all=False, grad_up
     return r
 
 
+def rpt2(E0, e_pt2, S):
+    """Renormalised PT2 (sec. "Renormalized PT2", eq. Z): the self-energy
+    Sigma[E] = sum_alpha <alpha|H|Psi>^2 / (E - H_aa) is linearised about E0,
+    where Sigma[E0] = E_PT2 and dSigma/dE = -S; solving E = E0 + Sigma[E] then
+    gives E = E0 + Z E_PT2 with Z = 1 / (1 - dSigma/dE) = 1 / (1 + S).
+    Per state k.  Returns (Z, E0 + Z E_PT2)."""
+    E0 = np.atleast_1d(np.asarray(E0, dtype=np.float64))
+    e = np.atleast_1d(np.asarray(e_pt2, dtype=np.float64))
+    S = np.atleast_1d(np.asarray(S, dtype=np.float64))
+    Z = 1.0 / (1.0 + S)
+    return Z, E0 + Z * e
+
+
 def alpha_eval(n_orb, h, eri, dets, coefs, rank, alpha):
     """(N[ns], D, owner_rank, internal) for one determinant alpha, scanning all of Psi."""
     dets = _c(dets, np.uint64); coefs = _c(np.atleast_2d(coefs), np.float64)

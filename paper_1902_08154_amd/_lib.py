@@ -21,7 +21,9 @@ QP_E_OVERFLOW = -9
 
 QP_FLAG_FINGERPRINT = 1
 QP_FLAG_NOCHECK = 2
+QP_FLAG_REUSE_INTEGRALS = 4
 QP_MAX_STATES = 4
+QP_MAX_SYSTEMS = 4096
 
 ERROR_NAMES = {
     QP_E_ARG: "QP_E_ARG", QP_E_NORB: "QP_E_NORB", QP_E_ELEC: "QP_E_ELEC", QP_E_DUP: "QP_E_DUP",
@@ -42,13 +44,39 @@ class Stats(ctypes.Structure):
         ("n_alpha_general", ctypes.c_uint64),
         ("S", ctypes.c_double * QP_MAX_STATES),
         ("min_abs_delta", ctypes.c_double),
-        ("reserved_d", ctypes.c_double * 3),
+        ("Z", ctypes.c_double * QP_MAX_STATES),
+        ("e_rpt2", ctypes.c_double * QP_MAX_STATES),
+    ]
+
+
+class System(ctypes.Structure):
+    """qp_system of include/qp_pt2.h (device pointers as integers)."""
+    _fields_ = [
+        ("n_orb", ctypes.c_int),
+        ("n_states", ctypes.c_int),
+        ("n_det", ctypes.c_int64),
+        ("h", ctypes.c_void_p),
+        ("eri_packed", ctypes.c_void_p),
+        ("dets", ctypes.c_void_p),
+        ("coefs", ctypes.c_void_p),
+        ("E0", ctypes.c_void_p),
+        ("n_select", ctypes.c_int64),
+        ("e_pt2", ctypes.c_void_p),
+        ("sel_dets", ctypes.c_void_p),
+        ("sel_e", ctypes.c_void_p),
+        ("n_sel", ctypes.c_void_p),
+        ("stats", ctypes.c_void_p),
+        ("eps_gen", ctypes.c_void_p),
+        ("grad_e_pt2", ctypes.c_void_p),
+        ("grad_coefs", ctypes.c_void_p),
+        ("grad_E0", ctypes.c_void_p),
+        ("grad_h", ctypes.c_void_p),
     ]
 
 
 # every entry point declared in include/qp_pt2.h
 EXPORTS = ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
-           "qp_pt2_backward", "qp_energy", "qp_set_timing", "qp_last_timing")
+           "qp_pt2_backward", "qp_pt2_batched", "qp_energy", "qp_set_timing", "qp_last_timing")
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -76,6 +104,8 @@ def load():
     lib.qp_pt2.restype = _I
     lib.qp_pt2_backward.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I, _P, _P, _P, _P, _P]
     lib.qp_pt2_backward.restype = _I
+    lib.qp_pt2_batched.argtypes = [_P, _I, ctypes.POINTER(System), _I, _I, _P]
+    lib.qp_pt2_batched.restype = _I
     lib.qp_energy.argtypes = [_P, _P, _P, _I64, _I, _I, _P, _P]
     lib.qp_energy.restype = _I
     lib.qp_set_timing.argtypes = [_P, _I]

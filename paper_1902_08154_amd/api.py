@@ -98,6 +98,12 @@ class Context:
                                               _ptr(grad_coefs), _ptr(grad_E0), _ptr(grad_h), _ptr(stats),
                                               _stream(self.device)))
 
+    def qp_pt2_batched(self, systems, with_backward=False, flags=0):
+        """systems: a sequence of _lib.System records."""
+        arr = (_lib.System * max(len(systems), 1))(*systems)
+        self._check(self._lib.qp_pt2_batched(self._h, len(systems), arr, 1 if with_backward else 0, flags,
+                                             _stream(self.device)))
+
     def qp_energy(self, dets, coefs, E0_out, flags=0):
         self._check(self._lib.qp_energy(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], coefs.shape[0],
                                         flags, _ptr(E0_out), _stream(self.device)))
@@ -156,6 +162,63 @@ class Context:
         self.qp_pt2_backward(dets, coefs, E0, g, 0, gc, gE, gh, None)
         return gc, gE, gh
 
+    def pt2_batched(self, systems, with_backward=False, fingerprint=False, check=True, reuse_integrals=False):
+        """Many systems in one call.  `systems` is a sequence of dicts with
+        tensors h [n,n], eri_packed, dets [n_det,2,n_int], coefs [ns,n_det],
+        E0 [ns], and optionally n_select (forward only), eps_gen (bool) and,
+        with_backward, grad_e_pt2 [ns] (default ones).  Returns one dict per
+        system: e_pt2, stats, sel_dets/sel_e when n_select > 0, eps_gen if
+        asked, and grad_coefs/grad_E0/grad_h with_backward."""
+        dev = self.device
+        recs, outs = [], []
+        for i, y in enumerate(systems):
+            h, eri, dets, coefs, E0 = y["h"], y["eri_packed"], y["dets"], y["coefs"], y["E0"]
+            _need(h, torch.float64, f"systems[{i}].h", dev)
+            _need(eri, torch.float64, f"systems[{i}].eri_packed", dev)
+            self._inputs(dets, coefs, E0)
+            n = h.shape[0]
+            ns, nd = coefs.shape
+            k = int(y.get("n_select", 0) or 0)
+            o = dict(e_pt2=torch.empty(ns, dtype=torch.float64, device=dev),
+                     stats=torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev))
+            r = _lib.System(n_orb=n, n_states=ns, n_det=nd, h=h.data_ptr(), eri_packed=eri.data_ptr(),
+                            dets=dets.data_ptr(), coefs=coefs.data_ptr(), E0=E0.data_ptr(), n_select=k,
+                            e_pt2=o["e_pt2"].data_ptr(), stats=o["stats"].data_ptr())
+            if k > 0:
+                o["sel_dets"] = torch.empty((k, 2, dets.shape[2]), dtype=torch.int64, device=dev)
+                o["sel_e"] = torch.empty((k, ns), dtype=torch.float64, device=dev)
+                o["n_sel"] = torch.zeros(1, dtype=torch.int64, device=dev)
+                r.sel_dets, r.sel_e, r.n_sel = (o["sel_dets"].data_ptr(), o["sel_e"].data_ptr(),
+                                                o["n_sel"].data_ptr())
+            if y.get("eps_gen") and not with_backward:
+                o["eps_gen"] = torch.empty((ns, nd), dtype=torch.float64, device=dev)
+                r.eps_gen = o["eps_gen"].data_ptr()
+            if with_backward:
+                g = y.get("grad_e_pt2")
+                g = torch.ones(ns, dtype=torch.float64, device=dev) if g is None else \
+                    g.to(device=dev, dtype=torch.float64).contiguous()
+                o["_g"] = g
+                o["grad_coefs"] = torch.empty((ns, nd), dtype=torch.float64, device=dev)
+                o["grad_E0"] = torch.empty(ns, dtype=torch.float64, device=dev)
+                o["grad_h"] = torch.empty((n, n), dtype=torch.float64, device=dev)
+                r.grad_e_pt2 = g.data_ptr()
+                r.grad_coefs, r.grad_E0, r.grad_h = (o["grad_coefs"].data_ptr(), o["grad_E0"].data_ptr(),
+                                                     o["grad_h"].data_ptr())
+            recs.append(r)
+            outs.append((o, ns, k))
+        flags = ((_lib.QP_FLAG_FINGERPRINT if fingerprint else 0) | (0 if check else _lib.QP_FLAG_NOCHECK) |
+                 (_lib.QP_FLAG_REUSE_INTEGRALS if reuse_integrals else 0))
+        self.qp_pt2_batched(recs, with_backward, flags)
+        res = []
+        for o, ns, k in outs:
+            o.pop("_g", None)
+            o["stats"] = stats_to_dict(o["stats"], ns)
+            if k > 0:
+                m = int(o.pop("n_sel").item())
+                o["sel_dets"], o["sel_e"] = o["sel_dets"][:m], o["sel_e"][:m]
+            res.append(o)
+        return res
+
     def energy(self, dets, coefs):
         self._inputs(dets, coefs)
         out = torch.empty(coefs.shape[0], dtype=torch.float64, device=self.device)
@@ -203,7 +266,8 @@ def stats_to_dict(st: torch.Tensor, ns: int) -> dict:
                 n_coarse=int(s.n_coarse), n_candidates=int(s.n_candidates), overflow=int(s.overflow),
                 n_connections=int(s.n_connections), n_alpha_general=int(s.n_alpha_general),
                 S=[float(s.S[k]) for k in range(ns)],
-                min_abs_delta=float(s.min_abs_delta))
+                min_abs_delta=float(s.min_abs_delta),
+                Z=[float(s.Z[k]) for k in range(ns)], e_rpt2=[float(s.e_rpt2[k]) for k in range(ns)])
 
 
 def to_device_dets(dets_u64, device) -> torch.Tensor:

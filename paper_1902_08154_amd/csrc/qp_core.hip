@@ -520,7 +520,7 @@ __global__ void reduce_items(const double *eps_item, const double *S_item, const
 __global__ void reduce_total(const double *eps_g, const double *S_g, const uint64_t *cnt_g, const uint64_t *fp_g,
                              const uint64_t *conn_g, const uint64_t *defa_g, int64_t n_det, int ns, double *e_pt2,
                              qp_pt2_stats *stats, const Scalars *sc, int64_t n_cells, const double *gup,
-                             double *grad_E0)
+                             double *grad_E0, const double *E0)
 {
     __shared__ double se[256][QPD_MAX_STATES], ss[256][QPD_MAX_STATES];
     __shared__ uint64_t sc_[256], sf[256], sn[256], sd[256];
@@ -563,7 +563,12 @@ __global__ void reduce_total(const double *eps_g, const double *S_g, const uint6
             stats->n_alpha_general = sd[0];
             for (int k = 0; k < QPD_MAX_STATES; ++k) stats->S[k] = k < ns ? ss[0][k] : 0.0;
             stats->min_abs_delta = __longlong_as_double((long long)sc->min_delta_bits);
-            for (int k = 0; k < 3; ++k) stats->reserved_d[k] = 0.0;
+            // rPT2 (eq. Z): Z = 1 / (1 - dSigma/dE) with dSigma/dE = -S at E0
+            for (int k = 0; k < QPD_MAX_STATES; ++k) {
+                const double z = k < ns ? 1.0 / (1.0 + ss[0][k]) : 0.0;
+                stats->Z[k] = z;
+                stats->e_rpt2[k] = k < ns ? E0[k] + z * se[0][k] : 0.0;
+            }
         }
     }
 }
@@ -672,16 +677,41 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+enum BufId {
+    B_W, B_IDX, B_RANK, B_F, B_HII, B_COUNTS, B_OFFS, B_BSUM, B_COFF, B_CENT, B_EPSI, B_SI, B_CNTI, B_FPI,
+    B_DCI, B_EPSG, B_SG, B_CNTG, B_FPG, B_SC, B_HIST, B_CAND, B_COMP, B_SKEY, B_SBITS, B_SIDX, B_MAXC2,
+    B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFE, B_DEFS, B_DEFC, B_DEFN, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
+    B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS,
+    // integral layouts of a system of a batched call
+    B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
+    B_COUNT
+};
+
+// what a slot's integral layouts were last built from (batched calls)
+struct LayoutKey {
+    const double *h = nullptr, *eri = nullptr;
+    int n = 0;
+};
+
 struct qp_ctx {
     int device = 0;
     std::string err;
     int n = 0;
     double *h = nullptr, *X = nullptr, *Y = nullptr, *Cj = nullptr, *Xj = nullptr, *Jm = nullptr, *Km = nullptr,
            *JK = nullptr;
-    std::vector<DevBuf> bufs;
+    // device scratch, one set per system slot: slot s serves system s of a
+    // batched call; single-system calls use slot 0
+    std::vector<std::vector<DevBuf>> slots;
+    std::vector<LayoutKey> layout_keys;
+    DevBuf args[2];                // per-launch system descriptors (dense, general)
+    DevBuf defn;                   // per-system count of handed-over batches
     int num_cu = 256;
-    Scalars *host_sc = nullptr;   // pinned
-    uint64_t *host_det0 = nullptr;
+    Scalars *host_sc = nullptr;    // pinned, one per system
+    int host_sc_n = 0;
+    uint64_t *host_det0 = nullptr; // pinned
+    double *host_maxc2 = nullptr;  // pinned
+    unsigned char *host_stage = nullptr;  // pinned staging of system descriptors
+    size_t host_stage_bytes = 0;
     bool timing = false;
     bool timed = false;
     // call start, dense sweep start, general kernel start, sweep end, call end
@@ -689,13 +719,6 @@ struct qp_ctx {
 };
 
 namespace {
-
-enum BufId {
-    B_W, B_IDX, B_RANK, B_F, B_HII, B_COUNTS, B_OFFS, B_BSUM, B_COFF, B_CENT, B_EPSI, B_SI, B_CNTI, B_FPI,
-    B_DCI, B_EPSG, B_SG, B_CNTG, B_FPG, B_SC, B_HIST, B_CAND, B_COMP, B_SKEY, B_SBITS, B_SIDX, B_MAXC2,
-    B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFN, B_DEFE, B_DEFS, B_DEFC, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
-    B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_COUNT
-};
 
 int fail(qp_ctx *c, int code, const std::string &msg)
 {
@@ -709,10 +732,9 @@ int fail(qp_ctx *c, int code, const std::string &msg)
         if (e_ != hipSuccess) return fail(ctx, QP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-void *scratch(qp_ctx *c, int id, size_t bytes)
+void *grow(DevBuf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 8;
-    DevBuf &b = c->bufs[id];
     if (b.bytes >= bytes) return b.p;
     if (b.p) (void)hipFree(b.p);
     b.p = nullptr;
@@ -725,6 +747,41 @@ void *scratch(qp_ctx *c, int id, size_t bytes)
     }
     b.bytes = want;
     return b.p;
+}
+
+void *scratch(qp_ctx *c, int slot, int id, size_t bytes)
+{
+    if ((int)c->slots.size() <= slot) c->slots.resize(slot + 1);
+    std::vector<DevBuf> &v = c->slots[slot];
+    if (v.empty()) v.resize(B_COUNT);
+    return grow(v[id], bytes);
+}
+
+// pinned host staging for the per-launch system descriptors and the per-system
+// scalars read back by the host
+int host_space(qp_ctx *c, size_t stage_bytes, int n_sys)
+{
+    if (c->host_stage_bytes < stage_bytes || c->host_sc_n < n_sys) {
+        // earlier calls' transfers may still read the old buffers
+        HIPCHK(c, hipDeviceSynchronize());
+    }
+    if (c->host_stage_bytes < stage_bytes) {
+        if (c->host_stage) (void)hipHostFree(c->host_stage);
+        c->host_stage = nullptr;
+        c->host_stage_bytes = 0;
+        if (hipHostMalloc((void **)&c->host_stage, stage_bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(c, QP_E_OOM, "pinned host allocation failed");
+        c->host_stage_bytes = stage_bytes;
+    }
+    if (c->host_sc_n < n_sys) {
+        if (c->host_sc) (void)hipHostFree(c->host_sc);
+        c->host_sc = nullptr;
+        c->host_sc_n = 0;
+        if (hipHostMalloc((void **)&c->host_sc, sizeof(Scalars) * n_sys, hipHostMallocDefault) != hipSuccess)
+            return fail(c, QP_E_OOM, "pinned host allocation failed");
+        c->host_sc_n = n_sys;
+    }
+    return QP_OK;
 }
 
 int64_t pow2_at_least(int64_t x)
@@ -742,22 +799,29 @@ int grid_for(int64_t n, int tb = 256, int64_t cap = 65536)
     return (int)g;
 }
 
-template <int NINT, int NS>
-void sweep_dispatch_ns(const SweepArgs &a, int grid, bool bwd, hipStream_t st)
+// integral layouts of one system into I's (already allocated) arrays
+void launch_layouts(const double *h, const double *eri, int n_orb, const DevInts &I, hipStream_t st)
 {
-    if (bwd) launch_sweep<NINT, NS, true>(a, grid, st);
-    else launch_sweep<NINT, NS, false>(a, grid, st);
+    const int64_t n = n_orb;
+    const int64_t nX = n * (n + 1) / 2 * n * n;
+    const int64_t P2 = n * (n - 1) / 2;
+    const int64_t n3 = n * n * n;
+    hipLaunchKernelGGL(build_X, dim3(grid_for(nX, 256, 1 << 16)), dim3(256), 0, st, eri, n_orb, (double *)I.X);
+    if (P2 > 0)
+        hipLaunchKernelGGL(build_Y, dim3(grid_for(P2 * P2, 256, 1 << 16)), dim3(256), 0, st, eri, n_orb, (double *)I.Y);
+    hipLaunchKernelGGL(build_small, dim3(grid_for(n3, 256, 1 << 16)), dim3(256), 0, st, eri, h, n_orb, (double *)I.Cj,
+                       (double *)I.Xj, (double *)I.Jm, (double *)I.Km, (double *)I.JK, (double *)I.h);
 }
 
-template <int NINT>
-void sweep_dispatch(const SweepArgs &a, int grid, bool bwd, hipStream_t st)
+struct LayoutSizes {
+    size_t nX, nY, n3, n2;
+};
+
+LayoutSizes layout_sizes(int n_orb)
 {
-    switch (a.ns) {
-    case 1: sweep_dispatch_ns<NINT, 1>(a, grid, bwd, st); break;
-    case 2: sweep_dispatch_ns<NINT, 2>(a, grid, bwd, st); break;
-    case 3: sweep_dispatch_ns<NINT, 3>(a, grid, bwd, st); break;
-    default: sweep_dispatch_ns<NINT, 4>(a, grid, bwd, st); break;
-    }
+    const size_t n = n_orb;
+    const size_t P2 = n * (n - 1) / 2;
+    return {n * (n + 1) / 2 * n * n, std::max<size_t>(1, P2 * P2), n * n * n, n * n};
 }
 
 // Everything before the sweep: order, prep, coarse lists.  One host sync.
@@ -770,24 +834,25 @@ struct Prepared {
     CoarseEnt *cent;
     Scalars *sc;
     double *maxc2;
+    double hmax[QPD_MAX_STATES];
     int64_t coarse_total;
 };
 
 template <int NINT>
-int prepare_t(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int ns, int flags,
-              hipStream_t st, Prepared &P)
+int prepare_t(qp_ctx *c, int slot, const DevInts &I, const uint64_t *dets, const double *coefs, int64_t n_det,
+              int ns, int flags, hipStream_t st, Prepared &P)
 {
-    const int n = c->n;
+    const int n = I.n;
     P.nint = NINT;
     P.n_det = n_det;
     const int64_t Pw = pow2_at_least(n_det);
-    double *w = (double *)scratch(c, B_W, sizeof(double) * n_det);
-    int32_t *idx = (int32_t *)scratch(c, B_IDX, sizeof(int32_t) * Pw);
-    int32_t *rank = (int32_t *)scratch(c, B_RANK, sizeof(int32_t) * n_det);
-    double *F = (double *)scratch(c, B_F, sizeof(double) * n_det * 2 * n);
-    double *HII = (double *)scratch(c, B_HII, sizeof(double) * n_det);
-    Scalars *sc = (Scalars *)scratch(c, B_SC, sizeof(Scalars));
-    double *maxc2 = (double *)scratch(c, B_MAXC2, sizeof(double) * QPD_MAX_STATES);
+    double *w = (double *)scratch(c, slot, B_W, sizeof(double) * n_det);
+    int32_t *idx = (int32_t *)scratch(c, slot, B_IDX, sizeof(int32_t) * Pw);
+    int32_t *rank = (int32_t *)scratch(c, slot, B_RANK, sizeof(int32_t) * n_det);
+    double *F = (double *)scratch(c, slot, B_F, sizeof(double) * n_det * 2 * n);
+    double *HII = (double *)scratch(c, slot, B_HII, sizeof(double) * n_det);
+    Scalars *sc = (Scalars *)scratch(c, slot, B_SC, sizeof(Scalars));
+    double *maxc2 = (double *)scratch(c, slot, B_MAXC2, sizeof(double) * QPD_MAX_STATES);
     if (!w || !idx || !rank || !F || !HII || !sc || !maxc2) return fail(c, QP_E_OOM, "device allocation failed");
     HIPCHK(c, hipMemsetAsync(sc, 0, sizeof(Scalars), st));
     {
@@ -798,19 +863,19 @@ int prepare_t(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     hipLaunchKernelGGL(max_c2, dim3(1), dim3(256), 0, st, coefs, n_det, ns, maxc2);
     bitonic_sort(idx, Pw, GenCmp<NINT>{w, dets}, st);
     hipLaunchKernelGGL(make_rank, dim3(grid_for(n_det)), dim3(256), 0, st, idx, n_det, rank);
-    hipLaunchKernelGGL(prep_generators<NINT>, dim3((unsigned)n_det), dim3(128), 0, st, dets, idx, n_det, n, c->h,
-                       c->Jm, c->Km, F, HII, sc);
+    hipLaunchKernelGGL(prep_generators<NINT>, dim3((unsigned)n_det), dim3(128), 0, st, dets, idx, n_det, n, I.h,
+                       I.Jm, I.Km, F, HII, sc);
     // coarse counts
     const int64_t gblocks = (n_det + 255) / 256;
     int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + gblocks - 1) / gblocks, (n_det + 255) / 256));
     const int64_t chunk = (n_det + nchunk - 1) / nchunk;
     const int64_t ncount = n_det * nchunk;
-    int32_t *counts = (int32_t *)scratch(c, B_COUNTS, sizeof(int32_t) * ncount);
-    int64_t *offs = (int64_t *)scratch(c, B_OFFS, sizeof(int64_t) * ncount);
+    int32_t *counts = (int32_t *)scratch(c, slot, B_COUNTS, sizeof(int32_t) * ncount);
+    int64_t *offs = (int64_t *)scratch(c, slot, B_OFFS, sizeof(int64_t) * ncount);
     const int64_t nsb = (ncount + 1023) / 1024;
-    int64_t *bsum = (int64_t *)scratch(c, B_BSUM, sizeof(int64_t) * nsb);
-    int64_t *total = (int64_t *)scratch(c, B_TOTAL, sizeof(int64_t));
-    int64_t *coff = (int64_t *)scratch(c, B_COFF, sizeof(int64_t) * (n_det + 1));
+    int64_t *bsum = (int64_t *)scratch(c, slot, B_BSUM, sizeof(int64_t) * nsb);
+    int64_t *total = (int64_t *)scratch(c, slot, B_TOTAL, sizeof(int64_t));
+    int64_t *coff = (int64_t *)scratch(c, slot, B_COFF, sizeof(int64_t) * (n_det + 1));
     if (!counts || !offs || !bsum || !total || !coff) return fail(c, QP_E_OOM, "device allocation failed");
     hipLaunchKernelGGL((coarse_kernel<NINT, false>), dim3((unsigned)gblocks, nchunk), dim3(256), 0, st, dets, idx, rank,
                        n_det, chunk, nchunk, counts, (const int64_t *)nullptr, (CoarseEnt *)nullptr, sc);
@@ -820,6 +885,7 @@ int prepare_t(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     hipLaunchKernelGGL(make_coff, dim3(grid_for(n_det + 1)), dim3(256), 0, st, offs, n_det, nchunk, total, coff, sc);
     HIPCHK(c, hipMemcpyAsync(c->host_det0, dets, sizeof(uint64_t) * 2 * NINT, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipMemcpyAsync(c->host_sc, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(c->host_maxc2, maxc2, sizeof(double) * QPD_MAX_STATES, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     HIPCHK(c, hipGetLastError());
     const Scalars hs = *c->host_sc;
@@ -834,8 +900,9 @@ int prepare_t(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
         ndn += __builtin_popcountll(c->host_det0[NINT + wq]);
     }
     P.nup = nup; P.ndn = ndn; P.nel = nup + ndn;
+    for (int k = 0; k < QPD_MAX_STATES; ++k) P.hmax[k] = c->host_maxc2[k];
     const int64_t ctot = (int64_t)hs.coarse_total;
-    CoarseEnt *cent = (CoarseEnt *)scratch(c, B_CENT, sizeof(CoarseEnt) * (ctot > 0 ? ctot : 1));
+    CoarseEnt *cent = (CoarseEnt *)scratch(c, slot, B_CENT, sizeof(CoarseEnt) * (ctot > 0 ? ctot : 1));
     if (!cent) return fail(c, QP_E_OOM, "device allocation failed (coarse lists)");
     hipLaunchKernelGGL((coarse_kernel<NINT, true>), dim3((unsigned)gblocks, nchunk), dim3(256), 0, st, dets, idx, rank,
                        n_det, chunk, nchunk, counts, (const int64_t *)offs, cent, sc);
@@ -844,14 +911,14 @@ int prepare_t(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     return QP_OK;
 }
 
-int prepare(qp_ctx *c, int nint, const uint64_t *dets, const double *coefs, int64_t n_det, int ns, int flags,
-            hipStream_t st, Prepared &P)
+int prepare(qp_ctx *c, int slot, const DevInts &I, const uint64_t *dets, const double *coefs, int64_t n_det, int ns,
+            int flags, hipStream_t st, Prepared &P)
 {
-    switch (nint) {
-    case 1: return prepare_t<1>(c, dets, coefs, n_det, ns, flags, st, P);
-    case 2: return prepare_t<2>(c, dets, coefs, n_det, ns, flags, st, P);
-    case 3: return prepare_t<3>(c, dets, coefs, n_det, ns, flags, st, P);
-    default: return prepare_t<4>(c, dets, coefs, n_det, ns, flags, st, P);
+    switch ((I.n - 1) / 64 + 1) {
+    case 1: return prepare_t<1>(c, slot, I, dets, coefs, n_det, ns, flags, st, P);
+    case 2: return prepare_t<2>(c, slot, I, dets, coefs, n_det, ns, flags, st, P);
+    case 3: return prepare_t<3>(c, slot, I, dets, coefs, n_det, ns, flags, st, P);
+    default: return prepare_t<4>(c, slot, I, dets, coefs, n_det, ns, flags, st, P);
     }
 }
 
@@ -862,15 +929,23 @@ int64_t cells_per_generator(int n, int nup, int ndn)
            (int64_t)ndn * (ndn - 1) / 2 * (vd * (vd - 1) / 2) + (int64_t)nup * vu * ndn * vd;
 }
 
+int check_system(qp_ctx *c, int n_orb, const uint64_t *dets, const double *coefs, int64_t n_det, int ns,
+                 const double *E0)
+{
+    if (n_det < 0) return fail(c, QP_E_ARG, "n_det < 0");
+    if (ns < 1 || ns > QP_MAX_STATES) return fail(c, QP_E_STATES, "n_states must be in [1,4]");
+    if (n_orb <= 0) return fail(c, QP_E_NOINT, "integrals not set");
+    if (n_det > 0 && (!dets || !coefs || !E0)) return fail(c, QP_E_ARG, "null input pointer");
+    if (n_det > (int64_t)INT32_MAX / 2) return fail(c, QP_E_ARG, "n_det too large");
+    return QP_OK;
+}
+
 int common_checks(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int ns, const double *E0)
 {
     if (!c) return QP_E_ARG;
     c->err.clear();
-    if (n_det < 0) return fail(c, QP_E_ARG, "n_det < 0");
-    if (ns < 1 || ns > QP_MAX_STATES) return fail(c, QP_E_STATES, "n_states must be in [1,4]");
-    if (c->n <= 0) return fail(c, QP_E_NOINT, "integrals not set");
-    if (n_det > 0 && (!dets || !coefs || !E0)) return fail(c, QP_E_ARG, "null input pointer");
-    if (n_det > (int64_t)INT32_MAX / 2) return fail(c, QP_E_ARG, "n_det too large");
+    int rc = check_system(c, c->n, dets, coefs, n_det, ns, E0);
+    if (rc != QP_OK) return rc;
     HIPCHK(c, hipSetDevice(c->device));
     return QP_OK;
 }
@@ -883,51 +958,38 @@ DevInts dev_ints(const qp_ctx *c)
     return I;
 }
 
+// ------------------------------------------------- launch-shape dispatchers
 template <int NINT>
-int occ_ns(int n, int ns, bool bwd)
+int sweep_occ_t(int ns, bool bwd, size_t lds)
 {
     switch (ns) {
-    case 1: return bwd ? sweep_occupancy<NINT, 1, true>(n) : sweep_occupancy<NINT, 1, false>(n);
-    case 2: return bwd ? sweep_occupancy<NINT, 2, true>(n) : sweep_occupancy<NINT, 2, false>(n);
-    case 3: return bwd ? sweep_occupancy<NINT, 3, true>(n) : sweep_occupancy<NINT, 3, false>(n);
-    default: return bwd ? sweep_occupancy<NINT, 4, true>(n) : sweep_occupancy<NINT, 4, false>(n);
+    case 1: return bwd ? sweep_occupancy<NINT, 1, true>(lds) : sweep_occupancy<NINT, 1, false>(lds);
+    case 2: return bwd ? sweep_occupancy<NINT, 2, true>(lds) : sweep_occupancy<NINT, 2, false>(lds);
+    case 3: return bwd ? sweep_occupancy<NINT, 3, true>(lds) : sweep_occupancy<NINT, 3, false>(lds);
+    default: return bwd ? sweep_occupancy<NINT, 4, true>(lds) : sweep_occupancy<NINT, 4, false>(lds);
+    }
+}
+
+template <int NINT>
+int fast_occ_t(int ns, bool bwd, size_t lds)
+{
+    switch (ns) {
+    case 1: return bwd ? fast_occupancy<NINT, 1, true>(lds) : fast_occupancy<NINT, 1, false>(lds);
+    case 2: return bwd ? fast_occupancy<NINT, 2, true>(lds) : fast_occupancy<NINT, 2, false>(lds);
+    case 3: return bwd ? fast_occupancy<NINT, 3, true>(lds) : fast_occupancy<NINT, 3, false>(lds);
+    default: return bwd ? fast_occupancy<NINT, 4, true>(lds) : fast_occupancy<NINT, 4, false>(lds);
     }
 }
 
 // persistent grid: every resident one-wavefront workgroup the CUs can hold
-int sweep_grid(qp_ctx *c, int nint, int ns, bool bwd)
+int persistent_grid(qp_ctx *c, bool dense, int nint, int ns, bool bwd, size_t lds)
 {
     int per_cu = 8;
     switch (nint) {
-    case 1: per_cu = occ_ns<1>(c->n, ns, bwd); break;
-    case 2: per_cu = occ_ns<2>(c->n, ns, bwd); break;
-    case 3: per_cu = occ_ns<3>(c->n, ns, bwd); break;
-    default: per_cu = occ_ns<4>(c->n, ns, bwd); break;
-    }
-    if (per_cu < 1) per_cu = 1;
-    if (per_cu > 32) per_cu = 32;
-    return c->num_cu * per_cu;
-}
-
-template <int NINT>
-int focc_ns(int n, int nvm, int ns, bool bwd, int rc, int cc)
-{
-    switch (ns) {
-    case 1: return bwd ? fast_occupancy<NINT, 1, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 1, false>(n, nvm, rc, cc);
-    case 2: return bwd ? fast_occupancy<NINT, 2, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 2, false>(n, nvm, rc, cc);
-    case 3: return bwd ? fast_occupancy<NINT, 3, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 3, false>(n, nvm, rc, cc);
-    default: return bwd ? fast_occupancy<NINT, 4, true>(n, nvm, rc, cc) : fast_occupancy<NINT, 4, false>(n, nvm, rc, cc);
-    }
-}
-
-int fast_grid(qp_ctx *c, int nint, int ns, bool bwd, int nvm, int rc, int cc)
-{
-    int per_cu = 8;
-    switch (nint) {
-    case 1: per_cu = focc_ns<1>(c->n, nvm, ns, bwd, rc, cc); break;
-    case 2: per_cu = focc_ns<2>(c->n, nvm, ns, bwd, rc, cc); break;
-    case 3: per_cu = focc_ns<3>(c->n, nvm, ns, bwd, rc, cc); break;
-    default: per_cu = focc_ns<4>(c->n, nvm, ns, bwd, rc, cc); break;
+    case 1: per_cu = dense ? fast_occ_t<1>(ns, bwd, lds) : sweep_occ_t<1>(ns, bwd, lds); break;
+    case 2: per_cu = dense ? fast_occ_t<2>(ns, bwd, lds) : sweep_occ_t<2>(ns, bwd, lds); break;
+    case 3: per_cu = dense ? fast_occ_t<3>(ns, bwd, lds) : sweep_occ_t<3>(ns, bwd, lds); break;
+    default: per_cu = dense ? fast_occ_t<4>(ns, bwd, lds) : sweep_occ_t<4>(ns, bwd, lds); break;
     }
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
@@ -935,20 +997,38 @@ int fast_grid(qp_ctx *c, int nint, int ns, bool bwd, int nvm, int rc, int cc)
 }
 
 template <int NINT, int NS>
-void fast_dispatch_ns(const SweepArgs &a, int grid, bool bwd, hipStream_t st)
+void launch_ns(bool dense, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd, bool fp, size_t lds,
+               int grid, hipStream_t st)
 {
-    if (bwd) launch_fast<NINT, NS, true>(a, grid, st);
-    else launch_fast<NINT, NS, false>(a, grid, st);
+    if (dense) {
+        if (bwd) launch_fast<NINT, NS, true>(sys, end, n_sys, fp, lds, grid, st);
+        else launch_fast<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
+    } else {
+        if (bwd) launch_sweep<NINT, NS, true>(sys, end, n_sys, lds, grid, st);
+        else launch_sweep<NINT, NS, false>(sys, end, n_sys, lds, grid, st);
+    }
 }
 
 template <int NINT>
-void fast_dispatch(const SweepArgs &a, int grid, bool bwd, hipStream_t st)
+void launch_nint(bool dense, int ns, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd, bool fp,
+                 size_t lds, int grid, hipStream_t st)
 {
-    switch (a.ns) {
-    case 1: fast_dispatch_ns<NINT, 1>(a, grid, bwd, st); break;
-    case 2: fast_dispatch_ns<NINT, 2>(a, grid, bwd, st); break;
-    case 3: fast_dispatch_ns<NINT, 3>(a, grid, bwd, st); break;
-    default: fast_dispatch_ns<NINT, 4>(a, grid, bwd, st); break;
+    switch (ns) {
+    case 1: launch_ns<NINT, 1>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 2: launch_ns<NINT, 2>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 3: launch_ns<NINT, 3>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    default: launch_ns<NINT, 4>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    }
+}
+
+void launch_kernel(bool dense, int nint, int ns, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd,
+                   bool fp, size_t lds, int grid, hipStream_t st)
+{
+    switch (nint) {
+    case 1: launch_nint<1>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 2: launch_nint<2>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 3: launch_nint<3>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    default: launch_nint<4>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
     }
 }
 
@@ -969,194 +1049,381 @@ int items_per_generator(int64_t n_det, int nb, bool bwd)
     return std::max(q, 1);
 }
 
-int run_sweep(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int ns, const double *E0,
-              int64_t n_select, int flags, bool bwd, const double *gup, double *e_pt2, uint64_t *sel_dets,
-              double *sel_e, int64_t *n_sel, qp_pt2_stats *stats, double *eps_gen, double *grad_coefs,
-              double *grad_E0, double *grad_h, hipStream_t st)
-{
-    const int n = c->n;
-    const int nint = (n - 1) / 64 + 1;
-    c->timed = false;
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], st));
+// one system of a sweep call
+struct SysIn {
+    DevInts I;
+    const uint64_t *dets;
+    const double *coefs;
+    int64_t n_det;
+    int ns;
+    const double *E0;
+    int64_t n_select;
+    double *e_pt2;
+    uint64_t *sel_dets;
+    double *sel_e;
+    int64_t *n_sel;
+    qp_pt2_stats *stats;
+    double *eps_gen;
+    const double *gup;
+    double *grad_coefs, *grad_E0, *grad_h;
+};
+
+// per-system state between the phases of a sweep call
+struct SysRun {
+    int slot = 0;
+    int nint = 1;
+    bool swept = false;         // has dense-kernel items
     Prepared P;
-    int rc = prepare(c, nint, dets, coefs, n_det, ns, flags, st, P);
-    if (rc != QP_OK) return rc;
-    const int nel = P.nel;
-    const int Q = items_per_generator(n_det, nel + nel * (nel - 1) / 2, bwd);
-    const int64_t n_items = n_det * Q;
-    double *eps_item = (double *)scratch(c, B_EPSI, sizeof(double) * std::max<int64_t>(1, n_items) * ns);
-    double *S_item = (double *)scratch(c, B_SI, sizeof(double) * std::max<int64_t>(1, n_items) * ns);
-    uint32_t *cnt_item = (uint32_t *)scratch(c, B_CNTI, sizeof(uint32_t) * std::max<int64_t>(1, n_items));
-    uint64_t *fp_item = (uint64_t *)scratch(c, B_FPI, sizeof(uint64_t) * std::max<int64_t>(1, n_items));
-    double *dc_item = bwd ? (double *)scratch(c, B_DCI, sizeof(double) * std::max<int64_t>(1, n_items) * ns) : nullptr;
-    double *eps_g = (double *)scratch(c, B_EPSG, sizeof(double) * n_det * ns);
-    double *S_g = (double *)scratch(c, B_SG, sizeof(double) * n_det * ns);
-    uint64_t *cnt_g = (uint64_t *)scratch(c, B_CNTG, sizeof(uint64_t) * n_det);
-    uint64_t *fp_g = (uint64_t *)scratch(c, B_FPG, sizeof(uint64_t) * n_det);
-    unsigned int *hist = (unsigned int *)scratch(c, B_HIST, sizeof(unsigned int) * QP_HIST_BINS);
-    if (!eps_item || !S_item || !cnt_item || !fp_item || (bwd && !dc_item) || !eps_g || !S_g || !cnt_g || !fp_g || !hist)
-        return fail(c, QP_E_OOM, "device allocation failed (sweep buffers)");
-    const int rscap = n <= 128 ? 6 : 3, cscap = n <= 128 ? 6 : 3;
-    const int fgrid = fast_grid(c, nint, ns, bwd, n - std::min(P.nup, P.ndn), rscap, cscap);
-    const int ggrid = sweep_grid(c, nint, ns, bwd);
-    const int grid = std::max(fgrid, ggrid);
-    // batches the dense kernel hands to the general kernel: one bit per
-    // (generator rank, batch), then a list in (rank, batch) order
-    const int nb = nel + nel * (nel - 1) / 2;
-    const int nbw = std::max(1, (nb + 31) / 32);
-    uint32_t *conn_item = (uint32_t *)scratch(c, B_CONNI, sizeof(uint32_t) * std::max<int64_t>(1, n_items));
-    uint64_t *conn_g = (uint64_t *)scratch(c, B_CONNG, sizeof(uint64_t) * n_det);
-    uint64_t *defa_g = (uint64_t *)scratch(c, B_DEFAG, sizeof(uint64_t) * n_det);
-    uint32_t *def_bits = (uint32_t *)scratch(c, B_DEFBITS, sizeof(uint32_t) * n_det * nbw);
-    int32_t *def_cnt_g = (int32_t *)scratch(c, B_DEFCG, sizeof(int32_t) * n_det);
-    int64_t *def_off = (int64_t *)scratch(c, B_DEFOFF, sizeof(int64_t) * n_det);
-    const int64_t nsb = (n_det + 1023) / 1024;
-    int64_t *def_bsum = (int64_t *)scratch(c, B_DEFBS, sizeof(int64_t) * std::max<int64_t>(1, nsb));
-    if (!conn_item || !conn_g || !defa_g || !def_bits || !def_cnt_g || !def_off || !def_bsum)
-        return fail(c, QP_E_OOM, "device allocation failed (deferred batches)");
-    HIPCHK(c, hipMemsetAsync(def_bits, 0, sizeof(uint32_t) * n_det * nbw, st));
+    int Q = 1;
+    int64_t n_items = 0;
+    int nbw = 1;
+    int64_t nsb = 1;
+    SweepArgs a;
     int64_t cand_cap = 0;
     Cand *cand = nullptr;
-    if (n_select > 0) {
-        const int64_t maxcell = std::max<int64_t>((int64_t)(n - P.nup) * (n - P.ndn), (int64_t)(n - P.nup) * (n - P.nup - 1) / 2);
-        cand_cap = n_select + std::max<int64_t>(1 << 22, 2 * (int64_t)grid * std::min<int64_t>(maxcell, 3072));
-        cand = (Cand *)scratch(c, B_CAND, sizeof(Cand) * cand_cap);
-        if (!cand) return fail(c, QP_E_OOM, "device allocation failed (selection candidates)");
-        HIPCHK(c, hipMemsetAsync(hist, 0, sizeof(unsigned int) * QP_HIST_BINS, st));
-    }
-    if (bwd) {
-        if (grad_coefs) HIPCHK(c, hipMemsetAsync(grad_coefs, 0, sizeof(double) * ns * n_det, st));
-        if (grad_h) HIPCHK(c, hipMemsetAsync(grad_h, 0, sizeof(double) * n * n, st));
-    }
-    double hmax[QPD_MAX_STATES];
-    HIPCHK(c, hipMemcpyAsync(hmax, P.maxc2, sizeof(double) * QPD_MAX_STATES, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-
-    SweepArgs a;
-    memset(&a, 0, sizeof(a));
-    a.I = dev_ints(c);
-    a.n = n; a.nup = P.nup; a.ndn = P.ndn; a.ns = ns; a.nel = nel;
-    a.n_det = n_det; a.dets = dets; a.coefs = coefs; a.E0 = E0;
-    a.perm = P.perm; a.F = P.F; a.HII = P.HII; a.coff = P.coff; a.cent = P.cent;
-    a.n_items = n_items;
-    a.q_per_gen = Q;
-    a.flags = ((flags & QP_FLAG_FINGERPRINT) ? 1 : 0) | (bwd ? 2 : 0);
-    a.eps_item = eps_item; a.S_item = S_item; a.cnt_item = cnt_item; a.fp_item = fp_item; a.conn_item = conn_item;
-    a.min_delta_bits = &P.sc->min_delta_bits;
-    a.n_select = n_select;
-    for (int k = 0; k < QPD_MAX_STATES; ++k) {
-        a.maxc2[k] = k < ns ? hmax[k] : 1.0;
-        a.inv_maxc2[k] = k < ns ? 1.0 / hmax[k] : 0.0;
-    }
-    a.cand = cand; a.cand_count = &P.sc->cand_count; a.cand_cap = cand_cap; a.hist = hist;
-    a.tau_bin = &P.sc->tau_bin; a.overflow = &P.sc->overflow;
-    a.gup = gup; a.dc_item = dc_item; a.dc = grad_coefs; a.dh = grad_h;
-    a.rscap = rscap; a.cscap = cscap;
-    a.def_bits = def_bits; a.nbw = nbw;
-    a.def_mode = 0;
-
+    uint32_t *def_bits = nullptr;
+    int32_t *def_cnt_g = nullptr;
+    int64_t *def_off = nullptr, *def_bsum = nullptr;
+    double *eps_item = nullptr, *S_item = nullptr, *dc_item = nullptr;
+    uint32_t *cnt_item = nullptr, *conn_item = nullptr;
+    uint64_t *fp_item = nullptr;
+    double *eps_g = nullptr, *S_g = nullptr;
+    uint64_t *cnt_g = nullptr, *fp_g = nullptr, *conn_g = nullptr, *defa_g = nullptr;
     int64_t n_def = 0;
-    double *def_eps = nullptr, *def_S = nullptr, *def_dc = nullptr;
-    uint32_t *def_alpha = nullptr, *def_conn = nullptr;
-    uint64_t *def_fp = nullptr;
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], st));
-    if (n_items > 0 && nel > 0) {
-        switch (nint) {
-        case 1: fast_dispatch<1>(a, fgrid, bwd, st); break;
-        case 2: fast_dispatch<2>(a, fgrid, bwd, st); break;
-        case 3: fast_dispatch<3>(a, fgrid, bwd, st); break;
-        default: fast_dispatch<4>(a, fgrid, bwd, st); break;
-        }
-        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
-        HIPCHK(c, hipGetLastError());
-        hipLaunchKernelGGL(def_count, dim3(grid_for(n_det)), dim3(256), 0, st, def_bits, n_det, nbw, def_cnt_g);
-        hipLaunchKernelGGL(scan_block, dim3((unsigned)nsb), dim3(256), 0, st, def_cnt_g, n_det, def_off, def_bsum);
-        hipLaunchKernelGGL(scan_bsum, dim3(1), dim3(1), 0, st, def_bsum, nsb, (int64_t *)&P.sc->def_count);
-        hipLaunchKernelGGL(scan_add, dim3(grid_for(n_det, 256, 1 << 30)), dim3(256), 0, st, def_off, n_det, def_bsum);
-        HIPCHK(c, hipMemcpyAsync(&n_def, &P.sc->def_count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        HIPCHK(c, hipGetLastError());
-        const int64_t m = std::max<int64_t>(1, n_def);
-        uint32_t *def_g = (uint32_t *)scratch(c, B_DEFG, sizeof(uint32_t) * m);
-        uint32_t *def_b = (uint32_t *)scratch(c, B_DEFB, sizeof(uint32_t) * m);
-        def_eps = (double *)scratch(c, B_DEFE, sizeof(double) * m * ns);
-        def_S = (double *)scratch(c, B_DEFS, sizeof(double) * m * ns);
-        def_alpha = (uint32_t *)scratch(c, B_DEFC, sizeof(uint32_t) * m);
-        def_conn = (uint32_t *)scratch(c, B_DEFN, sizeof(uint32_t) * m);
-        def_fp = (uint64_t *)scratch(c, B_DEFF, sizeof(uint64_t) * m);
-        def_dc = bwd ? (double *)scratch(c, B_DEFD, sizeof(double) * m * ns) : nullptr;
-        if (!def_g || !def_b || !def_eps || !def_S || !def_alpha || !def_conn || !def_fp || (bwd && !def_dc))
-            return fail(c, QP_E_OOM, "device allocation failed (deferred batches)");
-        if (n_def > 0) {
-            hipLaunchKernelGGL(def_fill, dim3(grid_for(n_det)), dim3(256), 0, st, def_bits, n_det, nbw, def_off,
-                               def_g, def_b);
-            // the general kernel on the listed batches: its own slots
-            SweepArgs d = a;
-            d.def_mode = 1;
-            d.def_g = def_g; d.def_b = def_b; d.def_n = (const int64_t *)&P.sc->def_count;
-            d.eps_item = def_eps; d.S_item = def_S; d.cnt_item = def_alpha; d.fp_item = def_fp;
-            d.conn_item = def_conn; d.dc_item = def_dc;
-            const int dgrid = (int)std::min<int64_t>(ggrid, n_def);
-            switch (nint) {
-            case 1: sweep_dispatch<1>(d, dgrid, bwd, st); break;
-            case 2: sweep_dispatch<2>(d, dgrid, bwd, st); break;
-            case 3: sweep_dispatch<3>(d, dgrid, bwd, st); break;
-            default: sweep_dispatch<4>(d, dgrid, bwd, st); break;
-            }
-            HIPCHK(c, hipGetLastError());
-        }
-        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], st));
-    } else {
-        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
-        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], st));
-    }
+    SweepArgs d;
     DefParts dp;
-    memset(&dp, 0, sizeof(dp));
-    dp.off = def_off; dp.cnt = def_cnt_g; dp.eps = def_eps; dp.S = def_S; dp.dc = def_dc;
-    dp.alpha = def_alpha; dp.conn = def_conn; dp.fp = def_fp;
-    if (n_items > 0 && nel > 0)
-        hipLaunchKernelGGL(reduce_items, dim3(grid_for(n_det)), dim3(256), 0, st, eps_item, S_item, cnt_item,
-                           (flags & QP_FLAG_FINGERPRINT) ? fp_item : (const uint64_t *)nullptr, conn_item, dc_item,
-                           n_det, Q, ns, P.perm, eps_g, S_g, cnt_g, fp_g, conn_g, defa_g, bwd ? nullptr : eps_gen,
-                           bwd ? grad_coefs : nullptr, dp);
-    else
-        hipLaunchKernelGGL(reduce_empty, dim3(grid_for(n_det)), dim3(256), 0, st, n_det, ns, P.perm, eps_g, S_g,
-                           cnt_g, fp_g, conn_g, defa_g, bwd ? nullptr : eps_gen);
-    const int64_t n_cells = n_det * cells_per_generator(n, P.nup, P.ndn);
-    hipLaunchKernelGGL(reduce_total, dim3(1), dim3(256), 0, st, eps_g, S_g, cnt_g, fp_g, conn_g, defa_g, n_det, ns,
-                       bwd ? nullptr : e_pt2, stats, P.sc, n_cells, gup, bwd ? grad_E0 : nullptr);
-    HIPCHK(c, hipGetLastError());
+};
 
-    if (!bwd && n_select > 0) {
-        int32_t *comp = (int32_t *)scratch(c, B_COMP, sizeof(int32_t) * cand_cap);
-        if (!comp) return fail(c, QP_E_OOM, "device allocation failed (selection)");
-        hipLaunchKernelGGL(sel_compact, dim3(grid_for(cand_cap, 256, 8192)), dim3(256), 0, st, cand, P.sc, cand_cap,
-                           comp, P.sc);
-        HIPCHK(c, hipMemcpyAsync(c->host_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+// the launches of one kernel over several systems: one per (n_int, n_states)
+// class, each system's items in system order
+struct LaunchPlan {
+    int nint, ns;
+    size_t lds;
+    int grid;
+    std::vector<int> sys;       // indices into the call's systems
+    std::vector<int64_t> end;   // running item end per listed system
+};
+
+std::vector<LaunchPlan> plan_launches(qp_ctx *c, bool dense, bool bwd, const std::vector<SysIn> &in,
+                                      const std::vector<SysRun> &run, const std::vector<int64_t> &items)
+{
+    std::vector<LaunchPlan> plans;
+    for (size_t s = 0; s < in.size(); ++s) {
+        if (items[s] <= 0) continue;
+        const int nint = run[s].nint, ns = in[s].ns, n = in[s].I.n;
+        size_t lds;
+        if (dense) {
+            const int nvm = n - std::min(run[s].P.nup, run[s].P.ndn);
+            lds = fast_lds_bytes(n, nvm, ns, bwd, run[s].a.rscap, run[s].a.cscap);
+        } else {
+            lds = sweep_lds_bytes(n, ns, bwd);
+        }
+        LaunchPlan *p = nullptr;
+        for (auto &q : plans) if (q.nint == nint && q.ns == ns) p = &q;
+        if (!p) {
+            plans.push_back(LaunchPlan{nint, ns, 0, 0, {}, {}});
+            p = &plans.back();
+        }
+        p->lds = std::max(p->lds, lds);
+        p->sys.push_back((int)s);
+        p->end.push_back((p->end.empty() ? 0 : p->end.back()) + items[s]);
+    }
+    for (auto &p : plans) p.grid = persistent_grid(c, dense, p.nint, p.ns, bwd, p.lds);
+    return plans;
+}
+
+// copy the plans' descriptors to the device in one transfer and launch them
+int launch_plans(qp_ctx *c, bool dense, bool bwd, bool fp, std::vector<LaunchPlan> &plans,
+                 const std::vector<SysRun> &run, hipStream_t st)
+{
+    if (plans.empty()) return QP_OK;
+    size_t nsys = 0;
+    for (auto &p : plans) nsys += p.sys.size();
+    const size_t args_bytes = sizeof(SweepArgs) * nsys;
+    const size_t bytes = args_bytes + sizeof(int64_t) * nsys;
+    // the staging area is reused only after a host synchronisation on `st`,
+    // which every call performs between its two launch rounds
+    unsigned char *stage = c->host_stage + (dense ? 0 : c->host_stage_bytes / 2);
+    if (bytes > c->host_stage_bytes / 2) return fail(c, QP_E_ARG, "staging area too small");
+    unsigned char *dev = (unsigned char *)grow(c->args[dense ? 0 : 1], bytes);
+    if (!dev) return fail(c, QP_E_OOM, "device allocation failed (system descriptors)");
+    SweepArgs *ha = (SweepArgs *)stage;
+    int64_t *he = (int64_t *)(stage + args_bytes);
+    size_t k = 0;
+    for (auto &p : plans)
+        for (size_t i = 0; i < p.sys.size(); ++i, ++k) {
+            ha[k] = dense ? run[p.sys[i]].a : run[p.sys[i]].d;
+            he[k] = p.end[i];
+        }
+    HIPCHK(c, hipMemcpyAsync(dev, stage, bytes, hipMemcpyHostToDevice, st));
+    k = 0;
+    for (auto &p : plans) {
+        const SweepArgs *da = (const SweepArgs *)dev + k;
+        const int64_t *de = (const int64_t *)(dev + args_bytes) + k;
+        int grid = p.grid;
+        if (!dense) grid = (int)std::min<int64_t>(grid, p.end.back());
+        launch_kernel(dense, p.nint, p.ns, da, de, (int)p.sys.size(), bwd, fp, p.lds, grid, st);
+        HIPCHK(c, hipGetLastError());
+        k += p.sys.size();
+    }
+    return QP_OK;
+}
+
+// The sweep over one or more systems (bwd: the adjoint sweep, which also
+// yields E_PT2).  Phases, each over all systems: preparation (one host sync
+// per system), the dense kernel, the deferred-batch lists (one host sync), the
+// general kernel, the deterministic reductions, and the selection (one host
+// sync).
+int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream_t st)
+{
+    const int n_sys = (int)in.size();
+    c->timed = false;
+    if (n_sys == 0) return QP_OK;
+    {
+        int rc = host_space(c, std::max<size_t>(1 << 16, 2 * (sizeof(SweepArgs) + 8) * (size_t)n_sys + 256), n_sys);
+        if (rc != QP_OK) return rc;
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], st));
+    std::vector<SysRun> run(n_sys);
+    std::vector<int64_t> items(n_sys, 0);
+    const bool fp = (flags & QP_FLAG_FINGERPRINT) != 0;
+
+    // ------------------------------------------------------------ phase 1
+    for (int s = 0; s < n_sys; ++s) {
+        SysIn &x = in[s];
+        SysRun &r = run[s];
+        r.slot = s;
+        const int n = x.I.n;
+        const int ns = x.ns;
+        r.nint = (n - 1) / 64 + 1;
+        if (x.n_det == 0) {
+            if (x.e_pt2) HIPCHK(c, hipMemsetAsync(x.e_pt2, 0, sizeof(double) * ns, st));
+            if (x.stats) HIPCHK(c, hipMemsetAsync(x.stats, 0, sizeof(qp_pt2_stats), st));
+            if (x.n_sel) HIPCHK(c, hipMemsetAsync(x.n_sel, 0, sizeof(int64_t), st));
+            if (bwd && x.grad_E0) HIPCHK(c, hipMemsetAsync(x.grad_E0, 0, sizeof(double) * ns, st));
+            if (bwd && x.grad_h) HIPCHK(c, hipMemsetAsync(x.grad_h, 0, sizeof(double) * n * n, st));
+            continue;
+        }
+        int rc = prepare(c, s, x.I, x.dets, x.coefs, x.n_det, ns, flags, st, r.P);
+        if (rc != QP_OK) return rc;
+        const int64_t n_det = x.n_det;
+        const int nel = r.P.nel;
+        const int nb = nel + nel * (nel - 1) / 2;
+        r.Q = items_per_generator(n_det, nb, bwd);
+        r.n_items = n_det * r.Q;
+        r.swept = r.n_items > 0 && nel > 0;
+        const int64_t ni = std::max<int64_t>(1, r.n_items);
+        r.eps_item = (double *)scratch(c, s, B_EPSI, sizeof(double) * ni * ns);
+        r.S_item = (double *)scratch(c, s, B_SI, sizeof(double) * ni * ns);
+        r.cnt_item = (uint32_t *)scratch(c, s, B_CNTI, sizeof(uint32_t) * ni);
+        r.fp_item = (uint64_t *)scratch(c, s, B_FPI, sizeof(uint64_t) * ni);
+        r.dc_item = bwd ? (double *)scratch(c, s, B_DCI, sizeof(double) * ni * ns) : nullptr;
+        r.conn_item = (uint32_t *)scratch(c, s, B_CONNI, sizeof(uint32_t) * ni);
+        r.eps_g = (double *)scratch(c, s, B_EPSG, sizeof(double) * n_det * ns);
+        r.S_g = (double *)scratch(c, s, B_SG, sizeof(double) * n_det * ns);
+        r.cnt_g = (uint64_t *)scratch(c, s, B_CNTG, sizeof(uint64_t) * n_det);
+        r.fp_g = (uint64_t *)scratch(c, s, B_FPG, sizeof(uint64_t) * n_det);
+        r.conn_g = (uint64_t *)scratch(c, s, B_CONNG, sizeof(uint64_t) * n_det);
+        r.defa_g = (uint64_t *)scratch(c, s, B_DEFAG, sizeof(uint64_t) * n_det);
+        unsigned int *hist = (unsigned int *)scratch(c, s, B_HIST, sizeof(unsigned int) * QP_HIST_BINS);
+        // batches the dense kernel hands to the general kernel: one bit per
+        // (generator rank, batch), then a list in (rank, batch) order
+        r.nbw = std::max(1, (nb + 31) / 32);
+        r.def_bits = (uint32_t *)scratch(c, s, B_DEFBITS, sizeof(uint32_t) * n_det * r.nbw);
+        r.def_cnt_g = (int32_t *)scratch(c, s, B_DEFCG, sizeof(int32_t) * n_det);
+        r.def_off = (int64_t *)scratch(c, s, B_DEFOFF, sizeof(int64_t) * n_det);
+        r.nsb = (n_det + 1023) / 1024;
+        r.def_bsum = (int64_t *)scratch(c, s, B_DEFBS, sizeof(int64_t) * std::max<int64_t>(1, r.nsb));
+        if (!r.eps_item || !r.S_item || !r.cnt_item || !r.fp_item || (bwd && !r.dc_item) || !r.conn_item ||
+            !r.eps_g || !r.S_g || !r.cnt_g || !r.fp_g || !r.conn_g || !r.defa_g || !hist || !r.def_bits ||
+            !r.def_cnt_g || !r.def_off || !r.def_bsum)
+            return fail(c, QP_E_OOM, "device allocation failed (sweep buffers)");
+        HIPCHK(c, hipMemsetAsync(r.def_bits, 0, sizeof(uint32_t) * n_det * r.nbw, st));
+        const int rscap = n <= 128 ? 6 : 3, cscap = n <= 128 ? 6 : 3;
+        if (x.n_select > 0) {
+            const int nvm = n - std::min(r.P.nup, r.P.ndn);
+            const int grid = std::max(persistent_grid(c, true, r.nint, ns, bwd,
+                                                      fast_lds_bytes(n, nvm, ns, bwd, rscap, cscap)),
+                                      persistent_grid(c, false, r.nint, ns, bwd, sweep_lds_bytes(n, ns, bwd)));
+            const int64_t maxcell = std::max<int64_t>((int64_t)(n - r.P.nup) * (n - r.P.ndn),
+                                                      (int64_t)(n - r.P.nup) * (n - r.P.nup - 1) / 2);
+            r.cand_cap = x.n_select + std::max<int64_t>(1 << 22, 2 * (int64_t)grid * std::min<int64_t>(maxcell, 3072));
+            r.cand = (Cand *)scratch(c, s, B_CAND, sizeof(Cand) * r.cand_cap);
+            if (!r.cand) return fail(c, QP_E_OOM, "device allocation failed (selection candidates)");
+            HIPCHK(c, hipMemsetAsync(hist, 0, sizeof(unsigned int) * QP_HIST_BINS, st));
+        }
+        if (bwd) {
+            if (x.grad_coefs) HIPCHK(c, hipMemsetAsync(x.grad_coefs, 0, sizeof(double) * ns * n_det, st));
+            if (x.grad_h) HIPCHK(c, hipMemsetAsync(x.grad_h, 0, sizeof(double) * n * n, st));
+        }
+        SweepArgs &a = r.a;
+        memset(&a, 0, sizeof(a));
+        a.I = x.I;
+        a.n = n; a.nup = r.P.nup; a.ndn = r.P.ndn; a.ns = ns; a.nel = nel;
+        a.n_det = n_det; a.dets = x.dets; a.coefs = x.coefs; a.E0 = x.E0;
+        a.perm = r.P.perm; a.F = r.P.F; a.HII = r.P.HII; a.coff = r.P.coff; a.cent = r.P.cent;
+        a.n_items = r.n_items;
+        a.q_per_gen = r.Q;
+        a.flags = (fp ? 1 : 0) | (bwd ? 2 : 0);
+        a.eps_item = r.eps_item; a.S_item = r.S_item; a.cnt_item = r.cnt_item; a.fp_item = r.fp_item;
+        a.conn_item = r.conn_item;
+        a.min_delta_bits = &r.P.sc->min_delta_bits;
+        a.n_select = x.n_select;
+        for (int k = 0; k < QPD_MAX_STATES; ++k) {
+            a.maxc2[k] = k < ns ? r.P.hmax[k] : 1.0;
+            a.inv_maxc2[k] = k < ns ? 1.0 / r.P.hmax[k] : 0.0;
+        }
+        a.cand = r.cand; a.cand_count = &r.P.sc->cand_count; a.cand_cap = r.cand_cap; a.hist = hist;
+        a.tau_bin = &r.P.sc->tau_bin; a.overflow = &r.P.sc->overflow;
+        a.gup = x.gup; a.dc_item = r.dc_item; a.dc = x.grad_coefs; a.dh = x.grad_h;
+        a.rscap = rscap; a.cscap = cscap;
+        a.def_bits = r.def_bits; a.nbw = r.nbw;
+        a.def_mode = 0;
+        items[s] = r.swept ? r.n_items : 0;
+    }
+
+    // ------------------------------------------------- phase 2: dense kernel
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], st));
+    {
+        std::vector<LaunchPlan> plans = plan_launches(c, true, bwd, in, run, items);
+        int rc = launch_plans(c, true, bwd, fp, plans, run, st);
+        if (rc != QP_OK) return rc;
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
+
+    // -------------------------------------- phase 3: lists of handed-over batches
+    int64_t *def_n = (int64_t *)grow(c->defn, sizeof(int64_t) * n_sys);
+    if (!def_n) return fail(c, QP_E_OOM, "device allocation failed (deferred counts)");
+    HIPCHK(c, hipMemsetAsync(def_n, 0, sizeof(int64_t) * n_sys, st));
+    bool any = false;
+    for (int s = 0; s < n_sys; ++s) {
+        SysRun &r = run[s];
+        if (!r.swept) continue;
+        any = true;
+        const int64_t n_det = in[s].n_det;
+        hipLaunchKernelGGL(def_count, dim3(grid_for(n_det)), dim3(256), 0, st, r.def_bits, n_det, r.nbw, r.def_cnt_g);
+        hipLaunchKernelGGL(scan_block, dim3((unsigned)r.nsb), dim3(256), 0, st, r.def_cnt_g, n_det, r.def_off,
+                           r.def_bsum);
+        hipLaunchKernelGGL(scan_bsum, dim3(1), dim3(1), 0, st, r.def_bsum, r.nsb, def_n + s);
+        hipLaunchKernelGGL(scan_add, dim3(grid_for(n_det, 256, 1 << 30)), dim3(256), 0, st, r.def_off, n_det,
+                           r.def_bsum);
+    }
+    std::vector<int64_t> gitems(n_sys, 0);
+    if (any) {
+        int64_t *hn = (int64_t *)c->host_stage;   // the dense round's staging has been consumed by now
+        HIPCHK(c, hipMemcpyAsync(hn, def_n, sizeof(int64_t) * n_sys, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        const Scalars hs = *c->host_sc;
-        if (hs.overflow & 1ull) return fail(c, QP_E_OVERFLOW, "selection candidate buffer overflowed");
-        const int64_t M = (int64_t)hs.comp_count;
-        const int64_t m = std::min<int64_t>(M, n_select);
-        const int64_t PP = pow2_at_least(std::max<int64_t>(M, 1));
-        uint64_t *skey = (uint64_t *)scratch(c, B_SKEY, sizeof(uint64_t) * PP);
-        uint64_t *sbits = (uint64_t *)scratch(c, B_SBITS, sizeof(uint64_t) * PP * 2 * nint);
-        int32_t *sidx = (int32_t *)scratch(c, B_SIDX, sizeof(int32_t) * PP);
-        if (!skey || !sbits || !sidx) return fail(c, QP_E_OOM, "device allocation failed (selection sort)");
-        switch (nint) {
+        HIPCHK(c, hipGetLastError());
+        for (int s = 0; s < n_sys; ++s) run[s].n_def = run[s].swept ? hn[s] : 0;
+        for (int s = 0; s < n_sys; ++s) {
+            SysRun &r = run[s];
+            if (!r.swept) continue;
+            const int ns = in[s].ns;
+            const int64_t m = std::max<int64_t>(1, r.n_def);
+            uint32_t *def_g = (uint32_t *)scratch(c, s, B_DEFG, sizeof(uint32_t) * m);
+            uint32_t *def_b = (uint32_t *)scratch(c, s, B_DEFB, sizeof(uint32_t) * m);
+            double *def_eps = (double *)scratch(c, s, B_DEFE, sizeof(double) * m * ns);
+            double *def_S = (double *)scratch(c, s, B_DEFS, sizeof(double) * m * ns);
+            uint32_t *def_alpha = (uint32_t *)scratch(c, s, B_DEFC, sizeof(uint32_t) * m);
+            uint32_t *def_conn = (uint32_t *)scratch(c, s, B_DEFN, sizeof(uint32_t) * m);
+            uint64_t *def_fp = (uint64_t *)scratch(c, s, B_DEFF, sizeof(uint64_t) * m);
+            double *def_dc = bwd ? (double *)scratch(c, s, B_DEFD, sizeof(double) * m * ns) : nullptr;
+            if (!def_g || !def_b || !def_eps || !def_S || !def_alpha || !def_conn || !def_fp || (bwd && !def_dc))
+                return fail(c, QP_E_OOM, "device allocation failed (deferred batches)");
+            r.dp.eps = def_eps; r.dp.S = def_S; r.dp.alpha = def_alpha; r.dp.conn = def_conn; r.dp.fp = def_fp;
+            r.dp.dc = def_dc;
+            r.dp.off = r.def_off;
+            r.dp.cnt = r.def_cnt_g;
+            if (r.n_def > 0) {
+                hipLaunchKernelGGL(def_fill, dim3(grid_for(in[s].n_det)), dim3(256), 0, st, r.def_bits, in[s].n_det,
+                                   r.nbw, r.def_off, def_g, def_b);
+                // the general kernel on the listed batches: its own slots
+                SweepArgs &d = r.d;
+                d = r.a;
+                d.def_mode = 1;
+                d.def_g = def_g; d.def_b = def_b;
+                d.n_items = r.n_def;
+                d.eps_item = def_eps; d.S_item = def_S; d.cnt_item = def_alpha; d.fp_item = def_fp;
+                d.conn_item = def_conn; d.dc_item = def_dc;
+                gitems[s] = r.n_def;
+            }
+        }
+    }
+    // ------------------------------------------------ phase 4: general kernel
+    {
+        std::vector<LaunchPlan> plans = plan_launches(c, false, bwd, in, run, gitems);
+        int rc = launch_plans(c, false, bwd, fp, plans, run, st);
+        if (rc != QP_OK) return rc;
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], st));
+
+    // ---------------------------------------------------- phase 5: reductions
+    for (int s = 0; s < n_sys; ++s) {
+        SysIn &x = in[s];
+        SysRun &r = run[s];
+        if (x.n_det == 0) continue;
+        const int ns = x.ns;
+        if (r.swept)
+            hipLaunchKernelGGL(reduce_items, dim3(grid_for(x.n_det)), dim3(256), 0, st, r.eps_item, r.S_item,
+                               r.cnt_item, fp ? r.fp_item : (const uint64_t *)nullptr, r.conn_item, r.dc_item,
+                               x.n_det, r.Q, ns, r.P.perm, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g, r.defa_g,
+                               bwd ? nullptr : x.eps_gen, bwd ? x.grad_coefs : nullptr, r.dp);
+        else
+            hipLaunchKernelGGL(reduce_empty, dim3(grid_for(x.n_det)), dim3(256), 0, st, x.n_det, ns, r.P.perm,
+                               r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g, r.defa_g, bwd ? nullptr : x.eps_gen);
+        const int64_t n_cells = x.n_det * cells_per_generator(x.I.n, r.P.nup, r.P.ndn);
+        hipLaunchKernelGGL(reduce_total, dim3(1), dim3(256), 0, st, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
+                           r.defa_g, x.n_det, ns, x.e_pt2, x.stats, r.P.sc, n_cells, x.gup,
+                           bwd ? x.grad_E0 : nullptr, x.E0);
+        HIPCHK(c, hipGetLastError());
+    }
+
+    // ----------------------------------------------------- phase 6: selection
+    if (!bwd) {
+        bool sel = false;
+        for (int s = 0; s < n_sys; ++s) {
+            SysRun &r = run[s];
+            if (in[s].n_det == 0 || in[s].n_select <= 0) continue;
+            sel = true;
+            int32_t *comp = (int32_t *)scratch(c, s, B_COMP, sizeof(int32_t) * r.cand_cap);
+            if (!comp) return fail(c, QP_E_OOM, "device allocation failed (selection)");
+            hipLaunchKernelGGL(sel_compact, dim3(grid_for(r.cand_cap, 256, 8192)), dim3(256), 0, st, r.cand, r.P.sc,
+                               r.cand_cap, comp, r.P.sc);
+            HIPCHK(c, hipMemcpyAsync(c->host_sc + s, r.P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        }
+        if (sel) {
+            HIPCHK(c, hipStreamSynchronize(st));
+            for (int s = 0; s < n_sys; ++s) {
+                SysIn &x = in[s];
+                SysRun &r = run[s];
+                if (x.n_det == 0 || x.n_select <= 0) continue;
+                const Scalars hs = c->host_sc[s];
+                if (hs.overflow & 1ull) return fail(c, QP_E_OVERFLOW, "selection candidate buffer overflowed");
+                const int64_t M = (int64_t)hs.comp_count;
+                const int64_t m = std::min<int64_t>(M, x.n_select);
+                const int64_t PP = pow2_at_least(std::max<int64_t>(M, 1));
+                const int nint = r.nint;
+                int32_t *comp = (int32_t *)scratch(c, s, B_COMP, sizeof(int32_t) * r.cand_cap);
+                uint64_t *skey = (uint64_t *)scratch(c, s, B_SKEY, sizeof(uint64_t) * PP);
+                uint64_t *sbits = (uint64_t *)scratch(c, s, B_SBITS, sizeof(uint64_t) * PP * 2 * nint);
+                int32_t *sidx = (int32_t *)scratch(c, s, B_SIDX, sizeof(int32_t) * PP);
+                if (!comp || !skey || !sbits || !sidx) return fail(c, QP_E_OOM, "device allocation failed (selection sort)");
+                switch (nint) {
 #define SELCASE(NI)                                                                                        \
     case NI:                                                                                               \
-        hipLaunchKernelGGL(sel_materialise<NI>, dim3(grid_for(PP)), dim3(256), 0, st, cand, comp, M, dets, P.perm, \
-                           skey, sbits, PP, sidx);                                                         \
+        hipLaunchKernelGGL(sel_materialise<NI>, dim3(grid_for(PP)), dim3(256), 0, st, r.cand, comp, M, x.dets, \
+                           r.P.perm, skey, sbits, PP, sidx);                                               \
         bitonic_sort(sidx, PP, SelCmp<NI>{skey, sbits}, st);                                              \
-        hipLaunchKernelGGL(sel_output<NI>, dim3(grid_for(std::max<int64_t>(m, 1))), dim3(256), 0, st, cand, comp, sidx, m, \
-                           ns, sbits, sel_dets, sel_e, n_sel);                                             \
+        hipLaunchKernelGGL(sel_output<NI>, dim3(grid_for(std::max<int64_t>(m, 1))), dim3(256), 0, st, r.cand, comp, \
+                           sidx, m, x.ns, sbits, x.sel_dets, x.sel_e, x.n_sel);                            \
         break;
-            SELCASE(1) SELCASE(2) SELCASE(3) SELCASE(4)
+                    SELCASE(1) SELCASE(2) SELCASE(3) SELCASE(4)
 #undef SELCASE
-        default: break;
+                default: break;
+                }
+                HIPCHK(c, hipGetLastError());
+            }
         }
-        HIPCHK(c, hipGetLastError());
     }
     if (c->timing) {
         HIPCHK(c, hipEventRecord(c->ev[4], st));
@@ -1181,16 +1448,17 @@ int qp_create(qp_ctx **ctx, int device)
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QP_E_HIP;
     qp_ctx *c = new qp_ctx();
     c->device = device;
-    c->bufs.resize(B_COUNT);
     if (hipSetDevice(device) != hipSuccess) { delete c; return QP_E_HIP; }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
     if (hipHostMalloc((void **)&c->host_sc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&c->host_det0, sizeof(uint64_t) * 2 * QPD_MAX_NINT, hipHostMallocDefault) != hipSuccess) {
-        delete c;
+        hipHostMalloc((void **)&c->host_det0, sizeof(uint64_t) * 2 * QPD_MAX_NINT, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->host_maxc2, sizeof(double) * QPD_MAX_STATES, hipHostMallocDefault) != hipSuccess) {
+        qp_destroy(c);
         return QP_E_HIP;
     }
+    c->host_sc_n = 1;
     *ctx = c;
     return QP_OK;
 }
@@ -1200,12 +1468,17 @@ void qp_destroy(qp_ctx *c)
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    for (auto &b : c->bufs) if (b.p) (void)hipFree(b.p);
+    for (auto &v : c->slots)
+        for (auto &b : v) if (b.p) (void)hipFree(b.p);
+    for (auto &b : c->args) if (b.p) (void)hipFree(b.p);
+    if (c->defn.p) (void)hipFree(c->defn.p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     double *arrs[] = {c->h, c->X, c->Y, c->Cj, c->Xj, c->Jm, c->Km, c->JK};
     for (double *p : arrs) if (p) (void)hipFree(p);
     if (c->host_sc) (void)hipHostFree(c->host_sc);
     if (c->host_det0) (void)hipHostFree(c->host_det0);
+    if (c->host_maxc2) (void)hipHostFree(c->host_maxc2);
+    if (c->host_stage) (void)hipHostFree(c->host_stage);
     delete c;
 }
 
@@ -1226,24 +1499,18 @@ int qp_set_integrals(qp_ctx *c, const double *h, const double *eri_packed, int n
     double **arrs[] = {&c->h, &c->X, &c->Y, &c->Cj, &c->Xj, &c->Jm, &c->Km, &c->JK};
     for (double **p : arrs) if (*p) { (void)hipFree(*p); *p = nullptr; }
     c->n = 0;
-    const int64_t n = n_orb;
-    const size_t nX = (size_t)(n * (n + 1) / 2) * n * n;
-    const size_t P2 = (size_t)(n * (n - 1) / 2);
-    const size_t nY = std::max<size_t>(1, P2 * P2);
-    const size_t n3 = (size_t)n * n * n, n2 = (size_t)n * n;
-    if (hipMalloc(&c->X, nX * 8) != hipSuccess || hipMalloc(&c->Y, nY * 8) != hipSuccess ||
-        hipMalloc(&c->Cj, n3 * 8) != hipSuccess || hipMalloc(&c->Xj, n3 * 8) != hipSuccess ||
-        hipMalloc(&c->Jm, n2 * 8) != hipSuccess || hipMalloc(&c->Km, n2 * 8) != hipSuccess ||
-        hipMalloc(&c->JK, n2 * 8) != hipSuccess || hipMalloc(&c->h, n2 * 8) != hipSuccess) {
+    const LayoutSizes z = layout_sizes(n_orb);
+    if (hipMalloc(&c->X, z.nX * 8) != hipSuccess || hipMalloc(&c->Y, z.nY * 8) != hipSuccess ||
+        hipMalloc(&c->Cj, z.n3 * 8) != hipSuccess || hipMalloc(&c->Xj, z.n3 * 8) != hipSuccess ||
+        hipMalloc(&c->Jm, z.n2 * 8) != hipSuccess || hipMalloc(&c->Km, z.n2 * 8) != hipSuccess ||
+        hipMalloc(&c->JK, z.n2 * 8) != hipSuccess || hipMalloc(&c->h, z.n2 * 8) != hipSuccess) {
         (void)hipGetLastError();
         for (double **p : arrs) if (*p) { (void)hipFree(*p); *p = nullptr; }
         return fail(c, QP_E_OOM, "device allocation failed (integral layouts)");
     }
-    hipLaunchKernelGGL(build_X, dim3(grid_for((int64_t)nX, 256, 1 << 16)), dim3(256), 0, st, eri_packed, n_orb, c->X);
-    if (P2 > 0)
-        hipLaunchKernelGGL(build_Y, dim3(grid_for((int64_t)(P2 * P2), 256, 1 << 16)), dim3(256), 0, st, eri_packed, n_orb, c->Y);
-    hipLaunchKernelGGL(build_small, dim3(grid_for((int64_t)n3, 256, 1 << 16)), dim3(256), 0, st, eri_packed, h, n_orb,
-                       c->Cj, c->Xj, c->Jm, c->Km, c->JK, c->h);
+    DevInts I = dev_ints(c);
+    I.n = n_orb;
+    launch_layouts(h, eri_packed, n_orb, I, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     c->n = n_orb;
@@ -1260,15 +1527,14 @@ int qp_pt2(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, 
     if (n_select < 0) return fail(c, QP_E_ARG, "n_select < 0");
     if (n_select > 0 && (!sel_dets || !sel_e || !n_sel)) return fail(c, QP_E_ARG, "selection outputs required");
     if (n_select > (int64_t)INT32_MAX / 4) return fail(c, QP_E_ARG, "n_select too large");
-    hipStream_t st = (hipStream_t)stream;
-    if (n_det == 0) {
-        HIPCHK(c, hipMemsetAsync(e_pt2, 0, sizeof(double) * n_states, st));
-        if (stats) HIPCHK(c, hipMemsetAsync(stats, 0, sizeof(qp_pt2_stats), st));
-        if (n_sel) HIPCHK(c, hipMemsetAsync(n_sel, 0, sizeof(int64_t), st));
-        return QP_OK;
-    }
-    return run_sweep(c, dets, coefs, n_det, n_states, E0, n_select, flags, false, nullptr, e_pt2, sel_dets, sel_e,
-                     n_sel, stats, eps_gen, nullptr, nullptr, nullptr, st);
+    std::vector<SysIn> in(1);
+    SysIn &x = in[0];
+    memset(&x, 0, sizeof(x));
+    x.I = dev_ints(c);
+    x.dets = dets; x.coefs = coefs; x.n_det = n_det; x.ns = n_states; x.E0 = E0;
+    x.n_select = n_select; x.e_pt2 = e_pt2; x.sel_dets = sel_dets; x.sel_e = sel_e; x.n_sel = n_sel;
+    x.stats = stats; x.eps_gen = eps_gen;
+    return run_sweeps(c, in, flags, false, (hipStream_t)stream);
 }
 
 int qp_pt2_backward(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int n_states,
@@ -1278,15 +1544,77 @@ int qp_pt2_backward(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_
     int rc = common_checks(c, dets, coefs, n_det, n_states, E0);
     if (rc != QP_OK) return rc;
     if (!grad_e_pt2) return fail(c, QP_E_ARG, "grad_e_pt2 is required");
-    hipStream_t st = (hipStream_t)stream;
-    if (n_det == 0) {
-        if (grad_E0) HIPCHK(c, hipMemsetAsync(grad_E0, 0, sizeof(double) * n_states, st));
-        if (grad_h) HIPCHK(c, hipMemsetAsync(grad_h, 0, sizeof(double) * c->n * c->n, st));
-        if (stats) HIPCHK(c, hipMemsetAsync(stats, 0, sizeof(qp_pt2_stats), st));
-        return QP_OK;
+    std::vector<SysIn> in(1);
+    SysIn &x = in[0];
+    memset(&x, 0, sizeof(x));
+    x.I = dev_ints(c);
+    x.dets = dets; x.coefs = coefs; x.n_det = n_det; x.ns = n_states; x.E0 = E0;
+    x.stats = stats; x.gup = grad_e_pt2;
+    x.grad_coefs = grad_coefs; x.grad_E0 = grad_E0; x.grad_h = grad_h;
+    return run_sweeps(c, in, flags, true, (hipStream_t)stream);
+}
+
+int qp_pt2_batched(qp_ctx *c, int n_sys, const qp_system *sys, int with_backward, int flags, void *stream)
+{
+    if (!c) return QP_E_ARG;
+    c->err.clear();
+    if (n_sys < 0 || (n_sys > 0 && !sys)) return fail(c, QP_E_ARG, "bad system list");
+    if (n_sys > QP_MAX_SYSTEMS) return fail(c, QP_E_ARG, "too many systems");
+    for (int s = 0; s < n_sys; ++s) {
+        const qp_system &y = sys[s];
+        const std::string who = "system " + std::to_string(s) + ": ";
+        if (y.n_orb < 1 || y.n_orb > QP_MAX_ORB) return fail(c, QP_E_NORB, who + "n_orb must be in [1,256]");
+        if (!y.h || !y.eri_packed) return fail(c, QP_E_ARG, who + "null integral pointer");
+        int rc = check_system(c, y.n_orb, y.dets, y.coefs, y.n_det, y.n_states, y.E0);
+        if (rc != QP_OK) { c->err = who + c->err; return rc; }
+        if (!y.e_pt2) return fail(c, QP_E_ARG, who + "e_pt2 is required");
+        if (y.n_select < 0) return fail(c, QP_E_ARG, who + "n_select < 0");
+        if (y.n_select > 0 && with_backward) return fail(c, QP_E_ARG, who + "no selection with the adjoint sweep");
+        if (y.n_select > 0 && (!y.sel_dets || !y.sel_e || !y.n_sel))
+            return fail(c, QP_E_ARG, who + "selection outputs required");
+        if (y.n_select > (int64_t)INT32_MAX / 4) return fail(c, QP_E_ARG, who + "n_select too large");
+        if (with_backward && !y.grad_e_pt2) return fail(c, QP_E_ARG, who + "grad_e_pt2 is required");
     }
-    return run_sweep(c, dets, coefs, n_det, n_states, E0, 0, flags, true, grad_e_pt2, nullptr, nullptr, nullptr,
-                     nullptr, stats, nullptr, grad_coefs, grad_E0, grad_h, st);
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    if ((int)c->layout_keys.size() < n_sys) c->layout_keys.resize(n_sys);
+    std::vector<SysIn> in(n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+        const qp_system &y = sys[s];
+        SysIn &x = in[s];
+        memset(&x, 0, sizeof(x));
+        // the system's integral layouts, in its own slot
+        const LayoutSizes z = layout_sizes(y.n_orb);
+        DevInts I;
+        I.n = y.n_orb;
+        I.X = (double *)scratch(c, s, B_LX, z.nX * 8);
+        I.Y = (double *)scratch(c, s, B_LY, z.nY * 8);
+        I.Cj = (double *)scratch(c, s, B_LCJ, z.n3 * 8);
+        I.Xj = (double *)scratch(c, s, B_LXJ, z.n3 * 8);
+        I.Jm = (double *)scratch(c, s, B_LJM, z.n2 * 8);
+        I.Km = (double *)scratch(c, s, B_LKM, z.n2 * 8);
+        I.JK = (double *)scratch(c, s, B_LJK, z.n2 * 8);
+        I.h = (double *)scratch(c, s, B_LH, z.n2 * 8);
+        if (!I.X || !I.Y || !I.Cj || !I.Xj || !I.Jm || !I.Km || !I.JK || !I.h)
+            return fail(c, QP_E_OOM, "device allocation failed (integral layouts)");
+        LayoutKey &key = c->layout_keys[s];
+        const bool same = key.h == y.h && key.eri == y.eri_packed && key.n == y.n_orb;
+        if (!((flags & QP_FLAG_REUSE_INTEGRALS) && same)) {
+            key = LayoutKey{};
+            launch_layouts(y.h, y.eri_packed, y.n_orb, I, st);
+            HIPCHK(c, hipGetLastError());
+            key.h = y.h; key.eri = y.eri_packed; key.n = y.n_orb;
+        }
+        x.I = I;
+        x.dets = y.dets; x.coefs = y.coefs; x.n_det = y.n_det; x.ns = y.n_states; x.E0 = y.E0;
+        x.n_select = y.n_select; x.e_pt2 = y.e_pt2; x.sel_dets = y.sel_dets; x.sel_e = y.sel_e; x.n_sel = y.n_sel;
+        x.stats = y.stats; x.eps_gen = with_backward ? nullptr : y.eps_gen;
+        if (with_backward) {
+            x.gup = y.grad_e_pt2;
+            x.grad_coefs = y.grad_coefs; x.grad_E0 = y.grad_E0; x.grad_h = y.grad_h;
+        }
+    }
+    return run_sweeps(c, in, flags & ~QP_FLAG_REUSE_INTEGRALS, with_backward != 0, st);
 }
 
 int qp_energy(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int n_states, int flags,
@@ -1297,13 +1625,13 @@ int qp_energy(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_de
     hipStream_t st = (hipStream_t)stream;
     if (n_det == 0) return fail(c, QP_E_ARG, "empty wave function has no energy");
     const int nint = (c->n - 1) / 64 + 1;
+    const DevInts I = dev_ints(c);
     Prepared P;
-    rc = prepare(c, nint, dets, coefs, n_det, n_states, flags, st, P);
+    rc = prepare(c, 0, I, dets, coefs, n_det, n_states, flags, st, P);
     if (rc != QP_OK) return rc;
-    double *row = (double *)scratch(c, B_ROW, sizeof(double) * n_det * n_states);
-    double *c2 = (double *)scratch(c, B_C2, sizeof(double) * n_det * n_states);
+    double *row = (double *)scratch(c, 0, B_ROW, sizeof(double) * n_det * n_states);
+    double *c2 = (double *)scratch(c, 0, B_C2, sizeof(double) * n_det * n_states);
     if (!row || !c2) return fail(c, QP_E_OOM, "device allocation failed (energy)");
-    DevInts I = dev_ints(c);
     switch (nint) {
 #define ECASE(NI)                                                                                          \
     case NI:                                                                                               \

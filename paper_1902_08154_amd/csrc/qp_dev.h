@@ -39,8 +39,11 @@ struct DevInts {
 __device__ __forceinline__ int64_t qtri(int64_t a, int64_t b) { return b * (b + 1) / 2 + a; }
 __device__ __forceinline__ int64_t qtris(int64_t a, int64_t b) { return b * (b - 1) / 2 + a; }
 
-// chemist (pq|rs) through the X layout
-__device__ __forceinline__ double eri_x(const DevInts &I, int p, int q, int r, int s)
+// chemist (pq|rs) through the X layout.  The integral helpers take the
+// DevInts by a deduced type, so that a DevInts read through the constant
+// address space binds without a copy.
+template <class Ints>
+__device__ __forceinline__ double eri_x(const Ints &I, int p, int q, int r, int s)
 {
     const int64_t n = I.n;
     if (p <= r) return I.X[(qtri(p, r) * n + q) * n + s];
@@ -135,8 +138,8 @@ __device__ __forceinline__ uint64_t det_fold(const uint64_t *d)
 }
 
 // F^J_{pq} for spin s: h_pq + sum_{j in J} (pq|jj) - sum_{j in J_s} (pj|jq)
-template <int NINT>
-__device__ double fock_offdiag(const DevInts &I, const uint64_t *J, int s, int p, int q)
+template <int NINT, class Ints>
+__device__ double fock_offdiag(const Ints &I, const uint64_t *J, int s, int p, int q)
 {
     const int64_t n = I.n;
     double v = I.h[p * n + q];
@@ -175,8 +178,8 @@ __device__ __forceinline__ void low2_merge(uint64_t m, int base, int &a, int &b)
 // the intermediate determinant (same spin) or per spin (opposite spins).
 // When sgl is non-null and the pair is a single excitation, writes
 // {hole, particle, spin, sign} (hole in ket, particle in bra).
-template <int NINT>
-__device__ double sc_offdiag(const DevInts &I, const uint64_t *bra, const uint64_t *ket,
+template <int NINT, class Ints>
+__device__ double sc_offdiag(const Ints &I, const uint64_t *bra, const uint64_t *ket,
                              int *deg_out, int *sgl)
 {
     int c0 = 0, c1 = 0;
@@ -283,7 +286,7 @@ struct SweepArgs {
     const double *HII;        // [rank]
     const int64_t *coff;      // [n_det+1], by rank
     const CoarseEnt *cent;
-    int64_t n_items;          // dense kernel: n_det * q_per_gen; general kernel: see def_n
+    int64_t n_items;          // dense kernel: n_det * q_per_gen; general kernel: listed batches
     int q_per_gen;            // work items per generator
     // dense kernel: buffer capacities; batches it hands over are marked in
     // def_bits (nbw words per generator rank, bit b = batch b)
@@ -293,7 +296,6 @@ struct SweepArgs {
     // general kernel: its items are the marked batches, listed in (rank, batch) order
     int def_mode;
     const uint32_t *def_g, *def_b;
-    const int64_t *def_n;     // device: number of listed batches
     int flags;                // bit0 fingerprint, bit1 backward
     // per-item partials (deterministic reduction later)
     double *eps_item;         // [n_items][ns]
@@ -319,11 +321,21 @@ struct SweepArgs {
     double *dh;               // [n][n]         atomics
 };
 
+// The sweep kernels read each system's SweepArgs from a table in device
+// memory through the constant address space: the table does not change during
+// a launch, so the compiler may reload a field where it is used instead of
+// holding it in a register, and it takes the pointers read from the table to
+// be global memory (global, not flat, memory instructions).
+typedef const __attribute__((address_space(4))) SweepArgs ConstSys;
+
 template <int NINT, int NS, bool BWD>
-void launch_sweep(const SweepArgs &a, int grid, hipStream_t st);
+void launch_sweep(const SweepArgs *sys, const int64_t *item_end, int n_sys, size_t lds, int grid, hipStream_t st);
 template <int NINT, int NS, bool BWD>
-int sweep_occupancy(int n);
+int sweep_occupancy(size_t lds);
+size_t sweep_lds_bytes(int n, int ns, bool bwd);
 template <int NINT, int NS, bool BWD>
-void launch_fast(const SweepArgs &a, int grid, hipStream_t st);
+void launch_fast(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
+                 hipStream_t st);
 template <int NINT, int NS, bool BWD>
-int fast_occupancy(int n, int nvm, int rscap, int cscap);
+int fast_occupancy(size_t lds);
+size_t fast_lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap);

@@ -136,8 +136,8 @@ __device__ __forceinline__ double wsum(double v)
 }
 
 // <J|H|alpha> for alpha = I - holes + particles (generic Slater-Condon)
-template <int NINT>
-__device__ __forceinline__ double celem(const DevInts &I, const uint64_t *Ib, int hc0, int hc1, int pa, int sa,
+template <int NINT, class Ints>
+__device__ __forceinline__ double celem(const Ints &I, const uint64_t *Ib, int hc0, int hc1, int pa, int sa,
                                         int pb, int sb, const uint64_t *J, int *deg, int *sgl)
 {
     uint64_t al[2 * NINT], jb[2 * NINT];
@@ -183,51 +183,58 @@ constexpr int waves_target() { return qpf_caps[BWD ? 1 : 0][NINT - 1][NS - 1]; }
 
 template <int NINT, int NS, bool BWD, bool FP>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_target<NINT, NS, BWD>(), 8)))
-void fast_kernel(SweepArgs a)
+void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ item_end, int n_sys)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int n = a.n;
     const int lane = threadIdx.x;
-    const int64_t n2 = (int64_t)n * n;
-    const int P2 = n * (n - 1) / 2;
-    const int nel = a.nel;
-    const int nb = nel + nel * (nel - 1) / 2;
-    const int Q = a.q_per_gen;
-    const int RSCAP = a.rscap, CSCAP = a.cscap;
-    const bool want_sel = a.n_select > 0;
-    const int nvm = n - (a.nup < a.ndn ? a.nup : a.ndn);
+    // the items of all systems, system after system, are dealt round-robin
+    // over the persistent grid: a shared counter would cost one contended
+    // device-scope atomic per item.  item_end[s] is the end of system s's items.
+    const int64_t total = item_end[n_sys - 1];
+    int sid = 0;
+    int64_t ibase = 0;
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        while (it >= item_end[sid]) ibase = item_end[sid++];
+        ConstSys &a = ((ConstSys *)sys)[sid];
+        const int64_t item = it - ibase;
+        const int n = a.n;
+        const int64_t n2 = (int64_t)n * n;
+        const int P2 = n * (n - 1) / 2;
+        const int nel = a.nel;
+        const int nb = nel + nel * (nel - 1) / 2;
+        const int Q = a.q_per_gen;
+        const int RSCAP = a.rscap, CSCAP = a.cscap;
+        const bool want_sel = a.n_select > 0;
+        const int nvm = n - (a.nup < a.ndn ? a.nup : a.ndn);
 
-    unsigned off = 0;
-    PEnt *sRT = carve<PEnt>(lds, off, nvm);
-    PEnt *sCT = carve<PEnt>(lds, off, nvm);
-    double *sRB = carve<double>(lds, off, RSCAP * nvm);
-    uint32_t *sRI = carve<uint32_t>(lds, off, BWD ? RSCAP * nvm : 1);
-    double *sCB = carve<double>(lds, off, CSCAP * nvm);
-    double *sFC = carve<double>(lds, off, FCAP * NS);
-    double *sLH = carve<double>(lds, off, L2CAP);
-    double *sDCF = carve<double>(lds, off, BWD ? FCAP * NS : 1);
-    double *sDHD = carve<double>(lds, off, BWD ? n : 1);
-    FE *sFine = carve<FE>(lds, off, FCAP);
-    uint32_t *sL = carve<uint32_t>(lds, off, L2CAP);   // i1 | i2 << 8 | f << 16 | ban << 24
-    uint32_t *sPL = carve<uint32_t>(lds, off, PCAP);   // q1 | q2 << 8 | f << 16 | normal << 24
-    uint32_t *sRSg = carve<uint32_t>(lds, off, RSCAP); // row | f << 16 | ban << 24
-    uint32_t *sCSg = carve<uint32_t>(lds, off, CSCAP); // col | f << 16 | ban << 24
-    uint16_t *sVidx = carve<uint16_t>(lds, off, 2 * n);
-    uint8_t *sOcc = carve<uint8_t>(lds, off, 2 * n);
-    uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
-    uint8_t *sCnt = carve<uint8_t>(lds, off, 2 * n);
+        unsigned off = 0;
+        PEnt *sRT = carve<PEnt>(lds, off, nvm);
+        PEnt *sCT = carve<PEnt>(lds, off, nvm);
+        double *sRB = carve<double>(lds, off, RSCAP * nvm);
+        uint32_t *sRI = carve<uint32_t>(lds, off, BWD ? RSCAP * nvm : 1);
+        double *sCB = carve<double>(lds, off, CSCAP * nvm);
+        double *sFC = carve<double>(lds, off, FCAP * NS);
+        double *sLH = carve<double>(lds, off, L2CAP);
+        double *sDCF = carve<double>(lds, off, BWD ? FCAP * NS : 1);
+        double *sDHD = carve<double>(lds, off, BWD ? n : 1);
+        FE *sFine = carve<FE>(lds, off, FCAP);
+        uint32_t *sL = carve<uint32_t>(lds, off, L2CAP);   // i1 | i2 << 8 | f << 16 | ban << 24
+        uint32_t *sPL = carve<uint32_t>(lds, off, PCAP);   // q1 | q2 << 8 | f << 16 | normal << 24
+        uint32_t *sRSg = carve<uint32_t>(lds, off, RSCAP); // row | f << 16 | ban << 24
+        uint32_t *sCSg = carve<uint32_t>(lds, off, CSCAP); // col | f << 16 | ban << 24
+        uint16_t *sVidx = carve<uint16_t>(lds, off, 2 * n);
+        uint8_t *sOcc = carve<uint8_t>(lds, off, 2 * n);
+        uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
+        uint8_t *sCnt = carve<uint8_t>(lds, off, 2 * n);
 
-    double E0[NS], gup[NS], cI[NS], invm[NS];
+        double E0[NS], gup[NS], cI[NS], invm[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        E0[k] = in_vgpr(a.E0[k]);
-        invm[k] = in_vgpr(a.inv_maxc2[k]);
-        gup[k] = BWD ? a.gup[k] : 0.0;
-    }
+        for (int k = 0; k < NS; ++k) {
+            E0[k] = in_vgpr(a.E0[k]);
+            invm[k] = in_vgpr(a.inv_maxc2[k]);
+            gup[k] = BWD ? a.gup[k] : 0.0;
+        }
 
-    // items are dealt round-robin over the persistent grid: a shared counter
-    // would cost one contended device-scope atomic per item
-    for (int64_t item = blockIdx.x; item < a.n_items; item += gridDim.x) {
         const int q = (int)(item / a.n_det);
         const int64_t g = item - (int64_t)q * a.n_det;
         const int64_t slot = g * Q + q;
@@ -1239,27 +1246,27 @@ void fast_kernel(SweepArgs a)
 }  // namespace qpfast
 
 template <int NINT, int NS, bool BWD>
-void launch_fast(const SweepArgs &a, int grid, hipStream_t st)
+void launch_fast(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
+                 hipStream_t st)
 {
-    const int nvm = a.n - (a.nup < a.ndn ? a.nup : a.ndn);
-    const size_t lds = qpfast::lds_bytes(a.n, nvm, NS, BWD, a.rscap, a.cscap);
-    if (a.flags & 1)
-        hipLaunchKernelGGL((qpfast::fast_kernel<NINT, NS, BWD, true>), dim3(grid), dim3(qpfast::WAVE), lds, st, a);
+    if (fp)
+        hipLaunchKernelGGL((qpfast::fast_kernel<NINT, NS, BWD, true>), dim3(grid), dim3(qpfast::WAVE), lds, st, sys,
+                           item_end, n_sys);
     else
-        hipLaunchKernelGGL((qpfast::fast_kernel<NINT, NS, BWD, false>), dim3(grid), dim3(qpfast::WAVE), lds, st, a);
+        hipLaunchKernelGGL((qpfast::fast_kernel<NINT, NS, BWD, false>), dim3(grid), dim3(qpfast::WAVE), lds, st, sys,
+                           item_end, n_sys);
 }
 
 template <int NINT, int NS, bool BWD>
-int fast_occupancy(int n, int nvm, int rscap, int cscap)
+int fast_occupancy(size_t lds)
 {
     int blocks = 0;
-    const size_t lds = qpfast::lds_bytes(n, nvm, NS, BWD, rscap, cscap);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, qpfast::fast_kernel<NINT, NS, BWD, false>, qpfast::WAVE,
                                                      lds) != hipSuccess)
         return 8;
     return blocks > 0 ? blocks : 1;
 }
 
-#define QPF_INST(NI, NS, B)                                                     \
-    template void launch_fast<NI, NS, B>(const SweepArgs &, int, hipStream_t); \
-    template int fast_occupancy<NI, NS, B>(int, int, int, int);
+#define QPF_INST(NI, NS, B)                                                                                  \
+    template void launch_fast<NI, NS, B>(const SweepArgs *, const int64_t *, int, bool, size_t, int, hipStream_t); \
+    template int fast_occupancy<NI, NS, B>(size_t);

@@ -107,8 +107,8 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // generic <J|H|alpha>, alpha = I with the holes removed and the particles
 // added
-template <int NINT>
-__device__ __forceinline__ double corr_element(const DevInts I, const uint64_t *Ibits, int h0, int h1c, int pa,
+template <int NINT, class Ints>
+__device__ __forceinline__ double corr_element(const Ints &I, const uint64_t *Ibits, int h0, int h1c, int pa,
                                             int sa, int pb, int sb, const uint64_t *J, int *deg, int *sgl)
 {
     uint64_t al[2 * NINT];
@@ -121,47 +121,55 @@ __device__ __forceinline__ double corr_element(const DevInts I, const uint64_t *
 }
 
 template <int NINT, int NS, bool BWD>
-__global__ __launch_bounds__(WAVE) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict__ sys,
+                                                    const int64_t *__restrict__ item_end, int n_sys)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int n = a.n;
     const int lane = threadIdx.x;
-    const int64_t n2 = (int64_t)n * n;
-    const int P2 = n * (n - 1) / 2;
-    const int nel = a.nel;
-    const int nb = nel + nel * (nel - 1) / 2;
-    const int Q = a.q_per_gen;
-    const bool want_fp = (a.flags & 1) != 0;
-    const bool want_sel = a.n_select > 0;
+    // the items of all systems, system after system, are dealt round-robin
+    // over the persistent grid (no shared counter); item_end[s] is the end of
+    // system s's items
+    const int64_t total = item_end[n_sys - 1];
+    int sid = 0;
+    int64_t ibase = 0;
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        while (it >= item_end[sid]) ibase = item_end[sid++];
+        ConstSys &a = ((ConstSys *)sys)[sid];
+        const int64_t item = it - ibase;
+        const int n = a.n;
+        const int64_t n2 = (int64_t)n * n;
+        const int P2 = n * (n - 1) / 2;
+        const int nel = a.nel;
+        const int nb = nel + nel * (nel - 1) / 2;
+        const int Q = a.q_per_gen;
+        const bool want_fp = (a.flags & 1) != 0;
+        const bool want_sel = a.n_select > 0;
 
-    // ----------------------------------------------------------- LDS layout
-    unsigned lo_ = 0;
-    double *sF = carve<double>(lds_raw, lo_, 2 * n);                   // Fock diagonal of I [spin][p]
-    double *sRG = carve<double>(lds_raw, lo_, QPD_MAX_ORB);            // row vector: diagonal offset
-    double *sCB = carve<double>(lds_raw, lo_, CSCAP * QPD_MAX_ORB);    // column-segment elements
-    double *sFC = carve<double>(lds_raw, lo_, FCAP * NS);              // c_Jk of fine entries
-    double *sL2H = carve<double>(lds_raw, lo_, L2CAP);                 // m = 2 cell elements
-    double *sDCF = carve<double>(lds_raw, lo_, BWD ? FCAP * NS : 1);   // adjoint: dE/dc_J per entry
-    double *sDHD = carve<double>(lds_raw, lo_, BWD ? n : 1);           // adjoint: diagonal of dE/dh
-    uint64_t *sI = carve<uint64_t>(lds_raw, lo_, 2 * NINT);
-    FineE *sFine = carve<FineE>(lds_raw, lo_, FCAP);
-    uint32_t *sL2 = carve<uint32_t>(lds_raw, lo_, L2CAP);              // i1 | i2 << 8 | fine << 16 | ban << 24
-    int32_t *sCS = carve<int32_t>(lds_raw, lo_, CSCAP);                // fine | col << 8
-    uint8_t *sIL = carve<uint8_t>(lds_raw, lo_, ICAP);                 // inline fine entries
-    uint16_t *sVidx = carve<uint16_t>(lds_raw, lo_, 2 * n);
-    uint8_t *sOcc = carve<uint8_t>(lds_raw, lo_, 2 * QPD_MAX_ORB);
-    uint8_t *sVirt = carve<uint8_t>(lds_raw, lo_, 2 * QPD_MAX_ORB);
-    uint8_t *sCnt = carve<uint8_t>(lds_raw, lo_, 2 * n);
-    uint8_t *sRS = carve<uint8_t>(lds_raw, lo_, QPD_MAX_ORB);          // row vector: phase bit
-    uint64_t *sRowBits = carve<uint64_t>(lds_raw, lo_, 4);             // rows holding m = 2 cells
+        // ----------------------------------------------------------- LDS layout
+        unsigned lo_ = 0;
+        double *sF = carve<double>(lds_raw, lo_, 2 * n);                   // Fock diagonal of I [spin][p]
+        double *sRG = carve<double>(lds_raw, lo_, QPD_MAX_ORB);            // row vector: diagonal offset
+        double *sCB = carve<double>(lds_raw, lo_, CSCAP * QPD_MAX_ORB);    // column-segment elements
+        double *sFC = carve<double>(lds_raw, lo_, FCAP * NS);              // c_Jk of fine entries
+        double *sL2H = carve<double>(lds_raw, lo_, L2CAP);                 // m = 2 cell elements
+        double *sDCF = carve<double>(lds_raw, lo_, BWD ? FCAP * NS : 1);   // adjoint: dE/dc_J per entry
+        double *sDHD = carve<double>(lds_raw, lo_, BWD ? n : 1);           // adjoint: diagonal of dE/dh
+        uint64_t *sI = carve<uint64_t>(lds_raw, lo_, 2 * NINT);
+        FineE *sFine = carve<FineE>(lds_raw, lo_, FCAP);
+        uint32_t *sL2 = carve<uint32_t>(lds_raw, lo_, L2CAP);              // i1 | i2 << 8 | fine << 16 | ban << 24
+        int32_t *sCS = carve<int32_t>(lds_raw, lo_, CSCAP);                // fine | col << 8
+        uint8_t *sIL = carve<uint8_t>(lds_raw, lo_, ICAP);                 // inline fine entries
+        uint16_t *sVidx = carve<uint16_t>(lds_raw, lo_, 2 * n);
+        uint8_t *sOcc = carve<uint8_t>(lds_raw, lo_, 2 * QPD_MAX_ORB);
+        uint8_t *sVirt = carve<uint8_t>(lds_raw, lo_, 2 * QPD_MAX_ORB);
+        uint8_t *sCnt = carve<uint8_t>(lds_raw, lo_, 2 * n);
+        uint8_t *sRS = carve<uint8_t>(lds_raw, lo_, QPD_MAX_ORB);          // row vector: phase bit
+        uint64_t *sRowBits = carve<uint64_t>(lds_raw, lo_, 4);             // rows holding m = 2 cells
 
-    double E0[NS], gup[NS], cI[NS];
+        double E0[NS], gup[NS], cI[NS];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) { E0[k] = a.E0[k]; gup[k] = BWD ? a.gup[k] : 0.0; }
+        for (int k = 0; k < NS; ++k) { E0[k] = a.E0[k]; gup[k] = BWD ? a.gup[k] : 0.0; }
 
-    // items are dealt round-robin over the persistent grid (no shared counter)
-    const int64_t n_work = a.def_mode ? *a.def_n : a.n_items;
-    for (int64_t item = blockIdx.x; item < n_work; item += gridDim.x) {
         int q, bstride;
         int64_t g, slot;
         if (a.def_mode) {
@@ -852,27 +860,25 @@ size_t sweep_lds_bytes(int n, int ns, bool bwd)
 }
 
 template <int NINT, int NS, bool BWD>
-void launch_sweep(const SweepArgs &a, int grid, hipStream_t st)
+void launch_sweep(const SweepArgs *sys, const int64_t *item_end, int n_sys, size_t lds, int grid, hipStream_t st)
 {
-    const size_t lds = sweep_lds_bytes(a.n, NS, BWD);
-    hipLaunchKernelGGL((sweep_kernel<NINT, NS, BWD>), dim3(grid), dim3(WAVE), lds, st, a);
+    hipLaunchKernelGGL((sweep_kernel<NINT, NS, BWD>), dim3(grid), dim3(WAVE), lds, st, sys, item_end, n_sys);
 }
 
 template <int NINT, int NS, bool BWD>
-int sweep_occupancy(int n)
+int sweep_occupancy(size_t lds)
 {
     int blocks = 0;
-    const size_t lds = sweep_lds_bytes(n, NS, BWD);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sweep_kernel<NINT, NS, BWD>, WAVE, lds) != hipSuccess)
         return 8;
     return blocks > 0 ? blocks : 1;
 }
 
-#define QP_INST(NI, NS)                                                              \
-    template void launch_sweep<NI, NS, false>(const SweepArgs &, int, hipStream_t);  \
-    template void launch_sweep<NI, NS, true>(const SweepArgs &, int, hipStream_t);   \
-    template int sweep_occupancy<NI, NS, false>(int);                                 \
-    template int sweep_occupancy<NI, NS, true>(int);
+#define QP_INST(NI, NS)                                                                                         \
+    template void launch_sweep<NI, NS, false>(const SweepArgs *, const int64_t *, int, size_t, int, hipStream_t); \
+    template void launch_sweep<NI, NS, true>(const SweepArgs *, const int64_t *, int, size_t, int, hipStream_t);  \
+    template int sweep_occupancy<NI, NS, false>(size_t);                                                       \
+    template int sweep_occupancy<NI, NS, true>(size_t);
 QP_INST(1, 1) QP_INST(1, 2) QP_INST(1, 3) QP_INST(1, 4)
 QP_INST(2, 1) QP_INST(2, 2) QP_INST(2, 3) QP_INST(2, 4)
 QP_INST(3, 1) QP_INST(3, 2) QP_INST(3, 3) QP_INST(3, 4)

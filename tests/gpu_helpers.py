@@ -77,11 +77,9 @@ def assert_selection_equal(g_dets, g_e, o, coefs):
     assert np.all(np.abs(g_e[ok] - o_e[ok]) <= e_tol[ok] + 1e-300)
 
 
-def compare_full(ctx, s, E0, n_select):
-    """Full parity of one system: |A|, fingerprint, E_PT2, S, eps per generator,
-    selection.  Returns (gpu, oracle) results."""
-    o = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, n_select=n_select, eps_gen=True)
-    g = run_gpu(ctx, s, E0, n_select=n_select)
+def check_full(g, o, s, n_select):
+    """Full parity of one system's GPU results g against the oracle's o: |A|,
+    fingerprint, E_PT2, S, eps per generator, selection."""
     st = g["stats"]
     assert st["n_alpha"] == o.n_alpha
     assert st["fingerprint"] == o.fp
@@ -93,6 +91,56 @@ def compare_full(ctx, s, E0, n_select):
                  + 64 * U * o.abs_gen[k])
         assert np.all(np.abs(g["eps_gen"][k] - o.eps_gen[k]) <= tol_g)
     assert abs(st["min_abs_delta"] - o.min_abs_delta) <= 64 * U * (np.abs(o.E0).max() + 1)
+    # rPT2 (eq. Z) from the same sums
+    Z, Er = orc.rpt2(o.E0, o.e_pt2, o.S)
+    for k in range(s.n_states):
+        dz = Z[k] ** 2 * s_tolerance(o, k)
+        assert abs(st["Z"][k] - Z[k]) <= dz + 4 * U, (k, st["Z"], Z)
+        assert abs(st["e_rpt2"][k] - Er[k]) <= e_tolerance(o, k) + abs(o.e_pt2[k]) * dz + 8 * U * abs(Er[k])
     if n_select > 0:
         assert_selection_equal(g["sel_dets"], g["sel_e"], o, s.coefs)
+
+
+def compare_full(ctx, s, E0, n_select):
+    """Full parity of one system through qp_pt2.  Returns (gpu, oracle) results."""
+    o = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, n_select=n_select, eps_gen=True)
+    g = run_gpu(ctx, s, E0, n_select=n_select)
+    check_full(g, o, s, n_select)
     return g, o
+
+
+def batched_inputs(ctx, systems, E0s, n_select=0, grad_up=None):
+    """Device inputs of qp_pt2_batched for synth systems."""
+    import torch
+    from paper_1902_08154_amd.api import to_device_dets
+    dev = ctx.device
+    out = []
+    for i, (s, E0) in enumerate(zip(systems, E0s)):
+        y = dict(h=torch.from_numpy(np.ascontiguousarray(s.h)).to(dev),
+                 eri_packed=torch.from_numpy(np.ascontiguousarray(s.eri)).to(dev),
+                 dets=to_device_dets(s.dets, dev),
+                 coefs=torch.from_numpy(np.ascontiguousarray(s.coefs)).to(dev),
+                 E0=torch.tensor(np.asarray(E0, dtype=np.float64), device=dev),
+                 n_select=n_select[i] if isinstance(n_select, (list, tuple)) else n_select,
+                 eps_gen=True)
+        if grad_up is not None:
+            y["grad_e_pt2"] = torch.tensor(np.asarray(grad_up[i], dtype=np.float64), device=dev)
+        out.append(y)
+    return out
+
+
+def batched_to_host(res):
+    from paper_1902_08154_amd.api import from_device_dets
+    out = []
+    for r in res:
+        g = dict(stats=r["stats"], e_pt2=r["e_pt2"].cpu().numpy())
+        if "eps_gen" in r:
+            g["eps_gen"] = r["eps_gen"].cpu().numpy()
+        if "sel_dets" in r:
+            g["sel_dets"] = from_device_dets(r["sel_dets"])
+            g["sel_e"] = r["sel_e"].cpu().numpy()
+        for k in ("grad_coefs", "grad_E0", "grad_h"):
+            if k in r:
+                g[k] = r[k].cpu().numpy()
+        out.append(g)
+    return out

@@ -40,4 +40,26 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
 
 def test_stats_struct_layout():
     from paper_1902_08154_amd import _lib
-    assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 8 * (4 + 1 + 3)
+    assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 8 * (4 + 1 + 4 + 4)
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of a header struct, from a C program built with gcc."""
+    import subprocess
+    body = "".join(f'    printf(" %zu", offsetof({struct}, {f}));\n' for f in fields)
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "qp_pt2.h"\nint main(void)\n{\n'
+                   f'    printf("%zu", sizeof({struct}));\n{body}    return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    from paper_1902_08154_amd import _lib
+    for cls, name in ((_lib.Stats, "qp_pt2_stats"), (_lib.System, "qp_system")):
+        fields = [f for f, _ in cls._fields_]
+        size, offs = _c_layout(tmp_path, name, fields)
+        assert size == ctypes.sizeof(cls), name
+        assert offs == [getattr(cls, f).offset for f in fields], name

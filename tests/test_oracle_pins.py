@@ -452,6 +452,35 @@ def test_gradients_finite_differences(orc):
     assert np.all(r.S > 0) and np.all(1.0 / (1.0 + r.S) <= 1.0)
 
 
+def test_rpt2_against_bruteforce_self_energy(orc):
+    """rPT2 (eq. Z): Sigma[E] is E_PT2 with E0 replaced by E, computed here by
+    second quantisation over the whole FCI space; its slope at E0 by central
+    differences must be -S of the oracle, and Z, E0 + Z E_PT2 follow."""
+    n, nup, ndn = 6, 2, 2
+    h, eri, g = _tiny(n, nup, ndn, 61)
+    basis = sq.fci_space(n, nup, ndn)
+    rng = np.random.default_rng(62)
+    psi = [basis[i] for i in rng.choice(len(basis), 9, replace=False)]
+    c = rng.standard_normal((2, 9))
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    E0 = np.array([-7.5, -6.0])
+    r = orc.pt2_full(n, h, eri, _words(psi, n), c, E0)
+    Z, Er = orc.rpt2(E0, r.e_pt2, r.S)
+    for k in range(2):
+        def sigma(E, k=k):
+            Ek = E0.copy(); Ek[k] = E
+            return sq.pt2_bruteforce(n, h, g, psi, c, Ek)[0][k]
+        t = 1e-4
+        d1 = (sigma(E0[k] + t) - sigma(E0[k] - t)) / (2 * t)
+        d2 = (sigma(E0[k] + t / 2) - sigma(E0[k] - t / 2)) / t
+        slope = (4 * d2 - d1) / 3
+        assert abs(slope + r.S[k]) < 1e-8 * max(1.0, r.S[k])
+        z_bf = 1.0 / (1.0 - slope)
+        assert abs(Z[k] - z_bf) < 1e-8
+        assert 0.0 < Z[k] <= 1.0
+        assert abs(Er[k] - (E0[k] + z_bf * sigma(E0[k]))) < 1e-8 * max(1.0, abs(Er[k]))
+
+
 # ------------------------------------------- the oracle's two modes agree
 
 def test_generator_mode_and_alpha_eval_agree_with_full(orc):
