@@ -44,7 +44,7 @@ FLAGS = [
 ]
 
 _REMARK = re.compile(r"Function Name: (\S+)[\s\S]*?ScratchSize \[bytes/lane\]: (\d+)")
-_FAST = re.compile(r"fast_kernelILi(\d)ELi(\d)ELb(\d)E")
+_FAST = re.compile(r"fast_kernelILi(\d)ELi(\d)ELb(\d)ELb(\d)E")
 
 
 def _compile(src: str) -> tuple[str, dict[str, int]]:
@@ -61,19 +61,24 @@ def _compile(src: str) -> tuple[str, dict[str, int]]:
 
 
 def _read_caps() -> list:
+    """caps[adjoint][fingerprint][n_int - 1][n_states - 1]"""
     txt = open(CAPS).read()
     body = txt[txt.index("= {") + 2: txt.rindex("};") + 1]
     nums = [int(x) for x in re.findall(r"\d+", body)]
-    if len(nums) != 32:
-        raise RuntimeError(f"{CAPS}: expected 32 entries, found {len(nums)}")
-    return [[nums[b * 16 + i * 4: b * 16 + i * 4 + 4] for i in range(4)] for b in range(2)]
+    if len(nums) != 64:
+        raise RuntimeError(f"{CAPS}: expected 64 entries, found {len(nums)}")
+    return [[[nums[b * 32 + f * 16 + i * 4: b * 32 + f * 16 + i * 4 + 4] for i in range(4)] for f in range(2)]
+            for b in range(2)]
 
 
 def _write_caps(caps: list) -> None:
     txt = open(CAPS).read()
     head = txt[: txt.index("= {") + 3]
-    rows = ["    {" + ", ".join("{" + ", ".join(str(v) for v in caps[b][i]) + "}" for i in range(4)) + "},"
-            for b in range(2)]
+
+    def plane(b, f):
+        return "{" + ", ".join("{" + ", ".join(str(v) for v in caps[b][f][i]) + "}" for i in range(4)) + "}"
+
+    rows = [f"    {{{plane(b, 0)},\n     {plane(b, 1)}}}," for b in range(2)]
     open(CAPS, "w").write(head + "\n" + "\n".join(rows) + "\n};\n")
 
 
@@ -97,11 +102,11 @@ def build(verbose: bool = False) -> str:
                 if m is None:
                     bad.append(f"{fn} ({size} bytes/lane)")
                     continue
-                spilling.setdefault((int(m.group(3)), int(m.group(1)), int(m.group(2))), []).append((fn, size))
-        # one occupancy target serves both fingerprint variants of an instantiation
-        for (bwd, ni, ns), fns in spilling.items():
-            if caps[bwd][ni - 1][ns - 1] > 1:
-                caps[bwd][ni - 1][ns - 1] -= 1
+                key = (int(m.group(3)), int(m.group(4)), int(m.group(1)), int(m.group(2)))
+                spilling.setdefault(key, []).append((fn, size))
+        for (bwd, fp, ni, ns), fns in spilling.items():
+            if caps[bwd][fp][ni - 1][ns - 1] > 1:
+                caps[bwd][fp][ni - 1][ns - 1] -= 1
                 lowered = True
             else:
                 bad += [f"{fn} ({size} bytes/lane at the lowest occupancy target)" for fn, size in fns]

@@ -971,25 +971,25 @@ int sweep_occ_t(int ns, bool bwd, size_t lds)
 }
 
 template <int NINT>
-int fast_occ_t(int ns, bool bwd, size_t lds)
+int fast_occ_t(int ns, bool bwd, size_t lds, bool fp)
 {
     switch (ns) {
-    case 1: return bwd ? fast_occupancy<NINT, 1, true>(lds) : fast_occupancy<NINT, 1, false>(lds);
-    case 2: return bwd ? fast_occupancy<NINT, 2, true>(lds) : fast_occupancy<NINT, 2, false>(lds);
-    case 3: return bwd ? fast_occupancy<NINT, 3, true>(lds) : fast_occupancy<NINT, 3, false>(lds);
-    default: return bwd ? fast_occupancy<NINT, 4, true>(lds) : fast_occupancy<NINT, 4, false>(lds);
+    case 1: return bwd ? fast_occupancy<NINT, 1, true>(lds, fp) : fast_occupancy<NINT, 1, false>(lds, fp);
+    case 2: return bwd ? fast_occupancy<NINT, 2, true>(lds, fp) : fast_occupancy<NINT, 2, false>(lds, fp);
+    case 3: return bwd ? fast_occupancy<NINT, 3, true>(lds, fp) : fast_occupancy<NINT, 3, false>(lds, fp);
+    default: return bwd ? fast_occupancy<NINT, 4, true>(lds, fp) : fast_occupancy<NINT, 4, false>(lds, fp);
     }
 }
 
 // persistent grid: every resident one-wavefront workgroup the CUs can hold
-int persistent_grid(qp_ctx *c, bool dense, int nint, int ns, bool bwd, size_t lds)
+int persistent_grid(qp_ctx *c, bool dense, int nint, int ns, bool bwd, size_t lds, bool fp)
 {
     int per_cu = 8;
     switch (nint) {
-    case 1: per_cu = dense ? fast_occ_t<1>(ns, bwd, lds) : sweep_occ_t<1>(ns, bwd, lds); break;
-    case 2: per_cu = dense ? fast_occ_t<2>(ns, bwd, lds) : sweep_occ_t<2>(ns, bwd, lds); break;
-    case 3: per_cu = dense ? fast_occ_t<3>(ns, bwd, lds) : sweep_occ_t<3>(ns, bwd, lds); break;
-    default: per_cu = dense ? fast_occ_t<4>(ns, bwd, lds) : sweep_occ_t<4>(ns, bwd, lds); break;
+    case 1: per_cu = dense ? fast_occ_t<1>(ns, bwd, lds, fp) : sweep_occ_t<1>(ns, bwd, lds); break;
+    case 2: per_cu = dense ? fast_occ_t<2>(ns, bwd, lds, fp) : sweep_occ_t<2>(ns, bwd, lds); break;
+    case 3: per_cu = dense ? fast_occ_t<3>(ns, bwd, lds, fp) : sweep_occ_t<3>(ns, bwd, lds); break;
+    default: per_cu = dense ? fast_occ_t<4>(ns, bwd, lds, fp) : sweep_occ_t<4>(ns, bwd, lds); break;
     }
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
@@ -1104,7 +1104,7 @@ struct LaunchPlan {
     std::vector<int64_t> end;   // running item end per listed system
 };
 
-std::vector<LaunchPlan> plan_launches(qp_ctx *c, bool dense, bool bwd, const std::vector<SysIn> &in,
+std::vector<LaunchPlan> plan_launches(qp_ctx *c, bool dense, bool bwd, bool fp, const std::vector<SysIn> &in,
                                       const std::vector<SysRun> &run, const std::vector<int64_t> &items)
 {
     std::vector<LaunchPlan> plans;
@@ -1128,7 +1128,7 @@ std::vector<LaunchPlan> plan_launches(qp_ctx *c, bool dense, bool bwd, const std
         p->sys.push_back((int)s);
         p->end.push_back((p->end.empty() ? 0 : p->end.back()) + items[s]);
     }
-    for (auto &p : plans) p.grid = persistent_grid(c, dense, p.nint, p.ns, bwd, p.lds);
+    for (auto &p : plans) p.grid = persistent_grid(c, dense, p.nint, p.ns, bwd, p.lds, fp);
     return plans;
 }
 
@@ -1243,8 +1243,8 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         if (x.n_select > 0) {
             const int nvm = n - std::min(r.P.nup, r.P.ndn);
             const int grid = std::max(persistent_grid(c, true, r.nint, ns, bwd,
-                                                      fast_lds_bytes(n, nvm, ns, bwd, rscap, cscap)),
-                                      persistent_grid(c, false, r.nint, ns, bwd, sweep_lds_bytes(n, ns, bwd)));
+                                                      fast_lds_bytes(n, nvm, ns, bwd, rscap, cscap), fp),
+                                      persistent_grid(c, false, r.nint, ns, bwd, sweep_lds_bytes(n, ns, bwd), fp));
             const int64_t maxcell = std::max<int64_t>((int64_t)(n - r.P.nup) * (n - r.P.ndn),
                                                       (int64_t)(n - r.P.nup) * (n - r.P.nup - 1) / 2);
             r.cand_cap = x.n_select + std::max<int64_t>(1 << 22, 2 * (int64_t)grid * std::min<int64_t>(maxcell, 3072));
@@ -1285,7 +1285,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     // ------------------------------------------------- phase 2: dense kernel
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], st));
     {
-        std::vector<LaunchPlan> plans = plan_launches(c, true, bwd, in, run, items);
+        std::vector<LaunchPlan> plans = plan_launches(c, true, bwd, fp, in, run, items);
         int rc = launch_plans(c, true, bwd, fp, plans, run, st);
         if (rc != QP_OK) return rc;
     }
@@ -1351,7 +1351,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     }
     // ------------------------------------------------ phase 4: general kernel
     {
-        std::vector<LaunchPlan> plans = plan_launches(c, false, bwd, in, run, gitems);
+        std::vector<LaunchPlan> plans = plan_launches(c, false, bwd, fp, in, run, gitems);
         int rc = launch_plans(c, false, bwd, fp, plans, run, st);
         if (rc != QP_OK) return rc;
     }

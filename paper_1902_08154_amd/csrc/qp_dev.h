@@ -337,5 +337,5 @@ template <int NINT, int NS, bool BWD>
 void launch_fast(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
                  hipStream_t st);
 template <int NINT, int NS, bool BWD>
-int fast_occupancy(size_t lds);
+int fast_occupancy(size_t lds, bool fp);
 size_t fast_lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap);

@@ -5,8 +5,10 @@
 // here (rewriting this file) when a change makes that kernel spill.
 #pragma once
 
-// [adjoint][n_int - 1][n_states - 1]
-constexpr int qpf_caps[2][4][4] = {
-    {{4, 3, 2, 2}, {3, 3, 2, 2}, {3, 3, 2, 2}, {2, 2, 2, 2}},
-    {{2, 2, 2, 1}, {2, 2, 2, 1}, {2, 2, 2, 1}, {2, 2, 1, 1}},
+// [adjoint][fingerprint][n_int - 1][n_states - 1]
+constexpr int qpf_caps[2][2][4][4] = {
+    {{{4, 3, 2, 2}, {3, 3, 2, 2}, {3, 3, 2, 2}, {2, 2, 2, 2}},
+     {{3, 3, 2, 2}, {3, 3, 2, 2}, {3, 3, 2, 2}, {2, 2, 2, 2}}},
+    {{{2, 2, 2, 1}, {2, 2, 2, 1}, {2, 2, 2, 1}, {2, 2, 1, 1}},
+     {{2, 2, 2, 1}, {2, 2, 2, 1}, {2, 2, 2, 1}, {2, 2, 1, 1}}},
 };

@@ -178,11 +178,11 @@ inline size_t lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap)
 
 // waves per SIMD the register allocation aims for: the highest target at
 // which the kernel needs no spill memory (see qp_fast_caps.h)
-template <int NINT, int NS, bool BWD>
-constexpr int waves_target() { return qpf_caps[BWD ? 1 : 0][NINT - 1][NS - 1]; }
+template <int NINT, int NS, bool BWD, bool FP>
+constexpr int waves_target() { return qpf_caps[BWD ? 1 : 0][FP ? 1 : 0][NINT - 1][NS - 1]; }
 
 template <int NINT, int NS, bool BWD, bool FP>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_target<NINT, NS, BWD>(), 8)))
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(waves_target<NINT, NS, BWD, FP>(), 8)))
 void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ item_end, int n_sys)
 {
     extern __shared__ __align__(16) unsigned char lds[];
@@ -915,41 +915,51 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                     const int lc = lok ? l : nc - 1;
                     const PEnt ce = sCT[lc];
                     const int pcol = ce.info & 255;
+                    // a lane past the last column, or on a flagged column (the column
+                    // pass finishes those), adds nothing in unflagged rows: a zero
+                    // numerator and a diagonal that makes the denominator huge, set
+                    // once here instead of per cell
+                    const bool quiet = !lok || (ce.info & FC) != 0u;
+                    const double Gq = quiet ? DEAD_D : ce.G;
+                    double cq[NS];
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) cq[k] = quiet ? 0.0 : cI[k];
                     double colacc = 0.0;
                     if (BWD || lok) {
-                        // integrals of the next row are loaded one row ahead; each
-                        // generator starts at its own row so that waves sharing a
-                        // block do not all read the same lines at once
+                        // the next row's integrals are loaded as soon as this row's
+                        // have been used, into the same registers, so that their
+                        // latency overlaps the rest of the cell; each generator
+                        // starts at its own row so that waves sharing a block do not
+                        // all read the same lines at once
                         const unsigned uc = (unsigned)pcol;
                         int r = (int)(g % nr);
                         uint32_t rinfo = rfl(sRT[r].info);
-                        double xn = (blk + (rinfo & 255) * n)[uc];
-                        double xjn = (Jm + (rinfo & 255) * n)[uc];
+                        double xc = (blk + (rinfo & 255) * n)[uc];
+                        double xjc = (Jm + (rinfo & 255) * n)[uc];
                         for (int t = 0; t < nr; ++t, r = r + 1 == nr ? 0 : r + 1) {
-                            const double x = xn, xj = xjn;
-                            const double Gr = rfl(sRT[r].G);
                             const uint32_t ri = rinfo;
-                            const int rn = r + 1 == nr ? 0 : r + 1;
-                            rinfo = rfl(sRT[rn].info);
-                            xn = (blk + (rinfo & 255) * n)[uc];
-                            xjn = (Jm + (rinfo & 255) * n)[uc];
-
                             const int pr = ri & 255;
-                            const double Hv = flip(x, ri ^ ce.info);
-                            double D = (ce.G + Gr) + xj;
+                            const double gx = rfl(sRT[r].G) + xjc;   // row part of H_aa
+                            const double Hv = flip(xc, ri ^ ce.info);
+                            {
+                                const int rn = r + 1 == nr ? 0 : r + 1;
+                                rinfo = rfl(sRT[rn].info);
+                                xc = (blk + (rinfo & 255) * n)[uc];
+                                xjc = (Jm + (rinfo & 255) * n)[uc];
+                            }
+                            double D = Gq + gx;
                             double A[NS];
 #pragma unroll
-                            for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
-                            bool live = true;
-                            if (BWD && !lok) {
-                                live = false; D = DEAD_D;
-#pragma unroll
-                                for (int k = 0; k < NS; ++k) A[k] = 0.0;
-                            }
+                            for (int k = 0; k < NS; ++k) A[k] = cq[k] * Hv;
+                            bool live = !quiet;
                             // a flagged row gathers its corrections here, all lanes at
-                            // once; a flagged column is finished by the column pass
+                            // once, flagged columns included
                             const bool rowf = (ri & FR) != 0u;
-                            if (live && rowf) {
+                            if (rowf && lok) {
+                                D = ce.G + gx;
+#pragma unroll
+                                for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
+                                live = true;
                                 uint32_t nco = 0;
                                 if (gather(r, l, A, nco)) {
                                     live = false; D = DEAD_D; nban++;
@@ -958,10 +968,6 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                                 } else {
                                     conn += nco;
                                 }
-                            } else if ((ce.info & FC) != 0u) {
-                                live = false; D = DEAD_D;
-#pragma unroll
-                                for (int k = 0; k < NS; ++k) A[k] = 0.0;
                             }
                             double ek[NS], w[NS], vsum;
                             const double tsel = finish(A, D, ek, w, vsum);
@@ -1010,26 +1016,56 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                     const bool lok = l < nr;
                     if (BWD || lok) {
                         // folded rows: row r holds cells (l, r) for l < r and
-                        // (l - r, nr - r) for l >= r, so every row has nr cells
+                        // (l - r, nr - r) for l >= r, so every row has nr cells.
+                        // The lane's cell in folded row rr: first index, second
+                        // index (A: rr itself, B: nr - rr), active or not.
+                        auto pick = [&](int rr, int &i1, int &i2, bool &act, bool &useA) {
+                            const bool pA = l < rr;
+                            act = lok && (pA || nr - rr > rr);
+                            useA = pA || !act;
+                            i1 = act ? (pA ? l : l - rr) : 0;
+                            i2 = useA ? rr : nr - rr;
+                        };
+                        // the next row's integrals are loaded as soon as this row's
+                        // have been used, into the same registers
+                        auto ss_offsets = [&](int rr, unsigned &ob, unsigned &oj) {
+                            int i1, i2;
+                            bool act, useA;
+                            pick(rr, i1, i2, act, useA);
+                            const int p1 = sRT[i1].info & 255, p2 = sRT[i2].info & 255;
+                            ob = (unsigned)(p2 * (p2 - 1) / 2 + p1);
+                            oj = (unsigned)(p2 * n + p1);
+                        };
                         const int nfr = nr / 2;
                         int r = nfr > 0 ? 1 + (int)(g % nfr) : 1;
+                        double xc = 0.0, xjc = 0.0;
+                        if (nfr > 0) {
+                            unsigned ob, oj;
+                            ss_offsets(r, ob, oj);
+                            xc = blk[ob];
+                            xjc = JK[oj];
+                        }
                         for (int t = 0; t < nfr; ++t, r = r == nfr ? 1 : r + 1) {
                             const bool validB = nr - r > r;
                             const uint32_t ia = rfl(sRT[r].info), ib = rfl(sRT[nr - r].info);
                             const double DA = D0 + rfl(sRT[r].G), DB = D0 + rfl(sRT[nr - r].G);
-                            const bool pA = l < r;
-                            const bool act = lok && (pA || validB);
+                            int i1, i2;
+                            bool act, useA;
+                            pick(r, i1, i2, act, useA);
+                            const PEnt e1 = sRT[i1];
+                            const uint32_t i2info = useA ? ia : ib;
+                            const int p1 = e1.info & 255, p2 = i2info & 255;
+                            const double Hv0 = flip(xc, e1.info ^ i2info ^ shb);
+                            const double D0c = ((useA ? DA : DB) + e1.G) + xjc;
+                            {
+                                unsigned ob, oj;
+                                ss_offsets(r == nfr ? 1 : r + 1, ob, oj);
+                                xc = blk[ob];
+                                xjc = JK[oj];
+                            }
                             if (BWD || act) {
-                                const bool useA = pA || !act;
-                                const int i1 = act ? (pA ? l : l - r) : 0;
-                                const int i2 = useA ? r : nr - r;
-                                const PEnt e1 = sRT[i1];
-                                const uint32_t i2info = useA ? ia : ib;
-                                const int p1 = e1.info & 255, p2 = i2info & 255;
-                                const double x = blk[(unsigned)(p2 * (p2 - 1) / 2 + p1)];
-                                const double xj = JK[(unsigned)(p2 * n + p1)];
-                                const double Hv = flip(x, e1.info ^ i2info ^ shb);
-                                double D = ((useA ? DA : DB) + e1.G) + xj;
+                                const double Hv = Hv0;
+                                double D = D0c;
                                 double A[NS];
 #pragma unroll
                                 for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
@@ -1258,15 +1294,17 @@ void launch_fast(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool 
 }
 
 template <int NINT, int NS, bool BWD>
-int fast_occupancy(size_t lds)
+int fast_occupancy(size_t lds, bool fp)
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, qpfast::fast_kernel<NINT, NS, BWD, false>, qpfast::WAVE,
-                                                     lds) != hipSuccess)
-        return 8;
+    const hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &blocks, qpfast::fast_kernel<NINT, NS, BWD, true>, qpfast::WAVE, lds)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &blocks, qpfast::fast_kernel<NINT, NS, BWD, false>, qpfast::WAVE, lds);
+    if (e != hipSuccess) return 8;
     return blocks > 0 ? blocks : 1;
 }
 
 #define QPF_INST(NI, NS, B)                                                                                  \
     template void launch_fast<NI, NS, B>(const SweepArgs *, const int64_t *, int, bool, size_t, int, hipStream_t); \
-    template int fast_occupancy<NI, NS, B>(size_t);
+    template int fast_occupancy<NI, NS, B>(size_t, bool);
