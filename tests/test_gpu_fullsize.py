@@ -80,3 +80,57 @@ def test_c2_full_size_sampled(ctx):
         assert o.dump_n[i] < 4096
         for t in range(int(o.dump_n[i])):
             assert bytes(o.dump_dets[i, t].tobytes()) in chosen, (ranks[i], o.dump_key[i, t], cut)
+
+
+def test_c3_adjoint_full_size(ctx):
+    """The adjoint workload at full size (n_orb 128, two words per spin, 14+14
+    electrons, 10^5 determinants): sampled generators against the oracle, the
+    gradient identities at full size, and central differences of the GPU
+    forward sweep for sampled coefficients (E_PT2 is quadratic in c at fixed
+    E0, so these are exact up to rounding)."""
+    import torch
+    from gpu_helpers import gpu_system
+    s = synth.workload(3)
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    g = run_gpu(ctx, s, E0, n_select=0)
+    print("forward done", flush=True)
+    st = g["stats"]
+    e = g["e_pt2"][0]
+    assert st["n_cells"] == s.n_det * 3722670
+    eps = g["eps_gen"]
+    assert abs(eps.sum() - e) <= 1e-12 * np.abs(eps).sum()
+    rank = orc.generator_rank(s.dets, s.coefs)
+    order = np.argsort(rank)
+    ranks = [0, 31337]
+    gens = order[ranks]
+    o = orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens)
+    print("oracle generators done", flush=True)
+    for i, gi in enumerate(gens):
+        tol = 1e-10 * abs(o.eps[i, 0]) + 32 * U * (abs(E0[0]) + 1) * o.S[i, 0] + 1e-15
+        assert abs(eps[0, gi] - o.eps[i, 0]) <= tol, (ranks[i], eps[0, gi], o.eps[i, 0])
+
+    dets, coefs = gpu_system(ctx, s)
+    dev = ctx.device
+    E0t = torch.tensor(E0, device=dev)
+    gc, gE, gh = ctx.pt2_backward(dets, coefs, E0t, torch.ones(1, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    print("backward done", flush=True)
+    gc, gE, gh = gc.cpu().numpy(), gE.cpu().numpy(), gh.cpu().numpy()
+    S = st["S"][0]
+    # rounding of the denominators moves E by up to a few ulps of |E0| times S
+    rtol_e = 1e-9 * abs(e) + 64 * U * (abs(E0[0]) + 1) * S
+    assert abs(float(s.coefs[0] @ gc[0]) - 2 * e) <= 2 * rtol_e
+    assert abs(gE[0] + S) <= 1e-9 * S
+    assert abs(np.trace(gh) - (s.n_up + s.n_dn) * S) <= 1e-9 * abs(np.trace(gh))
+    assert np.abs(gh - gh.T).max() <= 1e-12 * np.abs(gh).max()
+
+    def energy(c):
+        return float(ctx.pt2(dets, torch.from_numpy(c).to(dev), E0t)["e_pt2"].item())
+
+    rng = np.random.default_rng(3)
+    for j in rng.choice(s.n_det, 3, replace=False):
+        h = 1e-3 * max(abs(s.coefs[0, j]), 1e-3)
+        cp = s.coefs.copy(); cp[0, j] += h
+        cm = s.coefs.copy(); cm[0, j] -= h
+        fd = (energy(cp) - energy(cm)) / (2 * h)
+        assert abs(fd - gc[0, j]) <= 1e-7 * np.abs(gc).max() + 2 * rtol_e / h, (j, fd, gc[0, j])
