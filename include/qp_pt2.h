@@ -181,6 +181,60 @@ int qp_pt2_backward(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int6
                     qp_pt2_stats *stats, void *stream);
 
 /*
+ * qp_generator_order -- the generator order used by every sweep (sec. "CIPSI
+ * selection and PT2 energy"): determinant indices sorted by decreasing
+ * sum_k c_Ik^2, ties by key ascending.  order_out device int32 [n_det].
+ * Synchronises the stream once.  Errors as qp_pt2.
+ */
+int qp_generator_order(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
+                       int n_states, int flags, int32_t *order_out, void *stream);
+
+/*
+ * qp_pt2_generators -- the generator decomposition E_PT2 = sum_I eps_I (same
+ * section) evaluated for a list of generators only: eps_I,k of each listed
+ * determinant I, with alpha owned by the first generator (in the generator
+ * order of the whole wave function) it is connected to.
+ *   gens     device int32 [n_gen]: distinct determinant indices
+ *   eps_out  device double [n_states][n_gen] (position i: generator gens[i])
+ *   n_select, sel_dets, sel_e, n_sel: as qp_pt2, over the alpha owned by the
+ *            listed generators
+ *   stats    optional; n_alpha, S, ... summed over the listed generators,
+ *            n_cells counts their candidate cells
+ * A listed generator's eps_I is the same, bit for bit, as qp_pt2's eps_gen
+ * entry for it.  Errors as qp_pt2; QP_E_ARG for an index outside [0, n_det).
+ */
+int qp_pt2_generators(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
+                      int n_states, const double *E0, const int32_t *gens, int64_t n_gen,
+                      int64_t n_select, int flags, double *eps_out, uint64_t *sel_dets,
+                      double *sel_e, int64_t *n_sel, qp_pt2_stats *stats, void *stream);
+
+/*
+ * qp_pt2_stochastic -- semi-stochastic E_PT2 (sec. "CIPSI selection and PT2
+ * energy", the hybrid deterministic/stochastic scheme): E_PT2 = sum_{I in D}
+ * eps_I + sum_{K in S} eps_K, with D the first d generators in generator order
+ * (computed exactly) and the rest estimated from generators drawn with
+ * probability w_K / W, w_K = sum_k c_Kk^2.  eps of a drawn generator is
+ * computed once and reused when it is drawn again.  Rounds: D grows by
+ * det_chunk generators and draws_per_round generators are drawn, then the
+ * listed new generators are swept on the GPU together.  The estimate of
+ * state k is sum_{D} eps + mean over the draws that fall outside D of
+ * W_S eps_K / w_K (W_S the weight outside D), its error the standard error of
+ * that mean.  Stops when every state has error <= rel_err |estimate| (the
+ * paper's default is 0.002), when D holds every generator (exact, error 0),
+ * or when the random numbers run out.
+ *   uniforms   HOST double [n_uniforms] in [0, 1): the random numbers, one per
+ *              draw, consumed in order (the caller owns the generator)
+ *   e_est, e_err  HOST double [n_states]; n_computed, n_rounds HOST int64 [1]
+ * The call is synchronous.  Errors as qp_pt2; QP_E_ARG for det_chunk < 1,
+ * draws_per_round < 0 or rel_err < 0.
+ */
+int qp_pt2_stochastic(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
+                      int n_states, const double *E0, const double *uniforms, int64_t n_uniforms,
+                      double rel_err, int64_t det_chunk, int64_t draws_per_round, int flags,
+                      double *e_est, double *e_err, int64_t *n_computed, int64_t *n_rounds,
+                      void *stream);
+
+/*
  * qp_pt2_batched -- many independent wave functions in one sweep call: every
  * system's (generator, batch) work items go into one work list, and each of
  * the two sweep kernels runs as one persistent launch per (n_int, n_states)

@@ -189,6 +189,94 @@ def rpt2(E0, e_pt2, S):
     return Z, E0 + Z * e
 
 
+def semistochastic(eps_of_ranks, w, uniforms, rel_err, det_chunk, draws_per_round):
+    """Semi-stochastic E_PT2 (sec. "CIPSI selection and PT2 energy", the hybrid
+    deterministic/stochastic scheme), written from the paper's description.
+
+    Generators are taken in generator order (rank r).  E_PT2 = sum_I eps_I is
+    split into a deterministic part D, the first d ranks, and a stochastic part
+    S, the rest.  Each round, D grows by det_chunk ranks and draws_per_round
+    ranks are drawn with probability w_r / W (w_r = sum_k c_rk^2); a drawn
+    rank's eps is computed once and remembered.  A draw is the first rank r
+    whose running weight sum exceeds u W, for the next number u of
+    `uniforms`.  The draws that fall in S are a sample of S with probability
+    w_r / W_S (W_S the weight of S), so sum_S eps is estimated by the mean of
+    W_S eps_r / w_r over them, with the standard error of that mean.  The
+    run stops when every state's error is at most rel_err |estimate|, when D
+    covers every rank (exact), or when the uniforms run out.
+
+    eps_of_ranks(list of ranks) -> array [len][ns] gives eps for ranks.
+    Returns (estimate[ns], error[ns], number of ranks evaluated, rounds)."""
+    w = np.asarray(w, dtype=np.float64)
+    n = w.size
+    cum = np.empty(n)
+    run = 0.0
+    for r in range(n):
+        run += w[r]
+        cum[r] = run
+    tail = np.zeros(n + 1)
+    for r in range(n - 1, -1, -1):
+        tail[r] = tail[r + 1] + w[r]
+    W = run
+    memo = {}
+    draws = []
+    d = 0
+    nu = 0
+    rounds = 0
+    ns = None
+    det_sum = None
+    est = err = None
+    while True:
+        d_new = min(n, d + det_chunk)
+        todo = [r for r in range(d, d_new) if r not in memo]
+        drawn = 0
+        while drawn < draws_per_round and nu < len(uniforms) and W > 0.0:
+            t = uniforms[nu] * W
+            nu += 1
+            r = min(int(np.searchsorted(cum, t, side="right")), n - 1)
+            draws.append(r)
+            drawn += 1
+            if r >= d_new and r not in memo and r not in todo:
+                todo.append(r)
+        if todo:
+            vals = np.atleast_2d(np.asarray(eps_of_ranks(todo), dtype=np.float64))
+            for r, v in zip(todo, vals):
+                memo[r] = v
+        if ns is None:
+            ns = len(next(iter(memo.values()))) if memo else 1
+            det_sum = np.zeros(ns)
+        for r in range(d, d_new):
+            det_sum = det_sum + memo[r]
+        d = d_new
+        rounds += 1
+        est = np.zeros(ns)
+        err = np.zeros(ns)
+        converged = True
+        if d == n:
+            est = det_sum.copy()
+        else:
+            WS = tail[d]
+            inS = [r for r in draws if r >= d]
+            for k in range(ns):
+                mean = 0.0
+                m2 = 0.0
+                for j, r in enumerate(inS, start=1):
+                    y = WS * memo[r][k] / w[r]
+                    dl = y - mean
+                    mean += dl / j
+                    m2 += dl * (y - mean)
+                m = len(inS)
+                est[k] = det_sum[k] + (mean if m > 0 else 0.0)
+                err[k] = np.sqrt(m2 / (m - 1) / m) if m > 1 else np.inf
+                if not (m > 1 and err[k] <= rel_err * abs(est[k])):
+                    converged = False
+        if d == n or converged:
+            break
+        if draws_per_round > 0 and nu >= len(uniforms):
+            break
+    return est, err, len(memo), rounds
+
+
 def alpha_eval(n_orb, h, eri, dets, coefs, rank, alpha):
     """(N[ns], D, owner_rank, internal) for one determinant alpha, scanning all of Psi."""
     dets = _c(dets, np.uint64); coefs = _c(np.atleast_2d(coefs), np.float64)

@@ -76,7 +76,8 @@ class System(ctypes.Structure):
 
 # every entry point declared in include/qp_pt2.h
 EXPORTS = ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
-           "qp_pt2_backward", "qp_pt2_batched", "qp_energy", "qp_set_timing", "qp_last_timing")
+           "qp_pt2_backward", "qp_generator_order", "qp_pt2_generators", "qp_pt2_stochastic",
+           "qp_pt2_batched", "qp_energy", "qp_set_timing", "qp_last_timing")
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -104,6 +105,13 @@ def load():
     lib.qp_pt2.restype = _I
     lib.qp_pt2_backward.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I, _P, _P, _P, _P, _P]
     lib.qp_pt2_backward.restype = _I
+    lib.qp_generator_order.argtypes = [_P, _P, _P, _I64, _I, _I, _P, _P]
+    lib.qp_generator_order.restype = _I
+    lib.qp_pt2_generators.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I64, _I64, _I, _P, _P, _P, _P, _P, _P]
+    lib.qp_pt2_generators.restype = _I
+    lib.qp_pt2_stochastic.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I64, ctypes.c_double, _I64, _I64, _I,
+                                      _P, _P, _P, _P, _P]
+    lib.qp_pt2_stochastic.restype = _I
     lib.qp_pt2_batched.argtypes = [_P, _I, ctypes.POINTER(System), _I, _I, _P]
     lib.qp_pt2_batched.restype = _I
     lib.qp_energy.argtypes = [_P, _P, _P, _I64, _I, _I, _P, _P]

@@ -98,6 +98,33 @@ class Context:
                                               _ptr(grad_coefs), _ptr(grad_E0), _ptr(grad_h), _ptr(stats),
                                               _stream(self.device)))
 
+    def qp_generator_order(self, dets, coefs, order_out, flags=0):
+        self._check(self._lib.qp_generator_order(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], coefs.shape[0],
+                                                 flags, _ptr(order_out), _stream(self.device)))
+
+    def qp_pt2_generators(self, dets, coefs, E0, gens, n_select=0, flags=0, eps_out=None, sel_dets=None,
+                          sel_e=None, n_sel=None, stats=None):
+        self._check(self._lib.qp_pt2_generators(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], coefs.shape[0],
+                                                _ptr(E0), _ptr(gens), gens.numel(), n_select, flags,
+                                                _ptr(eps_out), _ptr(sel_dets), _ptr(sel_e), _ptr(n_sel),
+                                                _ptr(stats), _stream(self.device)))
+
+    def qp_pt2_stochastic(self, dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round, flags=0):
+        """uniforms: host float64 numpy array.  Returns (e_est, e_err, n_computed, n_rounds)."""
+        import numpy as np
+        ns = coefs.shape[0]
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        e = np.zeros(ns)
+        err = np.zeros(ns)
+        nc = np.zeros(1, dtype=np.int64)
+        nr = np.zeros(1, dtype=np.int64)
+        hp = lambda a: ctypes.c_void_p(a.ctypes.data)
+        self._check(self._lib.qp_pt2_stochastic(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], ns, _ptr(E0),
+                                                hp(u) if u.size else None, u.size, float(rel_err), int(det_chunk),
+                                                int(draws_per_round), flags, hp(e), hp(err), hp(nc), hp(nr),
+                                                _stream(self.device)))
+        return e, err, int(nc[0]), int(nr[0])
+
     def qp_pt2_batched(self, systems, with_backward=False, flags=0):
         """systems: a sequence of _lib.System records."""
         arr = (_lib.System * max(len(systems), 1))(*systems)
@@ -161,6 +188,43 @@ class Context:
         g = grad_e_pt2.to(device=dev, dtype=torch.float64).contiguous()
         self.qp_pt2_backward(dets, coefs, E0, g, 0, gc, gE, gh, None)
         return gc, gE, gh
+
+    def generator_order(self, dets, coefs):
+        """Determinant indices in generator order (torch.int32 on the device)."""
+        self._inputs(dets, coefs)
+        out = torch.empty(dets.shape[0], dtype=torch.int32, device=self.device)
+        self.qp_generator_order(dets, coefs, out)
+        return out
+
+    def pt2_generators(self, dets, coefs, E0, gens, n_select=0, fingerprint=False):
+        """eps_I [ns, len(gens)] of the listed generators (determinant indices),
+        with stats and, when n_select > 0, their selected alpha."""
+        self._inputs(dets, coefs, E0)
+        gens = gens.to(device=self.device, dtype=torch.int32).contiguous()
+        ns = coefs.shape[0]
+        dev = self.device
+        eps = torch.empty((ns, max(gens.numel(), 1)), dtype=torch.float64, device=dev)
+        st = torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev)
+        sd = torch.empty((max(n_select, 1), 2, dets.shape[2]), dtype=torch.int64, device=dev)
+        se = torch.empty((max(n_select, 1), ns), dtype=torch.float64, device=dev)
+        nsel = torch.zeros(1, dtype=torch.int64, device=dev)
+        flags = _lib.QP_FLAG_FINGERPRINT if fingerprint else 0
+        self.qp_pt2_generators(dets, coefs, E0, gens, n_select, flags, eps, sd if n_select > 0 else None,
+                               se if n_select > 0 else None, nsel if n_select > 0 else None, st)
+        m = int(nsel.item()) if n_select > 0 else 0
+        return dict(eps=eps[:, :gens.numel()], stats=stats_to_dict(st, ns), sel_dets=sd[:m], sel_e=se[:m])
+
+    def pt2_stochastic(self, dets, coefs, E0, uniforms, rel_err=0.002, det_chunk=None, draws_per_round=None):
+        """Semi-stochastic E_PT2.  uniforms: host random numbers in [0, 1), one
+        per draw.  Returns dict(e_pt2, err, n_computed, n_rounds)."""
+        self._inputs(dets, coefs, E0)
+        n = dets.shape[0]
+        if det_chunk is None:
+            det_chunk = max(1, n // 64)
+        if draws_per_round is None:
+            draws_per_round = max(16, n // 64)
+        e, err, nc, nr = self.qp_pt2_stochastic(dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round)
+        return dict(e_pt2=e, err=err, n_computed=nc, n_rounds=nr)
 
     def pt2_batched(self, systems, with_backward=False, fingerprint=False, check=True, reuse_integrals=False):
         """Many systems in one call.  `systems` is a sequence of dicts with

@@ -5,6 +5,7 @@
 #include "../../include/qp_pt2.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -108,7 +109,7 @@ struct Scalars {
     int bad_bits;     // a bit set at >= n_orb
     int bad_elec;     // electron counts differ from det 0
     int dup;          // duplicate determinant
-    int pad;
+    int bad_gen;      // a listed generator index outside [0, n_det)
 };
 
 // generator weight w_J = sum_k c_Jk^2 ; inverse max c^2 per state
@@ -233,6 +234,21 @@ __global__ void make_rank(const int32_t *perm, int64_t n_det, int32_t *rank)
 {
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_det; g += (int64_t)gridDim.x * blockDim.x)
         rank[perm[g]] = (int32_t)g;
+}
+
+// ranks of a list of generators given by determinant index
+__global__ void map_gen_ranks(const int32_t *gens, int64_t n_gen, const int32_t *rank, int64_t n_det,
+                              int32_t *out, Scalars *sc)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_gen; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = gens[i];
+        if (d < 0 || d >= n_det) {
+            sc->bad_gen = 1;
+            out[i] = 0;
+        } else {
+            out[i] = rank[d];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- per-generator prep
@@ -455,34 +471,41 @@ __global__ void def_fill(const uint32_t *bits, int64_t n_det, int nbw, const int
 }
 
 // no batches at all (no electrons): every partial is zero
-__global__ void reduce_empty(int64_t n_det, int ns, const int32_t *perm, double *eps_g, double *S_g, uint64_t *cnt_g,
-                             uint64_t *fp_g, uint64_t *conn_g, uint64_t *defa_g, double *eps_gen)
+__global__ void reduce_empty(int64_t n_gen, int ns, const int32_t *perm, const int32_t *gen_rank, int64_t n_det,
+                             double *eps_g, double *S_g, uint64_t *cnt_g, uint64_t *fp_g, uint64_t *conn_g,
+                             uint64_t *defa_g, double *eps_gen)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= n_det) return;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i0 >= n_gen) return;
     for (int k = 0; k < ns; ++k) {
-        eps_g[g * ns + k] = 0.0;
-        S_g[g * ns + k] = 0.0;
-        if (eps_gen) eps_gen[k * n_det + perm[g]] = 0.0;
+        eps_g[i0 * ns + k] = 0.0;
+        S_g[i0 * ns + k] = 0.0;
+        if (eps_gen) {
+            if (gen_rank) eps_gen[k * n_gen + i0] = 0.0;
+            else eps_gen[k * n_det + perm[i0]] = 0.0;
+        }
     }
-    cnt_g[g] = 0; fp_g[g] = 0; conn_g[g] = 0; defa_g[g] = 0;
+    cnt_g[i0] = 0; fp_g[i0] = 0; conn_g[i0] = 0; defa_g[i0] = 0;
 }
 
 // per generator, in a fixed order: its dense-kernel items, then its deferred
-// batches in batch order
+// batches in batch order.  Generator i of the call is rank gen_rank[i] (or
+// rank i when gen_rank is null); per-generator outputs go to position i, and
+// eps_gen to [k][det] for a full sweep or [k][i] for a list.
 __global__ void reduce_items(const double *eps_item, const double *S_item, const uint32_t *cnt_item,
                              const uint64_t *fp_item, const uint32_t *conn_item, const double *dc_item,
-                             int64_t n_det, int nq, int ns, const int32_t *perm, double *eps_g, double *S_g,
-                             uint64_t *cnt_g, uint64_t *fp_g, uint64_t *conn_g, uint64_t *defa_g, double *eps_gen,
-                             double *dc, DefParts dp)
+                             int64_t n_gen, int nq, int ns, const int32_t *perm, const int32_t *gen_rank,
+                             int64_t n_det, double *eps_g, double *S_g, uint64_t *cnt_g, uint64_t *fp_g,
+                             uint64_t *conn_g, uint64_t *defa_g, double *eps_gen, double *dc, DefParts dp)
 {
-    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= n_det) return;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i0 >= n_gen) return;
+    const int64_t g = gen_rank ? (int64_t)gen_rank[i0] : i0;
     const int det = perm[g];
     double e[QPD_MAX_STATES] = {0, 0, 0, 0}, s[QPD_MAX_STATES] = {0, 0, 0, 0}, d[QPD_MAX_STATES] = {0, 0, 0, 0};
     uint64_t c = 0, f = 0, cn = 0, cd = 0;
     for (int i = 0; i < nq; ++i) {
-        const int64_t sl = g * nq + i;
+        const int64_t sl = i0 * nq + i;
         for (int k = 0; k < ns; ++k) {
             e[k] += eps_item[sl * ns + k];
             s[k] += S_item[sl * ns + k];
@@ -505,15 +528,18 @@ __global__ void reduce_items(const double *eps_item, const double *S_item, const
     }
     c += cd;
     for (int k = 0; k < ns; ++k) {
-        eps_g[g * ns + k] = e[k];
-        S_g[g * ns + k] = s[k];
-        if (eps_gen) eps_gen[k * n_det + det] = e[k];
+        eps_g[i0 * ns + k] = e[k];
+        S_g[i0 * ns + k] = s[k];
+        if (eps_gen) {
+            if (gen_rank) eps_gen[k * n_gen + i0] = e[k];
+            else eps_gen[k * n_det + det] = e[k];
+        }
         if (dc_item && dc) dc[k * n_det + det] += d[k];
     }
-    conn_g[g] = cn;
-    defa_g[g] = cd;
-    cnt_g[g] = c;
-    fp_g[g] = f;
+    conn_g[i0] = cn;
+    defa_g[i0] = cd;
+    cnt_g[i0] = c;
+    fp_g[i0] = f;
 }
 
 // single block, fixed summation order
@@ -681,7 +707,7 @@ enum BufId {
     B_W, B_IDX, B_RANK, B_F, B_HII, B_COUNTS, B_OFFS, B_BSUM, B_COFF, B_CENT, B_EPSI, B_SI, B_CNTI, B_FPI,
     B_DCI, B_EPSG, B_SG, B_CNTG, B_FPG, B_SC, B_HIST, B_CAND, B_COMP, B_SKEY, B_SBITS, B_SIDX, B_MAXC2,
     B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFE, B_DEFS, B_DEFC, B_DEFN, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
-    B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS,
+    B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_GENR,
     // integral layouts of a system of a batched call
     B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
     B_COUNT
@@ -1055,6 +1081,8 @@ struct SysIn {
     const uint64_t *dets;
     const double *coefs;
     int64_t n_det;
+    const int32_t *gens;        // generators of the call by determinant index (null: all)
+    int64_t n_gen;
     int ns;
     const double *E0;
     int64_t n_select;
@@ -1072,6 +1100,8 @@ struct SysIn {
 struct SysRun {
     int slot = 0;
     int nint = 1;
+    int32_t *gen_rank = nullptr;  // ranks of the listed generators (null: all)
+    int64_t n_g = 0;              // generators of the call
     bool swept = false;         // has dense-kernel items
     Prepared P;
     int Q = 1;
@@ -1207,10 +1237,26 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         int rc = prepare(c, s, x.I, x.dets, x.coefs, x.n_det, ns, flags, st, r.P);
         if (rc != QP_OK) return rc;
         const int64_t n_det = x.n_det;
+        r.n_g = n_det;
+        if (x.gens) {
+            r.n_g = x.n_gen;
+            r.gen_rank = (int32_t *)scratch(c, s, B_GENR, sizeof(int32_t) * std::max<int64_t>(1, x.n_gen));
+            if (!r.gen_rank) return fail(c, QP_E_OOM, "device allocation failed (generator list)");
+            if (x.n_gen > 0) {
+                hipLaunchKernelGGL(map_gen_ranks, dim3(grid_for(x.n_gen)), dim3(256), 0, st, x.gens, x.n_gen,
+                                   r.P.rank, n_det, r.gen_rank, r.P.sc);
+                HIPCHK(c, hipMemcpyAsync(c->host_sc, r.P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipStreamSynchronize(st));
+                if (c->host_sc->bad_gen) return fail(c, QP_E_ARG, "a listed generator is outside [0, n_det)");
+            }
+        }
+        const int64_t n_g = r.n_g;
         const int nel = r.P.nel;
         const int nb = nel + nel * (nel - 1) / 2;
+        // the same split as a sweep over every generator, so that a listed
+        // generator's results do not depend on the list
         r.Q = items_per_generator(n_det, nb, bwd);
-        r.n_items = n_det * r.Q;
+        r.n_items = n_g * r.Q;
         r.swept = r.n_items > 0 && nel > 0;
         const int64_t ni = std::max<int64_t>(1, r.n_items);
         r.eps_item = (double *)scratch(c, s, B_EPSI, sizeof(double) * ni * ns);
@@ -1219,12 +1265,13 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         r.fp_item = (uint64_t *)scratch(c, s, B_FPI, sizeof(uint64_t) * ni);
         r.dc_item = bwd ? (double *)scratch(c, s, B_DCI, sizeof(double) * ni * ns) : nullptr;
         r.conn_item = (uint32_t *)scratch(c, s, B_CONNI, sizeof(uint32_t) * ni);
-        r.eps_g = (double *)scratch(c, s, B_EPSG, sizeof(double) * n_det * ns);
-        r.S_g = (double *)scratch(c, s, B_SG, sizeof(double) * n_det * ns);
-        r.cnt_g = (uint64_t *)scratch(c, s, B_CNTG, sizeof(uint64_t) * n_det);
-        r.fp_g = (uint64_t *)scratch(c, s, B_FPG, sizeof(uint64_t) * n_det);
-        r.conn_g = (uint64_t *)scratch(c, s, B_CONNG, sizeof(uint64_t) * n_det);
-        r.defa_g = (uint64_t *)scratch(c, s, B_DEFAG, sizeof(uint64_t) * n_det);
+        const int64_t ng1 = std::max<int64_t>(1, n_g);
+        r.eps_g = (double *)scratch(c, s, B_EPSG, sizeof(double) * ng1 * ns);
+        r.S_g = (double *)scratch(c, s, B_SG, sizeof(double) * ng1 * ns);
+        r.cnt_g = (uint64_t *)scratch(c, s, B_CNTG, sizeof(uint64_t) * ng1);
+        r.fp_g = (uint64_t *)scratch(c, s, B_FPG, sizeof(uint64_t) * ng1);
+        r.conn_g = (uint64_t *)scratch(c, s, B_CONNG, sizeof(uint64_t) * ng1);
+        r.defa_g = (uint64_t *)scratch(c, s, B_DEFAG, sizeof(uint64_t) * ng1);
         unsigned int *hist = (unsigned int *)scratch(c, s, B_HIST, sizeof(unsigned int) * QP_HIST_BINS);
         // batches the dense kernel hands to the general kernel: one bit per
         // (generator rank, batch), then a list in (rank, batch) order
@@ -1264,6 +1311,8 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         a.perm = r.P.perm; a.F = r.P.F; a.HII = r.P.HII; a.coff = r.P.coff; a.cent = r.P.cent;
         a.n_items = r.n_items;
         a.q_per_gen = r.Q;
+        a.gen_list = r.gen_rank;
+        a.n_gen = n_g;
         a.flags = (fp ? 1 : 0) | (bwd ? 2 : 0);
         a.eps_item = r.eps_item; a.S_item = r.S_item; a.cnt_item = r.cnt_item; a.fp_item = r.fp_item;
         a.conn_item = r.conn_item;
@@ -1364,16 +1413,18 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         if (x.n_det == 0) continue;
         const int ns = x.ns;
         if (r.swept)
-            hipLaunchKernelGGL(reduce_items, dim3(grid_for(x.n_det)), dim3(256), 0, st, r.eps_item, r.S_item,
+            hipLaunchKernelGGL(reduce_items, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.eps_item, r.S_item,
                                r.cnt_item, fp ? r.fp_item : (const uint64_t *)nullptr, r.conn_item, r.dc_item,
-                               x.n_det, r.Q, ns, r.P.perm, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g, r.defa_g,
-                               bwd ? nullptr : x.eps_gen, bwd ? x.grad_coefs : nullptr, r.dp);
-        else
-            hipLaunchKernelGGL(reduce_empty, dim3(grid_for(x.n_det)), dim3(256), 0, st, x.n_det, ns, r.P.perm,
-                               r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g, r.defa_g, bwd ? nullptr : x.eps_gen);
-        const int64_t n_cells = x.n_det * cells_per_generator(x.I.n, r.P.nup, r.P.ndn);
+                               r.n_g, r.Q, ns, r.P.perm, (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g,
+                               r.cnt_g, r.fp_g, r.conn_g, r.defa_g, bwd ? nullptr : x.eps_gen,
+                               bwd ? x.grad_coefs : nullptr, r.dp);
+        else if (r.n_g > 0)
+            hipLaunchKernelGGL(reduce_empty, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.n_g, ns, r.P.perm,
+                               (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
+                               r.defa_g, bwd ? nullptr : x.eps_gen);
+        const int64_t n_cells = r.n_g * cells_per_generator(x.I.n, r.P.nup, r.P.ndn);
         hipLaunchKernelGGL(reduce_total, dim3(1), dim3(256), 0, st, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
-                           r.defa_g, x.n_det, ns, x.e_pt2, x.stats, r.P.sc, n_cells, x.gup,
+                           r.defa_g, r.n_g, ns, x.e_pt2, x.stats, r.P.sc, n_cells, x.gup,
                            bwd ? x.grad_E0 : nullptr, x.E0);
         HIPCHK(c, hipGetLastError());
     }
@@ -1552,6 +1603,180 @@ int qp_pt2_backward(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_
     x.stats = stats; x.gup = grad_e_pt2;
     x.grad_coefs = grad_coefs; x.grad_E0 = grad_E0; x.grad_h = grad_h;
     return run_sweeps(c, in, flags, true, (hipStream_t)stream);
+}
+
+int qp_generator_order(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int n_states,
+                       int flags, int32_t *order_out, void *stream)
+{
+    int rc = common_checks(c, dets, coefs, n_det, n_states, coefs);
+    if (rc != QP_OK) return rc;
+    if (n_det > 0 && !order_out) return fail(c, QP_E_ARG, "order_out is required");
+    if (n_det == 0) return QP_OK;
+    hipStream_t st = (hipStream_t)stream;
+    Prepared P;
+    rc = prepare(c, 0, dev_ints(c), dets, coefs, n_det, n_states, flags, st, P);
+    if (rc != QP_OK) return rc;
+    HIPCHK(c, hipMemcpyAsync(order_out, P.perm, sizeof(int32_t) * n_det, hipMemcpyDeviceToDevice, st));
+    return QP_OK;
+}
+
+int qp_pt2_generators(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int n_states,
+                      const double *E0, const int32_t *gens, int64_t n_gen, int64_t n_select, int flags,
+                      double *eps_out, uint64_t *sel_dets, double *sel_e, int64_t *n_sel, qp_pt2_stats *stats,
+                      void *stream)
+{
+    int rc = common_checks(c, dets, coefs, n_det, n_states, E0);
+    if (rc != QP_OK) return rc;
+    if (n_gen < 0 || n_gen > n_det) return fail(c, QP_E_ARG, "n_gen must be in [0, n_det]");
+    if (n_gen > 0 && (!gens || !eps_out)) return fail(c, QP_E_ARG, "gens and eps_out are required");
+    if (n_select < 0) return fail(c, QP_E_ARG, "n_select < 0");
+    if (n_select > 0 && (!sel_dets || !sel_e || !n_sel)) return fail(c, QP_E_ARG, "selection outputs required");
+    if (n_select > (int64_t)INT32_MAX / 4) return fail(c, QP_E_ARG, "n_select too large");
+    std::vector<SysIn> in(1);
+    SysIn &x = in[0];
+    memset(&x, 0, sizeof(x));
+    x.I = dev_ints(c);
+    x.dets = dets; x.coefs = coefs; x.n_det = n_det; x.ns = n_states; x.E0 = E0;
+    x.gens = gens; x.n_gen = n_gen;
+    x.n_select = n_select; x.sel_dets = sel_dets; x.sel_e = sel_e; x.n_sel = n_sel;
+    x.stats = stats; x.eps_gen = eps_out;
+    return run_sweeps(c, in, flags, false, (hipStream_t)stream);
+}
+
+int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int n_states,
+                      const double *E0, const double *uniforms, int64_t n_uniforms, double rel_err,
+                      int64_t det_chunk, int64_t draws_per_round, int flags, double *e_est, double *e_err,
+                      int64_t *n_computed, int64_t *n_rounds, void *stream)
+{
+    int rc = common_checks(c, dets, coefs, n_det, n_states, E0);
+    if (rc != QP_OK) return rc;
+    if (!e_est || !e_err || !n_computed || !n_rounds) return fail(c, QP_E_ARG, "outputs are required");
+    if (n_uniforms < 0 || (n_uniforms > 0 && !uniforms)) return fail(c, QP_E_ARG, "bad uniform list");
+    if (det_chunk < 1 || draws_per_round < 0 || !(rel_err >= 0.0)) return fail(c, QP_E_ARG, "bad schedule");
+    const int ns = n_states;
+    for (int k = 0; k < ns; ++k) { e_est[k] = 0.0; e_err[k] = 0.0; }
+    *n_computed = 0;
+    *n_rounds = 0;
+    if (n_det == 0) return QP_OK;
+    hipStream_t st = (hipStream_t)stream;
+    // generator order and weights w_r = sum_k c_k(det of rank r)^2
+    std::vector<int32_t> perm(n_det);
+    std::vector<double> ch((size_t)ns * n_det);
+    {
+        Prepared P;
+        rc = prepare(c, 0, dev_ints(c), dets, coefs, n_det, ns, flags, st, P);
+        if (rc != QP_OK) return rc;
+        HIPCHK(c, hipMemcpyAsync(perm.data(), P.perm, sizeof(int32_t) * n_det, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(ch.data(), coefs, sizeof(double) * ns * n_det, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
+    std::vector<double> w(n_det), cum(n_det), tail(n_det + 1, 0.0);
+    double run = 0.0;
+    for (int64_t r = 0; r < n_det; ++r) {
+        double v = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            const double x = ch[(size_t)k * n_det + perm[r]];
+            v += x * x;
+        }
+        w[r] = v;
+        run += v;
+        cum[r] = run;
+    }
+    for (int64_t r = n_det - 1; r >= 0; --r) tail[r] = tail[r + 1] + w[r];   // weight of ranks >= r
+    const double W = run;
+    // memoised eps_r,k, the draw log, and the deterministic prefix [0, d)
+    std::vector<double> eps((size_t)n_det * ns, 0.0);
+    std::vector<char> done(n_det, 0);
+    std::vector<int64_t> draws;
+    int64_t d = 0, next_u = 0, computed = 0, rounds = 0;
+    std::vector<double> det_sum(ns, 0.0);
+    int32_t *dgen = (int32_t *)scratch(c, 0, B_ROW, sizeof(int32_t) * n_det);
+    double *deps = (double *)scratch(c, 0, B_C2, sizeof(double) * n_det * ns);
+    int32_t *hgen = nullptr;
+    double *heps = nullptr;
+    if (!dgen || !deps) return fail(c, QP_E_OOM, "device allocation failed (stochastic driver)");
+    if (hipHostMalloc((void **)&hgen, sizeof(int32_t) * n_det, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&heps, sizeof(double) * n_det * ns, hipHostMallocDefault) != hipSuccess) {
+        if (hgen) (void)hipHostFree(hgen);
+        return fail(c, QP_E_OOM, "pinned host allocation failed (stochastic driver)");
+    }
+    auto cleanup = [&]() { (void)hipHostFree(hgen); (void)hipHostFree(heps); };
+    std::vector<int64_t> todo;
+    for (;;) {
+        // one round: the deterministic prefix grows by det_chunk generators and
+        // draws_per_round generators are drawn with probability w_r / W
+        todo.clear();
+        const int64_t d_new = std::min<int64_t>(n_det, d + det_chunk);
+        for (int64_t r = d; r < d_new; ++r)
+            if (!done[r]) todo.push_back(r);
+        int64_t drawn = 0;
+        while (drawn < draws_per_round && next_u < n_uniforms && W > 0.0) {
+            const double t = uniforms[next_u++] * W;
+            int64_t r = std::upper_bound(cum.begin(), cum.end(), t) - cum.begin();
+            if (r >= n_det) r = n_det - 1;
+            draws.push_back(r);
+            ++drawn;
+            if (r >= d_new && !done[r] && std::find(todo.begin(), todo.end(), r) == todo.end()) todo.push_back(r);
+        }
+        if (!todo.empty()) {
+            for (size_t i = 0; i < todo.size(); ++i) hgen[i] = perm[todo[i]];
+            const int64_t m = (int64_t)todo.size();
+            HIPCHK(c, hipMemcpyAsync(dgen, hgen, sizeof(int32_t) * m, hipMemcpyHostToDevice, st));
+            std::vector<SysIn> in(1);
+            SysIn &x = in[0];
+            memset(&x, 0, sizeof(x));
+            x.I = dev_ints(c);
+            x.dets = dets; x.coefs = coefs; x.n_det = n_det; x.ns = ns; x.E0 = E0;
+            x.gens = dgen; x.n_gen = m; x.eps_gen = deps;
+            rc = run_sweeps(c, in, flags | QP_FLAG_NOCHECK, false, st);
+            if (rc != QP_OK) { cleanup(); return rc; }
+            HIPCHK(c, hipMemcpyAsync(heps, deps, sizeof(double) * m * ns, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            for (int64_t i = 0; i < m; ++i) {
+                const int64_t r = todo[i];
+                for (int k = 0; k < ns; ++k) eps[(size_t)r * ns + k] = heps[(size_t)k * m + i];
+                done[r] = 1;
+            }
+            computed += m;
+        }
+        for (int64_t r = d; r < d_new; ++r)
+            for (int k = 0; k < ns; ++k) det_sum[k] += eps[(size_t)r * ns + k];
+        d = d_new;
+        ++rounds;
+        // estimate: the prefix exactly, the rest by the draws that fall in it,
+        // each weighted by W_S / w_r (W_S the weight of the rest)
+        bool converged = true;
+        if (d == n_det) {
+            for (int k = 0; k < ns; ++k) { e_est[k] = det_sum[k]; e_err[k] = 0.0; }
+        } else {
+            const double WS = tail[d];
+            int64_t mS = 0;
+            for (int64_t r : draws) mS += r >= d;
+            for (int k = 0; k < ns; ++k) {
+                double mean = 0.0, m2 = 0.0;
+                int64_t j = 0;
+                for (int64_t r : draws) {
+                    if (r < d) continue;
+                    const double y = WS * eps[(size_t)r * ns + k] / w[r];
+                    ++j;
+                    const double dlt = y - mean;
+                    mean += dlt / (double)j;
+                    m2 += dlt * (y - mean);
+                }
+                e_est[k] = det_sum[k] + (mS > 0 ? mean : 0.0);
+                e_err[k] = mS > 1 ? std::sqrt(m2 / (double)(mS - 1) / (double)mS) : HUGE_VAL;
+                if (!(mS > 1 && e_err[k] <= rel_err * std::fabs(e_est[k]))) converged = false;
+            }
+        }
+        // stop when every state meets the relative error, when the prefix
+        // covers every generator, or when the random numbers run out
+        if (d == n_det || converged) break;
+        if (draws_per_round > 0 && next_u >= n_uniforms) break;
+    }
+    cleanup();
+    *n_computed = computed;
+    *n_rounds = rounds;
+    return QP_OK;
 }
 
 int qp_pt2_batched(qp_ctx *c, int n_sys, const qp_system *sys, int with_backward, int flags, void *stream)

@@ -286,8 +286,12 @@ struct SweepArgs {
     const double *HII;        // [rank]
     const int64_t *coff;      // [n_det+1], by rank
     const CoarseEnt *cent;
-    int64_t n_items;          // dense kernel: n_det * q_per_gen; general kernel: listed batches
+    int64_t n_items;          // dense kernel: n_gen * q_per_gen; general kernel: listed batches
     int q_per_gen;            // work items per generator
+    // the generators of the call: ranks 0..n_det-1 (gen_list null, n_gen = n_det)
+    // or the ranks gen_list[0..n_gen-1]
+    const int32_t *gen_list;
+    int64_t n_gen;
     // dense kernel: buffer capacities; batches it hands over are marked in
     // def_bits (nbw words per generator rank, bit b = batch b)
     int rscap, cscap;

@@ -235,9 +235,12 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
             gup[k] = BWD ? a.gup[k] : 0.0;
         }
 
-        const int q = (int)(item / a.n_det);
-        const int64_t g = item - (int64_t)q * a.n_det;
-        const int64_t slot = g * Q + q;
+        // items run q-major over the call's generators: every rank, or a list
+        // of ranks; g is the generator's rank, slot the item's partials
+        const int q = (int)(item / a.n_gen);
+        const int64_t gi = item - (int64_t)q * a.n_gen;
+        const int64_t g = a.gen_list ? (int64_t)a.gen_list[gi] : gi;
+        const int64_t slot = gi * Q + q;
         const int det = a.perm[g];
 
         uint64_t Ib[2 * NINT];

@@ -179,10 +179,11 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
             bstride = nb;
             slot = item;
         } else {
-            q = (int)(item / a.n_det);
-            g = item - (int64_t)q * a.n_det;
+            q = (int)(item / a.n_gen);
+            const int64_t gi = item - (int64_t)q * a.n_gen;
+            g = a.gen_list ? (int64_t)a.gen_list[gi] : gi;
             bstride = Q;
-            slot = g * Q + q;
+            slot = gi * Q + q;
         }
         const int det = a.perm[g];
 

@@ -361,3 +361,8 @@ def batched_workload(n_sys: int = 64, seed: int = 1004,
         out.append(make_system(f"c4_sys{i}", sseed, n_orb, nup, ndn, nd,
                                n_states=ns, n_select=0))
     return out
+
+
+def uniforms(seed: int, count: int) -> np.ndarray:
+    """Seeded random numbers in [0, 1), e.g. the draws of a stochastic estimate."""
+    return np.random.default_rng(seed).random(count)

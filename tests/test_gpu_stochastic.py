@@ -1,0 +1,127 @@
+"""GPU parity of the generator-list sweep and the semi-stochastic E_PT2
+(sec. "CIPSI selection and PT2 energy", hybrid deterministic/stochastic
+scheme): the generator order against the oracle's; eps_I of listed
+generators bit-identical to the full sweep's and within 1e-10 of the
+oracle's; the selection over listed generators; the stochastic estimate
+against the oracle's estimator fed the same random numbers, and at full size
+against the deterministic E_PT2."""
+import numpy as np
+import pytest
+
+from gpu_helpers import U, gpu_system, run_gpu
+from oracle import oracle as orc
+from paper_1902_08154_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1902_08154_amd.api import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _mid():
+    return synth.make_system("st_n24_4a4b", 2024, 24, 4, 4, 300, n_states=2)
+
+
+def test_generator_order_matches_oracle(ctx):
+    s = _mid()
+    dets, coefs = gpu_system(ctx, s)
+    order = ctx.generator_order(dets, coefs).cpu().numpy()
+    assert np.array_equal(order, np.argsort(orc.generator_rank(s.dets, s.coefs)))
+
+
+def test_generator_list_matches_full_sweep_and_oracle(ctx):
+    import torch
+    s = _mid()
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    full = run_gpu(ctx, s, E0, n_select=0)
+    rng = np.random.default_rng(5)
+    gens = rng.choice(s.n_det, 37, replace=False).astype(np.int32)
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    r = ctx.pt2_generators(dets, coefs, E0t, torch.from_numpy(gens), n_select=40, fingerprint=True)
+    eps = r["eps"].cpu().numpy()
+    assert eps.tobytes() == np.ascontiguousarray(full["eps_gen"][:, gens]).tobytes()
+    o = orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens)
+    assert r["stats"]["n_alpha"] == int(o.count.sum())
+    for k in range(s.n_states):
+        tol = 1e-10 * np.abs(o.eps[:, k]) + 32 * U * (abs(E0[k]) + 1) * o.S[:, k] + 1e-15
+        assert np.all(np.abs(eps[k] - o.eps[:, k]) <= tol)
+    # the selection: owned by listed generators, and complete above its cut
+    from paper_1902_08154_amd.api import from_device_dets
+    sel = from_device_dets(r["sel_dets"])
+    sel_e = r["sel_e"].cpu().numpy()
+    maxc2 = (s.coefs ** 2).max(axis=1)
+    keys = np.abs((sel_e / maxc2).sum(axis=1))
+    rank = orc.generator_rank(s.dets, s.coefs)
+    listed = set(int(rank[g]) for g in gens)
+    for a in sel:
+        _, _, own, internal = orc.alpha_eval(s.n_orb, s.h, s.eri, s.dets, s.coefs, rank, a)
+        assert not internal and own in listed
+    od = orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens, dump_thr=keys[-1] * (1 + 1e-6),
+                            dump_cap=200)
+    chosen = {bytes(d.tobytes()) for d in sel}
+    for i in range(len(gens)):
+        assert od.dump_n[i] < 200
+        for t in range(od.dump_n[i]):
+            assert bytes(od.dump_dets[i, t].tobytes()) in chosen
+
+
+def _oracle_estimate(s, E0, u, rel_err, chunk, draws):
+    order = np.argsort(orc.generator_rank(s.dets, s.coefs))
+    w = (s.coefs[:, order] ** 2).sum(axis=0)
+
+    def eps_of(ranks):
+        return orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, order[np.asarray(ranks)]).eps
+
+    return orc.semistochastic(eps_of, w, u, rel_err, chunk, draws)
+
+
+def test_stochastic_matches_oracle_estimator(ctx):
+    import torch
+    s = _mid()
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    u = synth.uniforms(11, 90)
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    g = ctx.pt2_stochastic(dets, coefs, E0t, u, rel_err=0.0, det_chunk=20, draws_per_round=30)
+    est, err, nc, nr = _oracle_estimate(s, E0, u, 0.0, 20, 30)
+    assert (g["n_computed"], g["n_rounds"]) == (nc, nr) and nr == 3
+    full = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0)
+    scale = full.abs_e + np.abs(est)
+    assert np.all(np.abs(g["e_pt2"] - est) <= 1e-8 * scale), (g["e_pt2"], est)
+    assert np.all(np.abs(g["err"] - err) <= 1e-8 * scale + 1e-8 * err)
+
+
+def test_stochastic_completes_to_the_deterministic_value(ctx):
+    import torch
+    s = _mid()
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    g = ctx.pt2_stochastic(dets, coefs, E0t, synth.uniforms(1, 10), rel_err=0.0, det_chunk=s.n_det,
+                           draws_per_round=5)
+    full = run_gpu(ctx, s, E0, n_select=0)
+    assert g["n_computed"] == s.n_det and g["n_rounds"] == 1 and np.all(g["err"] == 0)
+    assert np.all(np.abs(g["e_pt2"] - full["e_pt2"]) <= 1e-12 * np.abs(full["eps_gen"]).sum(axis=1))
+
+
+def test_stochastic_c2_full_size(ctx):
+    """c2 with the paper's stopping criterion |dE/E| = 0.002."""
+    import torch
+    s = synth.workload(2)
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    full = run_gpu(ctx, s, E0, n_select=0, eps_gen=False)
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    g = ctx.pt2_stochastic(dets, coefs, E0t, synth.uniforms(2019, 200000), rel_err=0.002, det_chunk=100,
+                           draws_per_round=400)
+    print("stochastic", g, "deterministic", full["e_pt2"], flush=True)
+    e, err = g["e_pt2"][0], g["err"][0]
+    assert err <= 0.002 * abs(e)
+    assert abs(e - full["e_pt2"][0]) <= 4 * err
+    assert g["n_computed"] < s.n_det

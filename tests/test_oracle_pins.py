@@ -502,3 +502,46 @@ def test_generator_mode_and_alpha_eval_agree_with_full(orc):
         assert np.allclose(N, full.all_N[i], rtol=1e-12, atol=1e-14)
         assert abs(D - full.all_D[i]) < 1e-12
         assert inv[own] == full.all_owner[i]
+
+
+# ------------------------------------------------ semi-stochastic estimate
+def _eps_by_rank(orc, s):
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    order = np.argsort(orc.generator_rank(s.dets, s.coefs))
+    o = orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, order)
+    w = (s.coefs[:, order] ** 2).sum(axis=0)
+    return o.eps, w
+
+
+def test_semistochastic_is_exact_once_deterministic(orc):
+    """With the deterministic prefix covering every generator the estimate is
+    the plain sum of eps_I (the generator decomposition) and its error is 0."""
+    s = synth.workload(1)
+    eps, w = _eps_by_rank(orc, s)
+    exact = np.zeros(eps.shape[1])
+    for r in range(len(w)):
+        exact = exact + eps[r]
+    est, err, nc, nr = orc.semistochastic(lambda rs: eps[rs], w, [], 0.002, len(w), 0)
+    assert np.array_equal(est, exact) and np.all(err == 0) and nc == len(w) and nr == 1
+    est, err, nc, nr = orc.semistochastic(lambda rs: eps[rs], w, [], 0.002, 7, 0)
+    assert np.array_equal(est, exact) and nr == -(-len(w) // 7)
+
+
+def test_semistochastic_is_unbiased_with_calibrated_errors(orc):
+    """Over many seeds the estimate averages to the exact E_PT2 (draws with
+    probability w_r / W restricted to the stochastic part are unbiased), and
+    the exact value lies within two reported standard errors about as often
+    as a normal error bar says."""
+    s = synth.make_system("ss_n16", 77, 16, 3, 3, 120, n_states=1)
+    eps, w = _eps_by_rank(orc, s)
+    exact = float(eps[:, 0].sum())
+    ests, hits = [], 0
+    for seed in range(600):
+        u = synth.uniforms(seed, 40)
+        est, err, _, nr = orc.semistochastic(lambda rs: eps[rs], w, u, 0.0, 10, 40)
+        assert nr == 1
+        ests.append(est[0])
+        hits += abs(est[0] - exact) <= 2 * err[0]
+    ests = np.array(ests)
+    assert abs(ests.mean() - exact) <= 4 * ests.std() / np.sqrt(len(ests))
+    assert 0.85 <= hits / len(ests) <= 1.0
