@@ -135,6 +135,34 @@ __device__ __forceinline__ double wsum(double v)
     return v;
 }
 
+// one DPP step on a double: lane i receives src from the lane the control
+// names (0 where that lane is outside the row, or the row is masked off)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// sum over the 64 lanes with cross-lane data moves inside the VALU (DPP)
+// rather than through the LDS crossbar: a scan within each 16-lane row, then
+// row 0 -> 1 and 2 -> 3, then rows 0-1 -> 2-3; lane 63 holds the total
+__device__ __forceinline__ double wsum_dpp(double v)
+{
+    v += dpp_f64<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_f64<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_f64<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_f64<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // <J|H|alpha> for alpha = I - holes + particles (generic Slater-Condon)
 template <int NINT, class Ints>
 __device__ __forceinline__ double celem(const Ints &I, const uint64_t *Ib, int hc0, int hc1, int pa, int sa,
@@ -983,7 +1011,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
 #pragma unroll
                                 for (int k = 0; k < NS; ++k) dcI[k] = fma(w[k], Hv, dcI[k]);
                                 vbatch += vsum;
-                                const double rsum = wsum(vsum);
+                                const double rsum = wsum_dpp(vsum);
                                 if (lane == 0 && rsum != 0.0) sDHD[pr] += rsum;
                                 colacc += vsum;
                                 if (live && rowf) gather_bwd(r, l, w);
@@ -1104,7 +1132,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
 #pragma unroll
                                     for (int k = 0; k < NS; ++k) dcI[k] = fma(w[k], Hv, dcI[k]);
                                     vbatch += vsum;
-                                    const double sA = wsum(useA ? vsum : 0.0), sB = wsum(useA ? 0.0 : vsum);
+                                    const double sA = wsum_dpp(useA ? vsum : 0.0), sB = wsum_dpp(useA ? 0.0 : vsum);
                                     if (lane == 0) {
                                         if (sA != 0.0) sDHD[ia & 255] += sA;
                                         if (sB != 0.0 && validB) sDHD[ib & 255] += sB;
