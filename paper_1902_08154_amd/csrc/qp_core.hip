@@ -437,6 +437,7 @@ __global__ void make_coff(const int64_t *offs, int64_t n_det, int nchunk, const 
 struct DefParts {
     const int64_t *off;
     const int32_t *cnt;
+    int parts;                // slots per listed batch
     const double *eps, *S, *dc;
     const uint32_t *alpha, *conn;
     const uint64_t *fp;
@@ -515,7 +516,7 @@ __global__ void reduce_items(const double *eps_item, const double *S_item, const
         cn += conn_item[sl];
         if (fp_item) f += fp_item[sl];
     }
-    const int64_t x0 = dp.off[g], x1 = x0 + dp.cnt[g];
+    const int64_t x0 = dp.off[g] * dp.parts, x1 = x0 + (int64_t)dp.cnt[g] * dp.parts;
     for (int64_t x = x0; x < x1; ++x) {
         for (int k = 0; k < ns; ++k) {
             e[k] += dp.eps[x * ns + k];
@@ -1064,6 +1065,9 @@ void launch_kernel(bool dense, int nint, int ns, const SweepArgs *sys, const int
 // updates of the n x n one-electron gradient.  Items are dealt round-robin,
 // without a shared counter.
 constexpr int Q_FORWARD = 16;
+// handed-over batches: up to 8 row parts each, aiming at 8192 general-kernel items
+constexpr int64_t DEF_PARTS_MAX = 8;
+constexpr int64_t DEF_PARTS_ITEMS = 8192;
 constexpr int Q_ADJOINT = 4;
 constexpr int64_t MAX_ITEMS = int64_t(1) << 25;
 
@@ -1368,7 +1372,12 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             SysRun &r = run[s];
             if (!r.swept) continue;
             const int ns = in[s].ns;
-            const int64_t m = std::max<int64_t>(1, r.n_def);
+            // a listed batch is split into row parts when there are few of them,
+            // so that the general kernel's time is not that of its largest batch;
+            // the split depends on the system alone
+            const int parts = (int)std::min<int64_t>(DEF_PARTS_MAX, std::max<int64_t>(
+                1, (DEF_PARTS_ITEMS + std::max<int64_t>(1, r.n_def) - 1) / std::max<int64_t>(1, r.n_def)));
+            const int64_t m = std::max<int64_t>(1, r.n_def) * parts;
             uint32_t *def_g = (uint32_t *)scratch(c, s, B_DEFG, sizeof(uint32_t) * m);
             uint32_t *def_b = (uint32_t *)scratch(c, s, B_DEFB, sizeof(uint32_t) * m);
             double *def_eps = (double *)scratch(c, s, B_DEFE, sizeof(double) * m * ns);
@@ -1383,6 +1392,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             r.dp.dc = def_dc;
             r.dp.off = r.def_off;
             r.dp.cnt = r.def_cnt_g;
+            r.dp.parts = parts;
             if (r.n_def > 0) {
                 hipLaunchKernelGGL(def_fill, dim3(grid_for(in[s].n_det)), dim3(256), 0, st, r.def_bits, in[s].n_det,
                                    r.nbw, r.def_off, def_g, def_b);
@@ -1391,10 +1401,11 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
                 d = r.a;
                 d.def_mode = 1;
                 d.def_g = def_g; d.def_b = def_b;
-                d.n_items = r.n_def;
+                d.def_parts = parts;
+                d.n_items = r.n_def * parts;
                 d.eps_item = def_eps; d.S_item = def_S; d.cnt_item = def_alpha; d.fp_item = def_fp;
                 d.conn_item = def_conn; d.dc_item = def_dc;
-                gitems[s] = r.n_def;
+                gitems[s] = r.n_def * parts;
             }
         }
     }

@@ -300,6 +300,7 @@ struct SweepArgs {
     // general kernel: its items are the marked batches, listed in (rank, batch) order
     int def_mode;
     const uint32_t *def_g, *def_b;
+    int def_parts;            // items per listed batch (row parts)
     int flags;                // bit0 fingerprint, bit1 backward
     // per-item partials (deterministic reduction later)
     double *eps_item;         // [n_items][ns]

@@ -170,12 +170,17 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
 #pragma unroll
         for (int k = 0; k < NS; ++k) { E0[k] = a.E0[k]; gup[k] = BWD ? a.gup[k] : 0.0; }
 
-        int q, bstride;
+        int q, bstride, part = 0, nparts = 1;
         int64_t g, slot;
         if (a.def_mode) {
-            // one listed batch per item; partials go to the item's own slot
-            g = a.def_g[item];
-            q = (int)a.def_b[item];
+            // one part of one listed batch per item: its rows rr = part mod
+            // nparts, so that a large batch does not rest on one wave; partials
+            // go to the item's own slot
+            nparts = a.def_parts;
+            const int64_t de = item / nparts;
+            part = (int)(item - de * nparts);
+            g = a.def_g[de];
+            q = (int)a.def_b[de];
             bstride = nb;
             slot = item;
         } else {
@@ -453,7 +458,7 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
                     csg = (B.sH + sCnt[B.cs * n + pcol] - (hcs < pcol)) & 1;
                     cbase = B.D0 + sF[B.cs * n + pcol] - a.I.JK[hcs * n + pcol] - a.I.Jm[hco * n + pcol];
                 }
-                for (int rr = 0; rr < nrow; ++rr) {
+                for (int rr = part; rr < nrow; rr += nparts) {
                     const int r = B.type == BT_SS ? rr + 1 : rr;
                     bool act = lane_ok;
                     int i1, i2;
