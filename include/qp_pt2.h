@@ -64,6 +64,7 @@ extern "C" {
 #define QP_E_HIP        -7  /* a HIP runtime call failed                        */
 #define QP_E_STATES     -8  /* n_states outside [1,4]                           */
 #define QP_E_OVERFLOW   -9  /* selection candidate buffer overflowed            */
+#define QP_E_NOCONV    -10  /* Davidson: residual above tolerance at the limit  */
 
 #define QP_MAX_STATES    4
 #define QP_MAX_ORB       256
@@ -72,6 +73,7 @@ extern "C" {
 /* qp_pt2 flags */
 #define QP_FLAG_FINGERPRINT  1  /* also compute stats.fingerprint of the alpha set */
 #define QP_FLAG_NOCHECK      2  /* skip input validation (duplicates, counts, bits) */
+#define QP_SIGMA_S2          8  /* qp_sigma: W = S^2 U instead of H U              */
 #define QP_FLAG_REUSE_INTEGRALS 4 /* qp_pt2_batched: keep a system's integral layouts
                                      from the previous batched call when its h and
                                      eri_packed pointers and n_orb are the same, and
@@ -282,6 +284,41 @@ typedef struct {
 
 int qp_pt2_batched(qp_ctx *ctx, int n_sys, const qp_system *sys, int with_backward, int flags,
                    void *stream);
+
+/*
+ * qp_sigma -- sigma vectors of a Davidson iteration over the determinant
+ * space of Psi (sec. "Davidson diagonalization", the H U product that
+ * dominates it): W = H U, or with QP_SIGMA_S2 in flags W = S^2 U, with
+ * S^2 = S_- S_+ + S_z (S_z + 1) applied by second quantisation in the
+ * canonical order (up spin-orbitals first).
+ *   U, W  device double [n_vec][n_det] (W overwritten)
+ * Matrix elements by the Slater-Condon rules as in qp_pt2.  Synchronises
+ * once (coarse-list sizes).  Errors: QP_E_ARG, QP_E_NOINT, QP_E_NORB,
+ * QP_E_ELEC, QP_E_DUP, QP_E_OOM, QP_E_HIP.
+ */
+int qp_sigma(qp_ctx *ctx, const uint64_t *dets, int64_t n_det, int n_vec, const double *U,
+             int flags, double *W, void *stream);
+
+/*
+ * qp_davidson -- the lowest n_states eigenpairs of H in the space of the
+ * given determinants (sec. "Davidson diagonalization"): Davidson iterations
+ * with the diagonal preconditioner, sigma vectors on the GPU (qp_sigma), the
+ * subspace problem on the host.  Converged when every residual
+ * ||H x - theta x|| < tol.
+ *   guess   device double [n_states][n_det] start vectors, or NULL (unit
+ *           vectors on the lowest diagonal elements)
+ *   E_out   HOST double [n_states] eigenvalues, ascending
+ *   C_out   device double [n_states][n_det] normalised eigenvectors, largest
+ *           component positive
+ *   s2_out  HOST double [n_states] <S^2> of each vector, or NULL
+ *   n_iter  HOST int [1] iterations used, or NULL
+ * The call is synchronous.  Errors: as qp_sigma, QP_E_STATES, and
+ * QP_E_NOCONV when max_iter iterations leave a residual above tol (the
+ * outputs then hold the last iterate).
+ */
+int qp_davidson(qp_ctx *ctx, const uint64_t *dets, int64_t n_det, int n_states, const double *guess,
+                double tol, int max_iter, int flags, double *E_out, double *C_out, double *s2_out,
+                int *n_iter, void *stream);
 
 /*
  * qp_energy -- variational energy E0_k = <Psi_k|H|Psi_k> / <Psi_k|Psi_k>

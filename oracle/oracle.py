@@ -57,6 +57,10 @@ def _load():
                                      _P, _P, _P, _P, _P]
         lib.orc_alpha_eval.restype = _I
         lib.orc_alpha_eval.argtypes = [_I, _I, _P, _P, _P, _P, _I64, _I, _P, _P, _P, _P, _P, _P]
+        lib.orc_hamiltonian.restype = _I
+        lib.orc_hamiltonian.argtypes = [_I, _I, _P, _P, _P, _I64, _P]
+        lib.orc_s2_matrix.restype = _I
+        lib.orc_s2_matrix.argtypes = [_I, _I, _P, _I64, _P]
         lib.orc_eps_generators.restype = _I
         lib.orc_eps_generators.argtypes = [_I, _I, _P, _P, _P, _P, _I64, _I, _P, _P, _I64,
                                            _P, _P, _P, _P, _D, _I64, _P, _P, _P, _P]
@@ -74,6 +78,25 @@ def _c(a, dtype):
 
 def _nint(dets):
     return dets.shape[-1]
+
+
+def hamiltonian(n_orb, h, eri, dets) -> np.ndarray:
+    """Dense H over the determinant list (Slater-Condon elements)."""
+    dets = _c(dets, np.uint64)
+    nd = dets.shape[0]
+    out = np.empty((nd, nd))
+    _load().orc_hamiltonian(n_orb, _nint(dets), _ptr(_c(h, np.float64)), _ptr(_c(eri, np.float64)), _ptr(dets),
+                            nd, _ptr(out))
+    return out
+
+
+def s2_matrix(n_orb, dets) -> np.ndarray:
+    """Dense S^2 over the determinant list, by operator application."""
+    dets = _c(dets, np.uint64)
+    nd = dets.shape[0]
+    out = np.empty((nd, nd))
+    _load().orc_s2_matrix(n_orb, _nint(dets), _ptr(dets), nd, _ptr(out))
+    return out
 
 
 def matrix_element(n_orb, h, eri, bra, ket) -> float:

@@ -907,3 +907,59 @@ int orc_eps_generators(int n, int nint, const double *h, const double *eri_packe
     free(rank);
     return fail ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Dense H and S^2 over a determinant list (sec. "Davidson diagonalization":  */
+/* the matrices whose lowest eigenpairs the Davidson iterations find).        */
+/* ------------------------------------------------------------------------ */
+
+/* H_IJ for every pair, from the Slater-Condon elements above; out [n_det][n_det] */
+int orc_hamiltonian(int n, int nint, const double *h, const double *eri_packed, const u64 *dets,
+                    int64_t n_det, double *out)
+{
+    orc_ints I = {n, nint, h, eri_packed};
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < n_det; ++i)
+        for (int64_t j = 0; j < n_det; ++j) {
+            const u64 *a = dets + (size_t)i * 2 * nint, *b = dets + (size_t)j * 2 * nint;
+            const int deg = excitation_degree(a, b, nint);
+            double v = 0.0;
+            if (deg == 0) v = orc_diagonal(&I, a);
+            else if (deg <= 2) v = offdiag_element(&I, a, b, NULL, NULL);
+            out[(size_t)i * n_det + j] = v;
+        }
+    return 0;
+}
+
+/* S^2 = S_- S_+ + S_z (S_z + 1), S_+ = sum_p a+(p,up) a(p,down),
+ * S_- = sum_q a+(q,down) a(q,up), applied to each determinant by operator
+ * application; out [n_det][n_det], <I|S^2|J> */
+int orc_s2_matrix(int n, int nint, const u64 *dets, int64_t n_det, double *out)
+{
+    for (size_t x = 0; x < (size_t)n_det * n_det; ++x) out[x] = 0.0;
+    u64 d[2 * 4], e[2 * 4];
+    for (int64_t j = 0; j < n_det; ++j) {
+        const u64 *ket = dets + (size_t)j * 2 * nint;
+        int nup = 0, ndn = 0;
+        for (int w = 0; w < nint; ++w) { nup += popcount64(ket[w]); ndn += popcount64(ket[nint + w]); }
+        const double sz = 0.5 * (nup - ndn);
+        out[(size_t)j * n_det + j] += sz * (sz + 1.0);
+        for (int p = 0; p < n; ++p)
+            for (int q = 0; q < n; ++q) {
+                for (int w = 0; w < 2 * nint; ++w) d[w] = ket[w];
+                int sg = apply_op(d, nint, n, 0, 1, p);          /* a(p, down)  */
+                if (sg) sg *= apply_op(d, nint, n, 1, 0, p);     /* a+(p, up)   */
+                if (sg) sg *= apply_op(d, nint, n, 0, 0, q);     /* a(q, up)    */
+                if (sg) sg *= apply_op(d, nint, n, 1, 1, q);     /* a+(q, down) */
+                if (!sg) continue;
+                for (int64_t i = 0; i < n_det; ++i) {
+                    const u64 *bra = dets + (size_t)i * 2 * nint;
+                    int same = 1;
+                    for (int w = 0; w < 2 * nint; ++w) if (bra[w] != d[w]) { same = 0; break; }
+                    if (same) { out[(size_t)i * n_det + j] += sg; break; }
+                }
+                (void)e;
+            }
+    }
+    return 0;
+}

@@ -18,17 +18,19 @@ QP_E_OOM = -6
 QP_E_HIP = -7
 QP_E_STATES = -8
 QP_E_OVERFLOW = -9
+QP_E_NOCONV = -10
 
 QP_FLAG_FINGERPRINT = 1
 QP_FLAG_NOCHECK = 2
 QP_FLAG_REUSE_INTEGRALS = 4
+QP_SIGMA_S2 = 8
 QP_MAX_STATES = 4
 QP_MAX_SYSTEMS = 4096
 
 ERROR_NAMES = {
     QP_E_ARG: "QP_E_ARG", QP_E_NORB: "QP_E_NORB", QP_E_ELEC: "QP_E_ELEC", QP_E_DUP: "QP_E_DUP",
     QP_E_NOINT: "QP_E_NOINT", QP_E_OOM: "QP_E_OOM", QP_E_HIP: "QP_E_HIP", QP_E_STATES: "QP_E_STATES",
-    QP_E_OVERFLOW: "QP_E_OVERFLOW",
+    QP_E_OVERFLOW: "QP_E_OVERFLOW", QP_E_NOCONV: "QP_E_NOCONV",
 }
 
 
@@ -77,7 +79,7 @@ class System(ctypes.Structure):
 # every entry point declared in include/qp_pt2.h
 EXPORTS = ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
            "qp_pt2_backward", "qp_generator_order", "qp_pt2_generators", "qp_pt2_stochastic",
-           "qp_pt2_batched", "qp_energy", "qp_set_timing", "qp_last_timing")
+           "qp_pt2_batched", "qp_sigma", "qp_davidson", "qp_energy", "qp_set_timing", "qp_last_timing")
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -114,6 +116,10 @@ def load():
     lib.qp_pt2_stochastic.restype = _I
     lib.qp_pt2_batched.argtypes = [_P, _I, ctypes.POINTER(System), _I, _I, _P]
     lib.qp_pt2_batched.restype = _I
+    lib.qp_sigma.argtypes = [_P, _P, _I64, _I, _P, _I, _P, _P]
+    lib.qp_sigma.restype = _I
+    lib.qp_davidson.argtypes = [_P, _P, _I64, _I, _P, ctypes.c_double, _I, _I, _P, _P, _P, _P, _P]
+    lib.qp_davidson.restype = _I
     lib.qp_energy.argtypes = [_P, _P, _P, _I64, _I, _I, _P, _P]
     lib.qp_energy.restype = _I
     lib.qp_set_timing.argtypes = [_P, _I]

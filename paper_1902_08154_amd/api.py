@@ -125,6 +125,22 @@ class Context:
                                                 _stream(self.device)))
         return e, err, int(nc[0]), int(nr[0])
 
+    def qp_sigma(self, dets, U, W, flags=0):
+        self._check(self._lib.qp_sigma(self._h, _ptr(dets), dets.shape[0], U.shape[0], _ptr(U), flags, _ptr(W),
+                                       _stream(self.device)))
+
+    def qp_davidson(self, dets, n_states, guess, tol, max_iter, C_out, flags=0):
+        """Returns (E [ns] numpy, <S^2> [ns] numpy, iterations); C_out is filled."""
+        import numpy as np
+        e = np.zeros(n_states)
+        s2 = np.zeros(n_states)
+        it = (ctypes.c_int * 1)()
+        hp = lambda a: ctypes.c_void_p(a.ctypes.data)
+        self._check(self._lib.qp_davidson(self._h, _ptr(dets), dets.shape[0], n_states, _ptr(guess), float(tol),
+                                          int(max_iter), flags, hp(e), _ptr(C_out), hp(s2), it,
+                                          _stream(self.device)))
+        return e, s2, int(it[0])
+
     def qp_pt2_batched(self, systems, with_backward=False, flags=0):
         """systems: a sequence of _lib.System records."""
         arr = (_lib.System * max(len(systems), 1))(*systems)
@@ -225,6 +241,23 @@ class Context:
             draws_per_round = max(16, n // 64)
         e, err, nc, nr = self.qp_pt2_stochastic(dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round)
         return dict(e_pt2=e, err=err, n_computed=nc, n_rounds=nr)
+
+    def sigma(self, dets, U, s2=False):
+        """W = H U (or S^2 U) for U [n_vec, n_det] on the device."""
+        _need(dets, torch.int64, "dets", self.device)
+        U = U.to(device=self.device, dtype=torch.float64).contiguous()
+        W = torch.empty_like(U)
+        self.qp_sigma(dets, U, W, _lib.QP_SIGMA_S2 if s2 else 0)
+        return W
+
+    def davidson(self, dets, n_states=1, guess=None, tol=1e-9, max_iter=200):
+        """Lowest eigenpairs of H in the determinant space: dict(E, C [ns, n_det], s2, n_iter)."""
+        _need(dets, torch.int64, "dets", self.device)
+        C = torch.empty((n_states, dets.shape[0]), dtype=torch.float64, device=self.device)
+        if guess is not None:
+            guess = guess.to(device=self.device, dtype=torch.float64).contiguous()
+        e, s2, it = self.qp_davidson(dets, n_states, guess, tol, max_iter, C)
+        return dict(E=e, C=C, s2=s2, n_iter=it)
 
     def pt2_batched(self, systems, with_backward=False, fingerprint=False, check=True, reuse_integrals=False):
         """Many systems in one call.  `systems` is a sequence of dicts with

@@ -112,6 +112,12 @@ struct Scalars {
     int bad_gen;      // a listed generator index outside [0, n_det)
 };
 
+__global__ void fill_ones(double *x, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 1.0;
+}
+
 // generator weight w_J = sum_k c_Jk^2 ; inverse max c^2 per state
 __global__ void gen_weights(const double *coefs, int64_t n_det, int ns, double *w, int64_t P, int32_t *idx)
 {
@@ -677,6 +683,104 @@ __global__ void energy_rows(const DevInts I, const uint64_t *dets, const double 
     }
 }
 
+// ---------------------------------------------------------------- sigma
+// W = H U or W = S^2 U over the determinant space of Psi (the sigma vectors
+// of a Davidson iteration, sec. "Davidson diagonalization"), one thread per
+// determinant, from its coarse list (every J != I with degree <= 4).
+//
+// number of occupied spin-orbitals before (s, p) in the canonical order: all
+// up spin-orbitals, then all down ones, by increasing orbital
+template <int NINT>
+__device__ __forceinline__ int n_before(const uint64_t *d, int s, int p)
+{
+    int c = 0;
+    if (s == 1)
+        for (int w = 0; w < NINT; ++w) c += popc64(d[w]);
+    const uint64_t *ds = d + s * NINT;
+    for (int w = 0; w < NINT; ++w) {
+        if (64 * w + 63 < p) c += popc64(ds[w]);
+        else if (64 * w <= p) c += popc64(ds[w] & ((1ull << (p - 64 * w)) - 1ull));
+    }
+    return c;
+}
+
+// <J|S_- S_+|I> for J = I with the spins of orbitals p (down in I) and q (up
+// in I) exchanged: the operator string a+(q,dn) a(q,up) a+(p,up) a(p,dn)
+// applied to I, one operator at a time
+template <int NINT>
+__device__ __forceinline__ double spin_exchange(const uint64_t *Ib, int p, int q)
+{
+    uint64_t d[2 * NINT];
+#pragma unroll
+    for (int w = 0; w < 2 * NINT; ++w) d[w] = Ib[w];
+    int sgn = 0;
+    auto op = [&](int s, int o) {
+        sgn += n_before<NINT>(d, s, o);
+        d[s * NINT + (o >> 6)] ^= 1ull << (o & 63);
+    };
+    op(1, p);   // a(p, down)
+    op(0, p);   // a+(p, up)
+    op(0, q);   // a(q, up)
+    op(1, q);   // a+(q, down)
+    return (sgn & 1) ? -1.0 : 1.0;
+}
+
+template <int NINT, bool S2>
+__global__ void sigma_rows(const DevInts I, const uint64_t *dets, const int32_t *perm, const double *HII,
+                           const int64_t *coff, const CoarseEnt *cent, int64_t n_det, int n_vec, double sz,
+                           const double *U, double *W)
+{
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_det; g += (int64_t)gridDim.x * blockDim.x) {
+        const int det = perm[g];
+        uint64_t Ib[2 * NINT];
+#pragma unroll
+        for (int w = 0; w < 2 * NINT; ++w) Ib[w] = dets[(int64_t)det * 2 * NINT + w];
+        double diag;
+        if (S2) {
+            // S^2 = S_- S_+ + S_z (S_z + 1): S_- S_+ counts the down electrons
+            // whose orbital has no up electron
+            int nb = 0;
+#pragma unroll
+            for (int w = 0; w < NINT; ++w) nb += popc64(Ib[NINT + w] & ~Ib[w]);
+            diag = sz * (sz + 1.0) + nb;
+        } else {
+            diag = HII[g];
+        }
+        for (int v0 = 0; v0 < n_vec; v0 += 4) {
+            double acc[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = v0 + t < n_vec ? diag * U[(int64_t)(v0 + t) * n_det + det] : 0.0;
+            for (int64_t e = coff[g]; e < coff[g + 1]; ++e) {
+                const CoarseEnt ce = cent[e];
+                const int deg = ce.flags >> 8;
+                double v;
+                if (S2) {
+                    // a spin exchange: I \ J = {q up, p down}, J \ I = {p up, q down}
+                    if (deg != 2) continue;
+                    int du = -1, dd = -1, eu = -1, ed = -1;
+                    for (int t = 0; t < 2; ++t) {
+                        const int x = ce.D[t], y = ce.E[t];
+                        if (x >> 8) dd = x & 255; else du = x & 255;
+                        if (y >> 8) ed = y & 255; else eu = y & 255;
+                    }
+                    if (du < 0 || dd < 0 || eu != dd || ed != du || du == dd) continue;
+                    v = spin_exchange<NINT>(Ib, dd, du);
+                } else {
+                    if (deg > 2) continue;
+                    int dg;
+                    v = sc_offdiag<NINT>(I, Ib, dets + (int64_t)ce.j * 2 * NINT, &dg, nullptr);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (v0 + t < n_vec) acc[t] += v * U[(int64_t)(v0 + t) * n_det + ce.j];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (v0 + t < n_vec) W[(int64_t)(v0 + t) * n_det + det] = acc[t];
+        }
+    }
+}
+
 __global__ void energy_total(const double *row, const double *c2, int64_t n_det, int ns, double *E0)
 {
     __shared__ double sn[256][QPD_MAX_STATES], sd[256][QPD_MAX_STATES];
@@ -711,6 +815,8 @@ enum BufId {
     B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_GENR,
     // integral layouts of a system of a batched call
     B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
+    // Davidson
+    B_ONES, B_DU, B_DW,
     B_COUNT
 };
 
@@ -1494,6 +1600,85 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     return QP_OK;
 }
 
+// W = H U (or S^2 U) for n_vec vectors [n_vec][n_det], over a prepared Psi
+void launch_sigma(const DevInts &I, const Prepared &P, const uint64_t *dets, int64_t n_det, int n_vec, bool s2,
+                  const double *U, double *W, hipStream_t st)
+{
+    const double sz = 0.5 * (P.nup - P.ndn);
+    const int grid = grid_for(n_det, 64, 1 << 20);
+    switch (P.nint) {
+#define SIGCASE(NI)                                                                                        \
+    case NI:                                                                                               \
+        if (s2) hipLaunchKernelGGL((sigma_rows<NI, true>), dim3(grid), dim3(64), 0, st, I, dets, P.perm, P.HII, \
+                                   P.coff, P.cent, n_det, n_vec, sz, U, W);                                \
+        else hipLaunchKernelGGL((sigma_rows<NI, false>), dim3(grid), dim3(64), 0, st, I, dets, P.perm, P.HII, \
+                                P.coff, P.cent, n_det, n_vec, sz, U, W);                                   \
+        break;
+        SIGCASE(1) SIGCASE(2) SIGCASE(3) SIGCASE(4)
+#undef SIGCASE
+    default: break;
+    }
+}
+
+// eigen-decomposition of a small symmetric matrix a [m][m] (destroyed) by
+// cyclic Jacobi rotations; eigenvalues ascending in w, vectors in columns of v
+void jacobi_eigen(std::vector<double> &a, int m, std::vector<double> &w, std::vector<double> &v)
+{
+    v.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) v[(size_t)i * m + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                const double x = a[(size_t)i * m + j] * a[(size_t)i * m + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = a[(size_t)p * m + q];
+                if (apq == 0.0) continue;
+                const double app = a[(size_t)p * m + p], aqq = a[(size_t)q * m + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < m; ++k) {
+                    const double akp = a[(size_t)k * m + p], akq = a[(size_t)k * m + q];
+                    a[(size_t)k * m + p] = cs * akp - sn * akq;
+                    a[(size_t)k * m + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < m; ++k) {
+                    const double apk = a[(size_t)p * m + k], aqk = a[(size_t)q * m + k];
+                    a[(size_t)p * m + k] = cs * apk - sn * aqk;
+                    a[(size_t)q * m + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < m; ++k) {
+                    const double vkp = v[(size_t)k * m + p], vkq = v[(size_t)k * m + q];
+                    v[(size_t)k * m + p] = cs * vkp - sn * vkq;
+                    v[(size_t)k * m + q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    std::vector<int> idx(m);
+    for (int i = 0; i < m; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a[(size_t)x * m + x] < a[(size_t)y * m + y]; });
+    std::vector<double> v2((size_t)m * m);
+    w.resize(m);
+    for (int j = 0; j < m; ++j) {
+        w[j] = a[(size_t)idx[j] * m + idx[j]];
+        for (int k = 0; k < m; ++k) v2[(size_t)k * m + j] = v[(size_t)k * m + idx[j]];
+    }
+    v.swap(v2);
+}
+
+double dotv(const double *x, const double *y, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1851,6 +2036,186 @@ int qp_pt2_batched(qp_ctx *c, int n_sys, const qp_system *sys, int with_backward
         }
     }
     return run_sweeps(c, in, flags & ~QP_FLAG_REUSE_INTEGRALS, with_backward != 0, st);
+}
+
+int qp_sigma(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_vec, const double *U, int flags, double *W,
+             void *stream)
+{
+    if (!c) return QP_E_ARG;
+    c->err.clear();
+    if (n_det < 0 || n_vec < 0) return fail(c, QP_E_ARG, "negative size");
+    if (c->n <= 0) return fail(c, QP_E_NOINT, "integrals not set");
+    if (n_det == 0 || n_vec == 0) return QP_OK;
+    if (!dets || !U || !W) return fail(c, QP_E_ARG, "null pointer");
+    if (n_det > (int64_t)INT32_MAX / 2) return fail(c, QP_E_ARG, "n_det too large");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    // the generator order does not matter here: every weight is 1
+    double *ones = (double *)scratch(c, 0, B_ONES, sizeof(double) * n_det);
+    if (!ones) return fail(c, QP_E_OOM, "device allocation failed");
+    hipLaunchKernelGGL(fill_ones, dim3(grid_for(n_det)), dim3(256), 0, st, ones, n_det);
+    const DevInts I = dev_ints(c);
+    Prepared P;
+    int rc = prepare(c, 0, I, dets, ones, n_det, 1, flags & ~QP_SIGMA_S2, st, P);
+    if (rc != QP_OK) return rc;
+    launch_sigma(I, P, dets, n_det, n_vec, (flags & QP_SIGMA_S2) != 0, U, W, st);
+    HIPCHK(c, hipGetLastError());
+    return QP_OK;
+}
+
+int qp_davidson(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_states, const double *guess, double tol,
+                int max_iter, int flags, double *E_out, double *C_out, double *s2_out, int *n_iter, void *stream)
+{
+    if (!c) return QP_E_ARG;
+    c->err.clear();
+    if (n_det < 1) return fail(c, QP_E_ARG, "n_det must be >= 1");
+    if (n_states < 1 || n_states > QP_MAX_STATES) return fail(c, QP_E_STATES, "n_states must be in [1,4]");
+    if (n_states > n_det) return fail(c, QP_E_ARG, "more states than determinants");
+    if (!dets || !E_out || !C_out) return fail(c, QP_E_ARG, "null pointer");
+    if (!(tol > 0.0) || max_iter < 1) return fail(c, QP_E_ARG, "bad tolerance or iteration limit");
+    if (c->n <= 0) return fail(c, QP_E_NOINT, "integrals not set");
+    if (n_det > (int64_t)INT32_MAX / 2) return fail(c, QP_E_ARG, "n_det too large");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int ns = n_states;
+    const int64_t N = n_det;
+    double *ones = (double *)scratch(c, 0, B_ONES, sizeof(double) * N);
+    if (!ones) return fail(c, QP_E_OOM, "device allocation failed");
+    hipLaunchKernelGGL(fill_ones, dim3(grid_for(N)), dim3(256), 0, st, ones, N);
+    const DevInts I = dev_ints(c);
+    Prepared P;
+    int rc = prepare(c, 0, I, dets, ones, N, 1, flags, st, P);
+    if (rc != QP_OK) return rc;
+    // the diagonal, by determinant, for the preconditioner
+    std::vector<double> hrank(N), diag(N);
+    std::vector<int32_t> perm(N);
+    HIPCHK(c, hipMemcpyAsync(hrank.data(), P.HII, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(perm.data(), P.perm, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (int64_t r = 0; r < N; ++r) diag[perm[r]] = hrank[r];
+    const int max_sub = std::min<int64_t>(N, std::max(8 * ns, 24));
+    double *dU = (double *)scratch(c, 0, B_DU, sizeof(double) * N * max_sub);
+    double *dW = (double *)scratch(c, 0, B_DW, sizeof(double) * N * max_sub);
+    if (!dU || !dW) return fail(c, QP_E_OOM, "device allocation failed (Davidson)");
+    std::vector<std::vector<double>> V, HV;
+    auto add_vectors = [&](std::vector<std::vector<double>> &nv) -> int {
+        // orthonormalise against the basis and each other (twice), drop the rest
+        std::vector<std::vector<double>> keep;
+        for (auto &x : nv) {
+            for (int pass = 0; pass < 2; ++pass) {
+                for (auto &b : V) { const double d = dotv(b.data(), x.data(), N); for (int64_t i = 0; i < N; ++i) x[i] -= d * b[i]; }
+                for (auto &b : keep) { const double d = dotv(b.data(), x.data(), N); for (int64_t i = 0; i < N; ++i) x[i] -= d * b[i]; }
+            }
+            const double nrm = std::sqrt(dotv(x.data(), x.data(), N));
+            if (nrm < 1e-10) continue;
+            for (int64_t i = 0; i < N; ++i) x[i] /= nrm;
+            keep.push_back(x);
+            if ((int)(V.size() + keep.size()) >= max_sub) break;
+        }
+        const int k = (int)keep.size();
+        if (k == 0) return 0;
+        for (int j = 0; j < k; ++j)
+            if (hipMemcpyAsync(dU + (int64_t)j * N, keep[j].data(), sizeof(double) * N, hipMemcpyHostToDevice, st) != hipSuccess)
+                return -1;
+        launch_sigma(I, P, dets, N, k, false, dU, dW, st);
+        std::vector<double> w((size_t)k * N);
+        if (hipMemcpyAsync(w.data(), dW, sizeof(double) * N * k, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return -1;
+        for (int j = 0; j < k; ++j) {
+            V.push_back(keep[j]);
+            HV.emplace_back(w.begin() + (size_t)j * N, w.begin() + (size_t)(j + 1) * N);
+        }
+        return k;
+    };
+    // start: the guess, else unit vectors on the lowest diagonal elements
+    std::vector<std::vector<double>> start(ns, std::vector<double>(N, 0.0));
+    if (guess) {
+        std::vector<double> g((size_t)ns * N);
+        HIPCHK(c, hipMemcpyAsync(g.data(), guess, sizeof(double) * ns * N, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        for (int k = 0; k < ns; ++k) std::copy(g.begin() + (size_t)k * N, g.begin() + (size_t)(k + 1) * N, start[k].begin());
+    } else {
+        std::vector<int64_t> idx(N);
+        for (int64_t i = 0; i < N; ++i) idx[i] = i;
+        std::partial_sort(idx.begin(), idx.begin() + ns, idx.end(),
+                          [&](int64_t x, int64_t y) { return diag[x] < diag[y] || (diag[x] == diag[y] && x < y); });
+        for (int k = 0; k < ns; ++k) start[k][idx[k]] = 1.0;
+    }
+    if (add_vectors(start) < 0) return fail(c, QP_E_HIP, "Davidson transfer failed");
+    std::vector<double> theta;
+    std::vector<std::vector<double>> X(ns, std::vector<double>(N)), R(ns, std::vector<double>(N));
+    int it = 0;
+    bool converged = false;
+    for (; it < max_iter; ++it) {
+        const int m = (int)V.size();
+        std::vector<double> G((size_t)m * m), y;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j <= i; ++j) {
+                const double g = 0.5 * (dotv(V[i].data(), HV[j].data(), N) + dotv(V[j].data(), HV[i].data(), N));
+                G[(size_t)i * m + j] = G[(size_t)j * m + i] = g;
+            }
+        jacobi_eigen(G, m, theta, y);
+        double rmax = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            std::fill(X[k].begin(), X[k].end(), 0.0);
+            std::fill(R[k].begin(), R[k].end(), 0.0);
+            for (int j = 0; j < m; ++j) {
+                const double yk = y[(size_t)j * m + k];
+                for (int64_t i = 0; i < N; ++i) { X[k][i] += yk * V[j][i]; R[k][i] += yk * HV[j][i]; }
+            }
+            for (int64_t i = 0; i < N; ++i) R[k][i] -= theta[k] * X[k][i];
+            rmax = std::max(rmax, std::sqrt(dotv(R[k].data(), R[k].data(), N)));
+        }
+        if (rmax < tol) { converged = true; break; }
+        // corrections from the diagonal preconditioner
+        std::vector<std::vector<double>> corr;
+        for (int k = 0; k < ns; ++k) {
+            if (std::sqrt(dotv(R[k].data(), R[k].data(), N)) < tol) continue;
+            std::vector<double> t(N);
+            for (int64_t i = 0; i < N; ++i) {
+                double d = theta[k] - diag[i];
+                if (std::fabs(d) < 1e-8) d = d < 0 ? -1e-8 : 1e-8;
+                t[i] = R[k][i] / d;
+            }
+            corr.push_back(std::move(t));
+        }
+        if ((int)V.size() + (int)corr.size() > max_sub) {
+            // restart from the current Ritz vectors
+            std::vector<std::vector<double>> HX(ns, std::vector<double>(N, 0.0));
+            for (int k = 0; k < ns; ++k)
+                for (int j = 0; j < m; ++j) {
+                    const double yk = y[(size_t)j * m + k];
+                    for (int64_t i = 0; i < N; ++i) HX[k][i] += yk * HV[j][i];
+                }
+            V.assign(X.begin(), X.end());
+            HV.swap(HX);
+        }
+        const int added = add_vectors(corr);
+        if (added < 0) return fail(c, QP_E_HIP, "Davidson transfer failed");
+        if (added == 0) break;
+    }
+    if (n_iter) *n_iter = it;
+    for (int k = 0; k < ns; ++k) E_out[k] = theta[k];
+    std::vector<double> cx((size_t)ns * N);
+    for (int k = 0; k < ns; ++k) {
+        // a fixed sign: the largest component positive
+        int64_t im = 0;
+        for (int64_t i = 1; i < N; ++i) if (std::fabs(X[k][i]) > std::fabs(X[k][im])) im = i;
+        const double sg = X[k][im] < 0 ? -1.0 : 1.0;
+        for (int64_t i = 0; i < N; ++i) cx[(size_t)k * N + i] = sg * X[k][i];
+    }
+    HIPCHK(c, hipMemcpyAsync(C_out, cx.data(), sizeof(double) * ns * N, hipMemcpyHostToDevice, st));
+    if (s2_out) {
+        launch_sigma(I, P, dets, N, ns, true, C_out, dW, st);
+        std::vector<double> sw((size_t)ns * N);
+        HIPCHK(c, hipMemcpyAsync(sw.data(), dW, sizeof(double) * ns * N, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        for (int k = 0; k < ns; ++k) s2_out[k] = dotv(cx.data() + (size_t)k * N, sw.data() + (size_t)k * N, N);
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (!converged) return fail(c, QP_E_NOCONV, "Davidson did not converge");
+    return QP_OK;
 }
 
 int qp_energy(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int n_states, int flags,

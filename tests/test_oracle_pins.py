@@ -545,3 +545,38 @@ def test_semistochastic_is_unbiased_with_calibrated_errors(orc):
     ests = np.array(ests)
     assert abs(ests.mean() - exact) <= 4 * ests.std() / np.sqrt(len(ests))
     assert 0.85 <= hits / len(ests) <= 1.0
+
+
+# --------------------------------------------- dense H and S^2 (Davidson)
+def test_dense_hamiltonian_matches_second_quantisation(orc):
+    n, nup, ndn = 5, 2, 2
+    h, eri, g = _tiny(n, nup, ndn, 91)
+    basis = sq.fci_space(n, nup, ndn)
+    H = orc.hamiltonian(n, h, eri, _words(basis, n))
+    Hs = sq.dense_hamiltonian(n, h, g, basis)
+    assert np.abs(H - Hs).max() < 1e-12
+    assert np.abs(H - H.T).max() < 1e-13
+
+
+def test_s2_spectrum_and_commutation(orc):
+    """On a full space of fixed S_z, S^2 has only eigenvalues S(S+1) with
+    S >= |S_z| in steps of 1, commutes with H, and a closed-shell determinant
+    is a singlet."""
+    for n, nup, ndn in ((4, 2, 2), (5, 3, 2), (4, 1, 1)):
+        h, eri, g = _tiny(n, nup, ndn, 17 + n)
+        basis = sq.fci_space(n, nup, ndn)
+        dets = _words(basis, n)
+        S2 = orc.s2_matrix(n, dets)
+        H = orc.hamiltonian(n, h, eri, dets)
+        assert np.abs(S2 - S2.T).max() < 1e-14
+        sz = 0.5 * (nup - ndn)
+        ev = np.linalg.eigvalsh(S2)
+        S = (-1 + np.sqrt(1 + 4 * ev)) / 2
+        assert np.all(np.abs(S - np.round(S - sz) - sz) < 1e-10) and np.all(S > abs(sz) - 1e-10)
+        assert np.abs(H @ S2 - S2 @ H).max() < 1e-10 * max(1.0, np.abs(H).max())
+    closed = sq.fci_space(4, 2, 2)
+    w = _words(closed, 4)
+    S2 = orc.s2_matrix(4, w)
+    for i, d in enumerate(w):
+        if d[0][0] == d[1][0]:   # every orbital doubly occupied or empty
+            assert S2[i, i] == 0.0 and np.all(S2[i] == 0.0)
