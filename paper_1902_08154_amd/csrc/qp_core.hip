@@ -105,7 +105,7 @@ struct Scalars {
     unsigned long long min_delta_bits;
     unsigned long long coarse_total;
     unsigned long long comp_count;
-    long long def_count;                // batches deferred to the general kernel
+    long long pad1;
     int bad_bits;     // a bit set at >= n_orb
     int bad_elec;     // electron counts differ from det 0
     int dup;          // duplicate determinant
