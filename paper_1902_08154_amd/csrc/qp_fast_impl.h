@@ -187,6 +187,7 @@ inline size_t lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap)
     add(16 * nvm);                    // column-spin particle table
     add(8 * rscap * nvm);             // row buffers
     add(4 * (bwd ? rscap * nvm : 1)); // row buffer single-excitation info (adjoint)
+    add(4 * (bwd ? cscap * nvm : 1)); // column buffer single-excitation info (adjoint)
     add(8 * cscap * nvm);             // column buffers
     add(8 * FCAP * ns);             // fine coefficients
     add(8 * L2CAP);                 // list values
@@ -240,6 +241,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
         PEnt *sCT = carve<PEnt>(lds, off, nvm);
         double *sRB = carve<double>(lds, off, RSCAP * nvm);
         uint32_t *sRI = carve<uint32_t>(lds, off, BWD ? RSCAP * nvm : 1);
+        uint32_t *sCI = carve<uint32_t>(lds, off, BWD ? CSCAP * nvm : 1);
         double *sCB = carve<double>(lds, off, CSCAP * nvm);
         double *sFC = carve<double>(lds, off, FCAP * NS);
         double *sLH = carve<double>(lds, off, L2CAP);
@@ -429,8 +431,10 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         // J lacks only holes of this batch: it is connected to every
                         // cell.  If it precedes the generator, it owns them all.
                         if (fe.earlier & 1) { allban = true; break; }
-                        // the adjoint leaves integral planes to the general kernel
-                        if (BWD) { slow = true; break; }
+                        // the adjoint of two or more states, or of three or more
+                        // words per spin, leaves integral planes to the general
+                        // kernel: their code would cost it registers
+                        if (BWD && !(NS == 1 && NINT <= 2)) { slow = true; break; }
                         // J = I - H + E_J is itself a cell when it lacks both holes:
                         // that cell is internal
                         const bool caseA = (fe.ner + fe.nec) == (type == BT_SINGLE ? 1 : 2);
@@ -611,16 +615,19 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 const uint64_t *Jb = a.dets + (int64_t)fe.j * 2 * NINT;
                 for (int r = lane; r < nr; r += WAVE) {
                     double v = 0.0;
+                    uint32_t sci = 0u;
                     // OS: cells (r, col), r not in E_r; SS: cells (col, r), r > col, r not in E
                     const bool use = !has(fe.er, fe.ner, r) && (type == BT_OS || r > col);
                     if (use) {
                         int pa, sa, pb, sb;
                         if (type == BT_OS) { pa = rvirt[r]; sa = rs; pb = cvirt[col]; sb = cs; }
                         else { pa = rvirt[col]; pb = rvirt[r]; sa = sb = rs; }
-                        int deg;
-                        v = celem<NINT>(a.I, Ib, hc0, hc1, pa, sa, pb, sb, Jb, &deg, nullptr);
+                        int deg, sgl[4] = {-1, -1, 0, 0};
+                        v = celem<NINT>(a.I, Ib, hc0, hc1, pa, sa, pb, sb, Jb, &deg, BWD ? sgl : nullptr);
+                        if (BWD) sci = deg == 1 ? (uint32_t)(sgl[0] | (sgl[1] << 8) | ((sgl[3] < 0) << 16) | (1u << 17)) : 0u;
                     }
                     sCB[s * nvm + r] = v;
+                    if (BWD) sCI[s * nvm + r] = sci;
                 }
             }
             if (BWD) for (int x = lane; x < FCAP * NS; x += WAVE) sDCF[x] = 0.0;
@@ -716,6 +723,18 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         const double hv = sCB[s * nvm + rowi];
 #pragma unroll
                         for (int k = 0; k < NS; ++k) atomicAdd(&sDCF[f * NS + k], w[k] * hv);
+                        // a single excitation J -> alpha (the lines of an integral
+                        // plane can be): its one-electron part feeds dE/dh
+                        const uint32_t inf = sCI[s * nvm + rowi];
+                        if (((inf >> 17) & 1u) && a.dh) {
+                            double gs = 0.0;
+#pragma unroll
+                            for (int k = 0; k < NS; ++k) gs += w[k] * sFC[f * NS + k];
+                            const double gg = 0.5 * (((inf >> 16) & 1u) ? -gs : gs);
+                            const int hh = inf & 255, pp = (inf >> 8) & 255;
+                            atomicAdd(&a.dh[(int64_t)hh * n + pp], gg);
+                            atomicAdd(&a.dh[(int64_t)pp * n + hh], gg);
+                        }
                     }
                 }
                 for (int t = 0; t < nl; ++t) {
@@ -841,6 +860,21 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
             // one cell of a batch with integral planes, evaluated exactly: u1/u2
             // are the plane bits of its first/second index, o_norm/o_tran its
             // offset in a plane block read as [first][second] or transposed
+            double pdc[PCAP][NS];
+#pragma unroll
+            for (int k = 0; k < PCAP; ++k)
+#pragma unroll
+                for (int t = 0; t < NS; ++t) pdc[k][t] = 0.0;
+            auto plane_flush = [&]() {
+                if (!BWD) return;
+#pragma unroll
+                for (int k = 0; k < PCAP; ++k)
+#pragma unroll
+                    for (int t = 0; t < NS; ++t) {
+                        const double v = wsum_dpp(pdc[k][t]);
+                        if (k < npl && lane == 0 && v != 0.0) sDCF[((sPL[k] >> 16) & 255) * NS + t] += v;
+                    }
+            };
             auto plane_cell = [&](int i1, int i2, double x, uint32_t sg, double D, int pa, int pb, uint32_t u1,
                                   uint32_t u2, int o_norm, int o_tran, bool needg) {
                 const double Hv = flip(x, sg);
@@ -886,20 +920,17 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                     }
                     if (live) {
                         if (needg) gather_bwd(i1, i2, w);
+                        // dE/dc of the planes' J: lane sums, reduced after the loop
 #pragma unroll
-                        for (int k = 0; k < PCAP; ++k) {
-                            if (vv[k] != 0.0) {
-                                const int f = (sPL[k] >> 16) & 255;
+                        for (int k = 0; k < PCAP; ++k)
 #pragma unroll
-                                for (int t = 0; t < NS; ++t) atomicAdd(&sDCF[f * NS + t], w[t] * vv[k]);
-                            }
-                        }
+                            for (int t = 0; t < NS; ++t) pdc[k][t] = fma(w[t], vv[k], pdc[k][t]);
                     }
                 }
             };
 
             // --------------------------------------------------- dense pass
-            if (!BWD && type == BT_OS && npl > 0) {
+            if ((!BWD || (NS == 1 && NINT <= 2)) && type == BT_OS && npl > 0) {
                 if (lane == 0) cnt += (uint32_t)(nr * nc);
                 const double *Jm = a.I.Jm;
                 for (int c0 = 0; c0 < nc; c0 += WAVE) {
@@ -917,7 +948,8 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         }
                     }
                 }
-            } else if (!BWD && type == BT_SS && npl > 0) {
+                plane_flush();
+            } else if ((!BWD || (NS == 1 && NINT <= 2)) && type == BT_SS && npl > 0) {
                 if (lane == 0) cnt += (uint32_t)(nr * (nr - 1) / 2);
                 const double *JK = a.I.JK;
                 const uint32_t shb = sH ? SGN : 0u;
@@ -937,6 +969,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         }
                     }
                 }
+                plane_flush();
             } else if (type == BT_OS) {
                 if (lane == 0) cnt += (uint32_t)(nr * nc);
                 const double *Jm = a.I.Jm;
