@@ -44,8 +44,8 @@ def log(*a):
 DENSE_SOURCES = ["qp_dev.h", "qp_fast_caps.h", "qp_fast_impl.h", "qp_fast_fwd.hip"]
 MEASURED_TRAFFIC = {
     "c2_n64_10a10b_1e4det_top1000": {
-        "sources_sha256": "d47bc2c43a2474753593715be2877df5ccd99e7c7cd82129348702e76063d24b",
-        "bytes": 46077463757 + 44849664,
+        "sources_sha256": "e6bf8748964fbfb9e10f57231b939193ceaae6abf1ada52585825ce166a15120",
+        "bytes": 46076670720 + 44515264,
     },
 }
 
