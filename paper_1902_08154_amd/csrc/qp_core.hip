@@ -839,6 +839,7 @@ struct qp_ctx {
     DevBuf args[2];                // per-launch system descriptors (dense, general)
     DevBuf defn;                   // per-system count of handed-over batches
     int num_cu = 256;
+    size_t lds_per_cu = 163840;
     Scalars *host_sc = nullptr;    // pinned, one per system
     int host_sc_n = 0;
     uint64_t *host_det0 = nullptr; // pinned
@@ -1123,6 +1124,18 @@ int persistent_grid(qp_ctx *c, bool dense, int nint, int ns, bool bwd, size_t ld
     case 2: per_cu = dense ? fast_occ_t<2>(ns, bwd, lds, fp) : sweep_occ_t<2>(ns, bwd, lds); break;
     case 3: per_cu = dense ? fast_occ_t<3>(ns, bwd, lds, fp) : sweep_occ_t<3>(ns, bwd, lds); break;
     default: per_cu = dense ? fast_occ_t<4>(ns, bwd, lds, fp) : sweep_occ_t<4>(ns, bwd, lds); break;
+    }
+    // The hardware allocates a workgroup's LDS in granules, which the runtime's
+    // occupancy figure does not round to: where the rounded size leaves room
+    // for fewer workgroups, a persistent grid sized by the runtime would leave
+    // the surplus workgroups waiting for a free slot, and their share of the
+    // statically dealt items would run after everyone else's.  The size is
+    // rounded to both 512 and 1280 bytes, whichever is larger, to stay on the
+    // safe side of the granule.
+    if (lds > 0) {
+        const size_t r512 = (lds + 511) / 512 * 512, r1280 = (lds + 1279) / 1280 * 1280;
+        const int fit = (int)(c->lds_per_cu / (r512 > r1280 ? r512 : r1280));
+        if (fit < per_cu) per_cu = fit;
     }
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 32) per_cu = 32;
@@ -1697,8 +1710,10 @@ int qp_create(qp_ctx **ctx, int device)
     c->device = device;
     if (hipSetDevice(device) != hipSuccess) { delete c; return QP_E_HIP; }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
         c->num_cu = prop.multiProcessorCount;
+        if (prop.maxSharedMemoryPerMultiProcessor > 0) c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+    }
     if (hipHostMalloc((void **)&c->host_sc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->host_det0, sizeof(uint64_t) * 2 * QPD_MAX_NINT, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&c->host_maxc2, sizeof(double) * QPD_MAX_STATES, hipHostMallocDefault) != hipSuccess) {

@@ -875,18 +875,22 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         if (k < npl && lane == 0 && v != 0.0) sDCF[((sPL[k] >> 16) & 255) * NS + t] += v;
                     }
             };
+            // act false: a lane with no cell (the adjoint runs every lane so that
+            // row sums can be wave reductions); it adds nothing.  vs returns the
+            // cell's sum over states of g A^2 / delta^2 for dE/dh's diagonal.
             auto plane_cell = [&](int i1, int i2, double x, uint32_t sg, double D, int pa, int pb, uint32_t u1,
-                                  uint32_t u2, int o_norm, int o_tran, bool needg) {
-                const double Hv = flip(x, sg);
+                                  uint32_t u2, int o_norm, int o_tran, bool needg, bool act, double &vs) {
+                const double Hv = act ? flip(x, sg) : 0.0;
                 double A[NS], vv[PCAP];
 #pragma unroll
                 for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
+                if (!act) D = DEAD_D;
                 uint32_t nco = 0;
 #pragma unroll
                 for (int k = 0; k < PCAP; ++k) {
                     vv[k] = 0.0;
                     const uint32_t b1 = u1 >> (4 * k), b2 = u2 >> (4 * k);
-                    if (k < npl && !((b1 & 2u) | (b2 & 8u))) {
+                    if (act && k < npl && !((b1 & 2u) | (b2 & 8u))) {
                         const uint32_t desc = sPL[k];
                         const double v = pblk[k][((desc >> 24) & 1u) ? o_norm : o_tran];
                         vv[k] = ((b1 ^ (b2 >> 2)) & 1u) ? -v : v;
@@ -896,8 +900,8 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         nco++;
                     }
                 }
-                bool live = true;
-                if (needg && gather(i1, i2, A, nco)) {
+                bool live = act;
+                if (act && needg && gather(i1, i2, A, nco)) {
                     live = false; D = DEAD_D; nban++;
 #pragma unroll
                     for (int k = 0; k < NS; ++k) A[k] = 0.0;
@@ -905,6 +909,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 if (live) conn += nco;
                 double ek[NS], w[NS], vsum;
                 const double tsel = finish(A, D, ek, w, vsum);
+                vs = vsum;
                 if (FP && live) fpsum += fold(pa, pb);
                 {
                     const bool c = live && fabs(tsel) >= tau_val;
@@ -914,10 +919,6 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
 #pragma unroll
                     for (int k = 0; k < NS; ++k) dcI[k] = fma(w[k], Hv, dcI[k]);
                     vbatch += vsum;
-                    if (vsum != 0.0) {
-                        atomicAdd(&sDHD[pa], vsum);
-                        atomicAdd(&sDHD[pb], vsum);
-                    }
                     if (live) {
                         if (needg) gather_bwd(i1, i2, w);
                         // dE/dc of the planes' J: lane sums, reduced after the loop
@@ -935,17 +936,27 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 const double *Jm = a.I.Jm;
                 for (int c0 = 0; c0 < nc; c0 += WAVE) {
                     const int l = c0 + lane;
-                    if (l < nc) {
-                        const PEnt ce = sCT[l];
+                    const bool lok = l < nc;
+                    if (BWD || lok) {
+                        const PEnt ce = sCT[lok ? l : nc - 1];
                         const int pcol = ce.info & 255;
+                        double colacc = 0.0;
                         for (int r = 0; r < nr; ++r) {
                             const PEnt re = sRT[r];
                             const int pr = re.info & 255;
                             const double xj = Jm[pr * n + pcol];
+                            double vs;
                             plane_cell(r, l, blk[pr * n + pcol], re.info ^ ce.info, (ce.G + re.G) + xj, pr, pcol,
                                        re.pad, ce.pad, pr * n + pcol, pcol * n + pr,
-                                       ((re.info & FR) | (ce.info & FC)) != 0u);
+                                       ((re.info & FR) | (ce.info & FC)) != 0u, lok, vs);
+                            if (BWD) {
+                                // the row's orbital is the same on every lane
+                                const double rsum = wsum_dpp(vs);
+                                if (lane == 0 && rsum != 0.0) sDHD[pr] += rsum;
+                                colacc += vs;
+                            }
                         }
+                        if (BWD && lok && colacc != 0.0) atomicAdd(&sDHD[pcol], colacc);
                     }
                 }
                 plane_flush();
@@ -958,14 +969,28 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                     const int l = c0 + lane;
                     for (int r = 1; r <= nfr; ++r) {
                         const bool pA = l < r;
-                        if (l < nr && (pA || nr - r > r)) {
-                            const int i1 = pA ? l : l - r, i2 = pA ? r : nr - r;
+                        const bool act = l < nr && (pA || nr - r > r);
+                        if (BWD || act) {
+                            // folded row r: cells (l, r) for l < r, (l - r, nr - r) after
+                            const bool useA = pA || !act;
+                            const int i1 = act ? (pA ? l : l - r) : 0, i2 = useA ? r : nr - r;
                             const PEnt e1 = sRT[i1], e2 = sRT[i2];
                             const int p1 = e1.info & 255, p2 = e2.info & 255;
                             const int off = p2 * (p2 - 1) / 2 + p1;
                             const double xj = JK[p2 * n + p1];
+                            double vs;
                             plane_cell(i1, i2, blk[off], e1.info ^ e2.info ^ shb, ((D0 + e2.G) + e1.G) + xj, p1, p2,
-                                       e1.pad, e2.pad, off, off, ((e2.info & FR) | (e1.info & FC)) != 0u);
+                                       e1.pad, e2.pad, off, off, ((e2.info & FR) | (e1.info & FC)) != 0u, act, vs);
+                            if (BWD) {
+                                // the second index is r on the lanes of part A and nr - r
+                                // on those of part B
+                                const double sA = wsum_dpp(useA ? vs : 0.0), sB = wsum_dpp(useA ? 0.0 : vs);
+                                if (lane == 0) {
+                                    if (sA != 0.0) sDHD[sRT[r].info & 255] += sA;
+                                    if (sB != 0.0) sDHD[sRT[nr - r].info & 255] += sB;
+                                }
+                                if (vs != 0.0) atomicAdd(&sDHD[p1], vs);
+                            }
                         }
                     }
                 }
