@@ -144,6 +144,50 @@ def batched_bench(ctx, dev, steps):
     return out
 
 
+def next_rows_bench(ctx, dev, s, dets, coefs, E0, steps):
+    """The rows built on the sweep, on the same workload: the semi-stochastic
+    E_PT2 to |dE/E| = 0.002 (against a deterministic sweep without selection),
+    the sigma-build W = H U and W = S^2 U, and the Davidson diagonaliser started
+    from the wave function's own coefficients."""
+    import torch
+    from paper_1902_08154_amd import synth
+
+    def timed(fn):
+        r = fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / steps, r
+
+    out = {}
+    t_det, r_det = timed(lambda: ctx.pt2(dets, coefs, E0))
+    u = synth.uniforms(2019, 200000)
+    t_sto, g = timed(lambda: ctx.pt2_stochastic(dets, coefs, E0, u, rel_err=0.002, det_chunk=256,
+                                                draws_per_round=1024))
+    out["semistochastic"] = {"rel_err": 0.002, "det_chunk": 256, "draws_per_round": 1024, "ms": t_sto,
+                             "deterministic_ms": t_det,
+                             "n_computed": g["n_computed"], "n_det": s.n_det, "n_rounds": g["n_rounds"],
+                             "e_pt2": float(g["e_pt2"][0]), "err": float(g["err"][0]),
+                             "e_pt2_deterministic": float(r_det["e_pt2"][0].item())}
+    log(f"semi-stochastic: {t_sto:.1f} ms ({g['n_computed']} of {s.n_det} generators, {g['n_rounds']} rounds), "
+        f"deterministic {t_det:.1f} ms")
+    gen = torch.Generator().manual_seed(7)
+    U4 = torch.rand((4, s.n_det), generator=gen, dtype=torch.float64).to(dev)
+    sig = {}
+    for name, U, s2 in (("H_1vec", coefs, False), ("H_4vec", U4, False), ("S2_1vec", coefs, True)):
+        sig[name + "_ms"], _ = timed(lambda: ctx.sigma(dets, U, s2=s2))
+    out["sigma"] = sig
+    t0 = time.perf_counter()
+    r = ctx.davidson(dets, n_states=1, guess=coefs, tol=1e-8, max_iter=400)
+    torch.cuda.synchronize()
+    out["davidson"] = {"ms": 1e3 * (time.perf_counter() - t0), "n_iter": r["n_iter"], "tol": 1e-8,
+                       "E": float(r["E"][0])}
+    log(f"sigma-build: {sig}; davidson {out['davidson']['ms']:.1f} ms, {r['n_iter']} iterations")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +198,8 @@ def main():
     ap.add_argument("--bwd-steps", type=int, default=2)
     ap.add_argument("--batched-steps", type=int, default=2,
                     help="timed repetitions of the 64-system batched workload (0: skip it)")
+    ap.add_argument("--next-steps", type=int, default=1,
+                    help="timed repetitions of the semi-stochastic PT2 and the sigma-build (0: skip them)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the steps, copy MIB MiB device to device once: a transfer of known size "
                          "against which the HBM traffic counters of the sweep are scaled")
@@ -243,6 +289,9 @@ def main():
 
     if args.batched_steps > 0:
         extra["batched"] = batched_bench(ctx, dev, args.batched_steps)
+
+    if args.next_steps > 0:
+        extra["next"] = next_rows_bench(ctx, dev, s, dets, coefs, E0, args.next_steps)
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8

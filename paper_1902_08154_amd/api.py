@@ -235,10 +235,12 @@ class Context:
         per draw.  Returns dict(e_pt2, err, n_computed, n_rounds)."""
         self._inputs(dets, coefs, E0)
         n = dets.shape[0]
+        # rounds large enough to keep the device busy: each one is a sweep launch
+        # followed by a host decision
         if det_chunk is None:
-            det_chunk = max(1, n // 64)
+            det_chunk = max(1, n // 40)
         if draws_per_round is None:
-            draws_per_round = max(16, n // 64)
+            draws_per_round = max(16, 4 * det_chunk)
         e, err, nc, nr = self.qp_pt2_stochastic(dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round)
         return dict(e_pt2=e, err=err, n_computed=nc, n_rounds=nr)
 

@@ -112,6 +112,20 @@ struct Scalars {
     int bad_gen;      // a listed generator index outside [0, n_det)
 };
 
+// the per-sweep fields of the scalars, as a fresh preparation leaves them; the
+// fields that describe the inputs (coarse-list size, input checks) are kept
+__global__ void reset_sweep_scalars(Scalars *sc)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->tau_bin = 0;
+        sc->cand_count = 0ull;
+        sc->overflow = 0ull;
+        sc->min_delta_bits = 0x7ff0000000000000ull;
+        sc->comp_count = 0ull;
+        sc->bad_gen = 0;
+    }
+}
+
 __global__ void fill_ones(double *x, int64_t n)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1217,6 +1231,9 @@ struct SysIn {
     double *eps_gen;
     const double *gup;
     double *grad_coefs, *grad_E0, *grad_h;
+    // order, generator tables and coarse lists already prepared in this
+    // system's slot from these same inputs (null: prepare them)
+    const Prepared *pre;
 };
 
 // per-system state between the phases of a sweep call
@@ -1357,8 +1374,13 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             if (bwd && x.grad_h) HIPCHK(c, hipMemsetAsync(x.grad_h, 0, sizeof(double) * n * n, st));
             continue;
         }
-        int rc = prepare(c, s, x.I, x.dets, x.coefs, x.n_det, ns, flags, st, r.P);
-        if (rc != QP_OK) return rc;
+        if (x.pre) {
+            r.P = *x.pre;
+            hipLaunchKernelGGL(reset_sweep_scalars, dim3(1), dim3(1), 0, st, r.P.sc);
+        } else {
+            int rc = prepare(c, s, x.I, x.dets, x.coefs, x.n_det, ns, flags, st, r.P);
+            if (rc != QP_OK) return rc;
+        }
         const int64_t n_det = x.n_det;
         r.n_g = n_det;
         if (x.gens) {
@@ -1873,8 +1895,9 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
     // generator order and weights w_r = sum_k c_k(det of rank r)^2
     std::vector<int32_t> perm(n_det);
     std::vector<double> ch((size_t)ns * n_det);
+    // prepared once: every round sweeps a list of generators of the same inputs
+    Prepared P;
     {
-        Prepared P;
         rc = prepare(c, 0, dev_ints(c), dets, coefs, n_det, ns, flags, st, P);
         if (rc != QP_OK) return rc;
         HIPCHK(c, hipMemcpyAsync(perm.data(), P.perm, sizeof(int32_t) * n_det, hipMemcpyDeviceToHost, st));
@@ -1939,6 +1962,7 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
             x.I = dev_ints(c);
             x.dets = dets; x.coefs = coefs; x.n_det = n_det; x.ns = ns; x.E0 = E0;
             x.gens = dgen; x.n_gen = m; x.eps_gen = deps;
+            x.pre = &P;
             rc = run_sweeps(c, in, flags | QP_FLAG_NOCHECK, false, st);
             if (rc != QP_OK) { cleanup(); return rc; }
             HIPCHK(c, hipMemcpyAsync(heps, deps, sizeof(double) * m * ns, hipMemcpyDeviceToHost, st));
