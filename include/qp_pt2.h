@@ -72,7 +72,9 @@ extern "C" {
 
 /* qp_pt2 flags */
 #define QP_FLAG_FINGERPRINT  1  /* also compute stats.fingerprint of the alpha set */
-#define QP_FLAG_NOCHECK      2  /* skip input validation (duplicates, counts, bits) */
+#define QP_FLAG_NOCHECK      2  /* skip input validation (duplicates, counts, bits,
+                                   generator indices: an index outside [0, n_det)
+                                   is then swept as generator rank 0)            */
 #define QP_SIGMA_S2          8  /* qp_sigma: W = S^2 U instead of H U              */
 #define QP_FLAG_REUSE_INTEGRALS 4 /* qp_pt2_batched: keep a system's integral layouts
                                      from the previous batched call when its h and
@@ -203,7 +205,8 @@ int qp_generator_order(qp_ctx *ctx, const uint64_t *dets, const double *coefs, i
  *   stats    optional; n_alpha, S, ... summed over the listed generators,
  *            n_cells counts their candidate cells
  * A listed generator's eps_I is the same, bit for bit, as qp_pt2's eps_gen
- * entry for it.  Errors as qp_pt2; QP_E_ARG for an index outside [0, n_det).
+ * entry for it.  Errors as qp_pt2; QP_E_ARG for an index outside [0, n_det)
+ * (not checked under QP_FLAG_NOCHECK).
  */
 int qp_pt2_generators(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
                       int n_states, const double *E0, const int32_t *gens, int64_t n_gen,

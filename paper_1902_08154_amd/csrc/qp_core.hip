@@ -1390,9 +1390,13 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             if (x.n_gen > 0) {
                 hipLaunchKernelGGL(map_gen_ranks, dim3(grid_for(x.n_gen)), dim3(256), 0, st, x.gens, x.n_gen,
                                    r.P.rank, n_det, r.gen_rank, r.P.sc);
-                HIPCHK(c, hipMemcpyAsync(c->host_sc, r.P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-                HIPCHK(c, hipStreamSynchronize(st));
-                if (c->host_sc->bad_gen) return fail(c, QP_E_ARG, "a listed generator is outside [0, n_det)");
+                // the list is checked unless the caller vouches for it (the
+                // semi-stochastic driver builds it from the generator order)
+                if (!(flags & QP_FLAG_NOCHECK)) {
+                    HIPCHK(c, hipMemcpyAsync(c->host_sc, r.P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+                    HIPCHK(c, hipStreamSynchronize(st));
+                    if (c->host_sc->bad_gen) return fail(c, QP_E_ARG, "a listed generator is outside [0, n_det)");
+                }
             }
         }
         const int64_t n_g = r.n_g;

@@ -135,3 +135,8 @@ def test_error_codes(ctx):
     # empty wave function: E_PT2 = 0, nothing selected
     r = ctx.pt2(to_device_dets(s.dets[:0], dev), coefs[:, :0].contiguous(), E0, n_select=5)
     assert r["e_pt2"].item() == 0.0 and r["sel_dets"].shape[0] == 0
+    # a generator list with an index outside [0, n_det) is refused
+    with pytest.raises(QPError) as e:
+        ctx.pt2_generators(to_device_dets(s.dets, dev), coefs, E0,
+                           torch.tensor([0, s.n_det], dtype=torch.int32))
+    assert e.value.code == _lib.QP_E_ARG
