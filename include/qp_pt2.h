@@ -305,9 +305,11 @@ int qp_sigma(qp_ctx *ctx, const uint64_t *dets, int64_t n_det, int n_vec, const 
 /*
  * qp_davidson -- the lowest n_states eigenpairs of H in the space of the
  * given determinants (sec. "Davidson diagonalization"): Davidson iterations
- * with the diagonal preconditioner, sigma vectors on the GPU (qp_sigma), the
- * subspace problem on the host.  Converged when every residual
- * ||H x - theta x|| < tol.
+ * with the diagonal preconditioner.  The basis, its sigma vectors (as
+ * qp_sigma), the Ritz vectors, residuals and Gram-Schmidt steps stay on the
+ * device; only the m x m Rayleigh matrix (m <= max(8 n_states, 24)) and the
+ * norms reach the host, which solves the subspace problem.  Converged when
+ * every residual ||H x - theta x|| < tol.
  *   guess   device double [n_states][n_det] start vectors, or NULL (unit
  *           vectors on the lowest diagonal elements)
  *   E_out   HOST double [n_states] eigenvalues, ascending
@@ -315,9 +317,10 @@ int qp_sigma(qp_ctx *ctx, const uint64_t *dets, int64_t n_det, int n_vec, const 
  *           component positive
  *   s2_out  HOST double [n_states] <S^2> of each vector, or NULL
  *   n_iter  HOST int [1] iterations used, or NULL
- * The call is synchronous.  Errors: as qp_sigma, QP_E_STATES, and
- * QP_E_NOCONV when max_iter iterations leave a residual above tol (the
- * outputs then hold the last iterate).
+ * The call is synchronous.  Errors: as qp_sigma, QP_E_STATES, QP_E_ARG when
+ * the guess spans fewer than n_states directions, and QP_E_NOCONV when
+ * max_iter iterations leave a residual above tol (the outputs then hold the
+ * last iterate).
  */
 int qp_davidson(qp_ctx *ctx, const uint64_t *dets, int64_t n_det, int n_states, const double *guess,
                 double tol, int max_iter, int flags, double *E_out, double *C_out, double *s2_out,

@@ -813,6 +813,86 @@ __global__ void energy_total(const double *row, const double *c2, int64_t n_det,
         for (int k = 0; k < ns; ++k) E0[k] = sn[0][k] / sd[0][k];
 }
 
+// ------------------------------------------------ Davidson vector algebra
+// Vectors are rows of length N in device memory; a block of them is
+// contiguous ([count][N]).  The subspace algebra of the Davidson method
+// (Rayleigh matrix, Ritz vectors, residuals, Gram-Schmidt) is made of these
+// few operations, so that only m x m matrices and norms cross to the host.
+
+// part[c][a * nb + b] = sum over chunk c of A_a . B_b
+__global__ void dav_dots_part(const double *A, int na, const double *B, int nb, int64_t N, int64_t chunk,
+                              double *part)
+{
+    __shared__ double red[256];
+    const int pair = blockIdx.x;
+    const int a = pair / nb, b = pair - a * nb;
+    const int64_t i0 = (int64_t)blockIdx.y * chunk;
+    const int64_t i1 = i0 + chunk < N ? i0 + chunk : N;
+    const double *x = A + (int64_t)a * N, *y = B + (int64_t)b * N;
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) s = fma(x[i], y[i], s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * na * nb + pair] = red[0];
+}
+
+// out[p] = sum over chunks, in chunk order (the result does not depend on timing)
+__global__ void dav_dots_sum(const double *part, int npair, int nchunk, double *out)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npair; p += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * npair + p];
+        out[p] = s;
+    }
+}
+
+// Y_k = (acc ? Y_k : 0) + alpha sum_j coef[j][k] A_j, k < kk
+__global__ void dav_gemv(const double *A, int m, int64_t N, const double *coef, int kk, double alpha, int acc,
+                         double *Y)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        for (int k = 0; k < kk; ++k) {
+            double v = 0.0;
+            for (int j = 0; j < m; ++j) v = fma(coef[j * kk + k], A[(int64_t)j * N + i], v);
+            Y[(int64_t)k * N + i] = acc ? fma(alpha, v, Y[(int64_t)k * N + i]) : alpha * v;
+        }
+}
+
+// residuals R_k = (H X)_k - theta_k X_k
+__global__ void dav_resid(const double *HX, const double *X, const double *theta, int kk, int64_t N, double *R)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        for (int k = 0; k < kk; ++k)
+            R[(int64_t)k * N + i] = HX[(int64_t)k * N + i] - theta[k] * X[(int64_t)k * N + i];
+}
+
+// diagonal preconditioner: T = R / (theta - H_ii), the denominator kept away from 0
+__global__ void dav_precond(const double *R, const double *diag, double theta, int64_t N, double *T)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        double d = theta - diag[i];
+        if (fabs(d) < 1e-8) d = d < 0 ? -1e-8 : 1e-8;
+        T[i] = R[i] / d;
+    }
+}
+
+__global__ void dav_scale(double *x, int64_t N, double s)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] *= s;
+}
+
+// the diagonal of H by determinant index, from the values by generator rank
+__global__ void dav_diag(const double *HII, const int32_t *perm, int64_t N, double *diag)
+{
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x)
+        diag[perm[r]] = HII[r];
+}
+
 // ===========================================================================
 // host side
 // ===========================================================================
@@ -830,7 +910,7 @@ enum BufId {
     // integral layouts of a system of a batched call
     B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
     // Davidson
-    B_ONES, B_DU, B_DW,
+    B_ONES, B_DU, B_DW, B_DX, B_DR, B_DHX, B_DDIAG, B_DCOEF, B_DPART, B_DDOT,
     B_COUNT
 };
 
@@ -1711,12 +1791,6 @@ void jacobi_eigen(std::vector<double> &a, int m, std::vector<double> &w, std::ve
     v.swap(v2);
 }
 
-double dotv(const double *x, const double *y, int64_t n)
-{
-    double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += x[i] * y[i];
-    return s;
-}
 
 }  // namespace
 
@@ -2129,132 +2203,161 @@ int qp_davidson(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_states, co
     Prepared P;
     int rc = prepare(c, 0, I, dets, ones, N, 1, flags, st, P);
     if (rc != QP_OK) return rc;
-    // the diagonal, by determinant, for the preconditioner
-    std::vector<double> hrank(N), diag(N);
-    std::vector<int32_t> perm(N);
-    HIPCHK(c, hipMemcpyAsync(hrank.data(), P.HII, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(perm.data(), P.perm, sizeof(int32_t) * N, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    for (int64_t r = 0; r < N; ++r) diag[perm[r]] = hrank[r];
-    const int max_sub = std::min<int64_t>(N, std::max(8 * ns, 24));
+    // Device-resident basis V [max_sub][N] with H V beside it, Ritz vectors X,
+    // H X and residuals R [ns][N] (R also holds the new directions); the host
+    // keeps the m x m Rayleigh matrix and solves the subspace problem.
+    const int max_sub = (int)std::min<int64_t>(N, std::max(8 * ns, 24));
+    const int64_t chunk = std::max<int64_t>(4096, (N + 63) / 64);
+    const int nchunk = (int)((N + chunk - 1) / chunk);
     double *dU = (double *)scratch(c, 0, B_DU, sizeof(double) * N * max_sub);
     double *dW = (double *)scratch(c, 0, B_DW, sizeof(double) * N * max_sub);
-    if (!dU || !dW) return fail(c, QP_E_OOM, "device allocation failed (Davidson)");
-    std::vector<std::vector<double>> V, HV;
-    auto add_vectors = [&](std::vector<std::vector<double>> &nv) -> int {
-        // orthonormalise against the basis and each other (twice), drop the rest
-        std::vector<std::vector<double>> keep;
-        for (auto &x : nv) {
-            for (int pass = 0; pass < 2; ++pass) {
-                for (auto &b : V) { const double d = dotv(b.data(), x.data(), N); for (int64_t i = 0; i < N; ++i) x[i] -= d * b[i]; }
-                for (auto &b : keep) { const double d = dotv(b.data(), x.data(), N); for (int64_t i = 0; i < N; ++i) x[i] -= d * b[i]; }
-            }
-            const double nrm = std::sqrt(dotv(x.data(), x.data(), N));
+    double *dX = (double *)scratch(c, 0, B_DX, sizeof(double) * N * ns);
+    double *dR = (double *)scratch(c, 0, B_DR, sizeof(double) * N * ns);
+    double *dHX = (double *)scratch(c, 0, B_DHX, sizeof(double) * N * ns);
+    double *ddiag = (double *)scratch(c, 0, B_DDIAG, sizeof(double) * N);
+    double *dcoef = (double *)scratch(c, 0, B_DCOEF, sizeof(double) * (max_sub * max_sub + QPD_MAX_STATES));
+    double *dpart = (double *)scratch(c, 0, B_DPART, sizeof(double) * nchunk * max_sub * max_sub);
+    double *ddot = (double *)scratch(c, 0, B_DDOT, sizeof(double) * max_sub * max_sub);
+    if (!dU || !dW || !dX || !dR || !dHX || !ddiag || !dcoef || !dpart || !ddot)
+        return fail(c, QP_E_OOM, "device allocation failed (Davidson)");
+    double *dtheta = dcoef + max_sub * max_sub;
+    const int gN = grid_for(N);
+    hipLaunchKernelGGL(dav_diag, dim3(gN), dim3(256), 0, st, P.HII, P.perm, N, ddiag);
+    // out[a * nb + b] = A_a . B_b (one host synchronisation)
+    auto dots = [&](const double *A, int na, const double *B, int nb, std::vector<double> &out) -> bool {
+        const int np = na * nb;
+        out.assign(np, 0.0);
+        if (np == 0) return true;
+        hipLaunchKernelGGL(dav_dots_part, dim3(np, nchunk), dim3(256), 0, st, A, na, B, nb, N, chunk, dpart);
+        hipLaunchKernelGGL(dav_dots_sum, dim3(grid_for(np)), dim3(256), 0, st, dpart, np, nchunk, ddot);
+        return hipMemcpyAsync(out.data(), ddot, sizeof(double) * np, hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipStreamSynchronize(st) == hipSuccess;
+    };
+    // Y_k = (acc ? Y_k : 0) + alpha sum_j coef[j][k] A_j
+    auto gemv = [&](const double *A, int m, const std::vector<double> &coef, int kk, double alpha, bool acc,
+                    double *Y) -> bool {
+        if (hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * m * kk, hipMemcpyHostToDevice, st) != hipSuccess)
+            return false;
+        hipLaunchKernelGGL(dav_gemv, dim3(gN), dim3(256), 0, st, A, m, N, dcoef, kk, alpha, acc ? 1 : 0, Y);
+        return true;
+    };
+    int m = 0;        // basis size
+    int g_done = 0;   // basis vectors whose Rayleigh rows are known
+    std::vector<double> G((size_t)max_sub * max_sub, 0.0);
+    bool ok = true;
+    // orthonormalise the rows against the basis and each other (classical
+    // Gram-Schmidt, twice), drop the negligible ones, append the rest and
+    // their sigma-vectors
+    auto add_vectors = [&](const std::vector<const double *> &rows) -> int {
+        const int m0 = m;
+        std::vector<double> d, nn;
+        for (const double *src : rows) {
+            if (m >= max_sub) break;
+            double *x = dU + (int64_t)m * N;
+            if (hipMemcpyAsync(x, src, sizeof(double) * N, hipMemcpyDeviceToDevice, st) != hipSuccess) return -1;
+            for (int pass = 0; pass < 2 && m > 0; ++pass)
+                if (!dots(dU, m, x, 1, d) || !gemv(dU, m, d, 1, -1.0, true, x)) return -1;
+            if (!dots(x, 1, x, 1, nn)) return -1;
+            const double nrm = std::sqrt(std::max(nn[0], 0.0));
             if (nrm < 1e-10) continue;
-            for (int64_t i = 0; i < N; ++i) x[i] /= nrm;
-            keep.push_back(x);
-            if ((int)(V.size() + keep.size()) >= max_sub) break;
+            hipLaunchKernelGGL(dav_scale, dim3(gN), dim3(256), 0, st, x, N, 1.0 / nrm);
+            ++m;
         }
-        const int k = (int)keep.size();
-        if (k == 0) return 0;
-        for (int j = 0; j < k; ++j)
-            if (hipMemcpyAsync(dU + (int64_t)j * N, keep[j].data(), sizeof(double) * N, hipMemcpyHostToDevice, st) != hipSuccess)
-                return -1;
-        launch_sigma(I, P, dets, N, k, false, dU, dW, st);
-        std::vector<double> w((size_t)k * N);
-        if (hipMemcpyAsync(w.data(), dW, sizeof(double) * N * k, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return -1;
-        for (int j = 0; j < k; ++j) {
-            V.push_back(keep[j]);
-            HV.emplace_back(w.begin() + (size_t)j * N, w.begin() + (size_t)(j + 1) * N);
-        }
-        return k;
+        if (m > m0) launch_sigma(I, P, dets, N, m - m0, false, dU + (int64_t)m0 * N, dW + (int64_t)m0 * N, st);
+        return m - m0;
     };
     // start: the guess, else unit vectors on the lowest diagonal elements
-    std::vector<std::vector<double>> start(ns, std::vector<double>(N, 0.0));
+    std::vector<const double *> rows;
     if (guess) {
-        std::vector<double> g((size_t)ns * N);
-        HIPCHK(c, hipMemcpyAsync(g.data(), guess, sizeof(double) * ns * N, hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        for (int k = 0; k < ns; ++k) std::copy(g.begin() + (size_t)k * N, g.begin() + (size_t)(k + 1) * N, start[k].begin());
+        HIPCHK(c, hipMemcpyAsync(dR, guess, sizeof(double) * ns * N, hipMemcpyDeviceToDevice, st));
     } else {
+        std::vector<double> diag(N);
+        HIPCHK(c, hipMemcpyAsync(diag.data(), ddiag, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
         std::vector<int64_t> idx(N);
         for (int64_t i = 0; i < N; ++i) idx[i] = i;
         std::partial_sort(idx.begin(), idx.begin() + ns, idx.end(),
                           [&](int64_t x, int64_t y) { return diag[x] < diag[y] || (diag[x] == diag[y] && x < y); });
-        for (int k = 0; k < ns; ++k) start[k][idx[k]] = 1.0;
+        std::vector<double> e((size_t)ns * N, 0.0);
+        for (int k = 0; k < ns; ++k) e[(size_t)k * N + idx[k]] = 1.0;
+        HIPCHK(c, hipMemcpyAsync(dR, e.data(), sizeof(double) * ns * N, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
     }
-    if (add_vectors(start) < 0) return fail(c, QP_E_HIP, "Davidson transfer failed");
-    std::vector<double> theta;
-    std::vector<std::vector<double>> X(ns, std::vector<double>(N)), R(ns, std::vector<double>(N));
+    for (int k = 0; k < ns; ++k) rows.push_back(dR + (int64_t)k * N);
+    if (add_vectors(rows) < 0) return fail(c, QP_E_HIP, "Davidson vector operation failed");
+    if (m < ns) return fail(c, QP_E_ARG, "the guess has fewer than n_states independent vectors");
+    std::vector<double> theta, y, D1, D2, rn;
     int it = 0;
     bool converged = false;
     for (; it < max_iter; ++it) {
-        const int m = (int)V.size();
-        std::vector<double> G((size_t)m * m), y;
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j <= i; ++j) {
-                const double g = 0.5 * (dotv(V[i].data(), HV[j].data(), N) + dotv(V[j].data(), HV[i].data(), N));
-                G[(size_t)i * m + j] = G[(size_t)j * m + i] = g;
-            }
-        jacobi_eigen(G, m, theta, y);
-        double rmax = 0.0;
-        for (int k = 0; k < ns; ++k) {
-            std::fill(X[k].begin(), X[k].end(), 0.0);
-            std::fill(R[k].begin(), R[k].end(), 0.0);
-            for (int j = 0; j < m; ++j) {
-                const double yk = y[(size_t)j * m + k];
-                for (int64_t i = 0; i < N; ++i) { X[k][i] += yk * V[j][i]; R[k][i] += yk * HV[j][i]; }
-            }
-            for (int64_t i = 0; i < N; ++i) R[k][i] -= theta[k] * X[k][i];
-            rmax = std::max(rmax, std::sqrt(dotv(R[k].data(), R[k].data(), N)));
-        }
-        if (rmax < tol) { converged = true; break; }
-        // corrections from the diagonal preconditioner
-        std::vector<std::vector<double>> corr;
-        for (int k = 0; k < ns; ++k) {
-            if (std::sqrt(dotv(R[k].data(), R[k].data(), N)) < tol) continue;
-            std::vector<double> t(N);
-            for (int64_t i = 0; i < N; ++i) {
-                double d = theta[k] - diag[i];
-                if (std::fabs(d) < 1e-8) d = d < 0 ? -1e-8 : 1e-8;
-                t[i] = R[k][i] / d;
-            }
-            corr.push_back(std::move(t));
-        }
-        if ((int)V.size() + (int)corr.size() > max_sub) {
-            // restart from the current Ritz vectors
-            std::vector<std::vector<double>> HX(ns, std::vector<double>(N, 0.0));
-            for (int k = 0; k < ns; ++k)
-                for (int j = 0; j < m; ++j) {
-                    const double yk = y[(size_t)j * m + k];
-                    for (int64_t i = 0; i < N; ++i) HX[k][i] += yk * HV[j][i];
+        // Rayleigh rows of the vectors added since the last iteration
+        if (g_done < m) {
+            const int k = m - g_done;
+            ok = dots(dU, m, dW + (int64_t)g_done * N, k, D1) && dots(dU + (int64_t)g_done * N, k, dW, m, D2);
+            if (!ok) break;
+            for (int a = 0; a < m; ++a)
+                for (int b = 0; b < k; ++b) {
+                    const double g = 0.5 * (D1[(size_t)a * k + b] + D2[(size_t)b * m + a]);
+                    G[(size_t)a * max_sub + g_done + b] = G[(size_t)(g_done + b) * max_sub + a] = g;
                 }
-            V.assign(X.begin(), X.end());
-            HV.swap(HX);
+            g_done = m;
         }
-        const int added = add_vectors(corr);
-        if (added < 0) return fail(c, QP_E_HIP, "Davidson transfer failed");
+        std::vector<double> Gm((size_t)m * m);
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) Gm[(size_t)a * m + b] = G[(size_t)a * max_sub + b];
+        jacobi_eigen(Gm, m, theta, y);
+        // Ritz vectors X = V y, H X = (H V) y, residuals R = H X - theta X
+        std::vector<double> cy((size_t)m * ns);
+        for (int j = 0; j < m; ++j)
+            for (int k = 0; k < ns; ++k) cy[(size_t)j * ns + k] = y[(size_t)j * m + k];
+        ok = gemv(dU, m, cy, ns, 1.0, false, dX) && gemv(dW, m, cy, ns, 1.0, false, dHX) &&
+             hipMemcpyAsync(dtheta, theta.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st) == hipSuccess;
+        if (!ok) break;
+        hipLaunchKernelGGL(dav_resid, dim3(gN), dim3(256), 0, st, dHX, dX, dtheta, ns, N, dR);
+        if (!(ok = dots(dR, ns, dR, ns, rn))) break;
+        double rmax = 0.0;
+        for (int k = 0; k < ns; ++k) rmax = std::max(rmax, std::sqrt(std::max(rn[(size_t)k * ns + k], 0.0)));
+        if (rmax < tol) { converged = true; break; }
+        // corrections from the diagonal preconditioner, in place of the residuals
+        rows.clear();
+        for (int k = 0; k < ns; ++k) {
+            if (std::sqrt(std::max(rn[(size_t)k * ns + k], 0.0)) < tol) continue;
+            hipLaunchKernelGGL(dav_precond, dim3(gN), dim3(256), 0, st, dR + (int64_t)k * N, ddiag, theta[k], N,
+                               dR + (int64_t)k * N);
+            rows.push_back(dR + (int64_t)k * N);
+        }
+        if (m + (int)rows.size() > max_sub) {
+            // restart from the current Ritz vectors
+            ok = hipMemcpyAsync(dU, dX, sizeof(double) * ns * N, hipMemcpyDeviceToDevice, st) == hipSuccess &&
+                 hipMemcpyAsync(dW, dHX, sizeof(double) * ns * N, hipMemcpyDeviceToDevice, st) == hipSuccess;
+            if (!ok) break;
+            m = ns;
+            g_done = 0;
+        }
+        const int added = add_vectors(rows);
+        if (added < 0) { ok = false; break; }
         if (added == 0) break;
     }
+    if (!ok) return fail(c, QP_E_HIP, "Davidson vector operation failed");
+    HIPCHK(c, hipGetLastError());
     if (n_iter) *n_iter = it;
     for (int k = 0; k < ns; ++k) E_out[k] = theta[k];
     std::vector<double> cx((size_t)ns * N);
+    HIPCHK(c, hipMemcpyAsync(cx.data(), dX, sizeof(double) * ns * N, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
     for (int k = 0; k < ns; ++k) {
         // a fixed sign: the largest component positive
+        double *xk = cx.data() + (size_t)k * N;
         int64_t im = 0;
-        for (int64_t i = 1; i < N; ++i) if (std::fabs(X[k][i]) > std::fabs(X[k][im])) im = i;
-        const double sg = X[k][im] < 0 ? -1.0 : 1.0;
-        for (int64_t i = 0; i < N; ++i) cx[(size_t)k * N + i] = sg * X[k][i];
+        for (int64_t i = 1; i < N; ++i) if (std::fabs(xk[i]) > std::fabs(xk[im])) im = i;
+        if (xk[im] < 0) for (int64_t i = 0; i < N; ++i) xk[i] = -xk[i];
     }
     HIPCHK(c, hipMemcpyAsync(C_out, cx.data(), sizeof(double) * ns * N, hipMemcpyHostToDevice, st));
     if (s2_out) {
         launch_sigma(I, P, dets, N, ns, true, C_out, dW, st);
-        std::vector<double> sw((size_t)ns * N);
-        HIPCHK(c, hipMemcpyAsync(sw.data(), dW, sizeof(double) * ns * N, hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        for (int k = 0; k < ns; ++k) s2_out[k] = dotv(cx.data() + (size_t)k * N, sw.data() + (size_t)k * N, N);
+        std::vector<double> sw;
+        if (!dots(C_out, ns, dW, ns, sw)) return fail(c, QP_E_HIP, "Davidson vector operation failed");
+        for (int k = 0; k < ns; ++k) s2_out[k] = sw[(size_t)k * ns + k];
     }
     HIPCHK(c, hipStreamSynchronize(st));
     if (!converged) return fail(c, QP_E_NOCONV, "Davidson did not converge");
