@@ -2217,19 +2217,25 @@ int qp_davidson(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_states, co
     double *ddiag = (double *)scratch(c, 0, B_DDIAG, sizeof(double) * N);
     double *dcoef = (double *)scratch(c, 0, B_DCOEF, sizeof(double) * (max_sub * max_sub + QPD_MAX_STATES));
     double *dpart = (double *)scratch(c, 0, B_DPART, sizeof(double) * nchunk * max_sub * max_sub);
-    double *ddot = (double *)scratch(c, 0, B_DDOT, sizeof(double) * max_sub * max_sub);
+    double *ddot = (double *)scratch(c, 0, B_DDOT, sizeof(double) * 2 * max_sub * max_sub);
     if (!dU || !dW || !dX || !dR || !dHX || !ddiag || !dcoef || !dpart || !ddot)
         return fail(c, QP_E_OOM, "device allocation failed (Davidson)");
     double *dtheta = dcoef + max_sub * max_sub;
     const int gN = grid_for(N);
     hipLaunchKernelGGL(dav_diag, dim3(gN), dim3(256), 0, st, P.HII, P.perm, N, ddiag);
-    // out[a * nb + b] = A_a . B_b (one host synchronisation)
+    // out[a * nb + b] = A_a . B_b into device memory, in stream order
+    auto dots_dev = [&](const double *A, int na, const double *B, int nb, double *out) {
+        const int np = na * nb;
+        if (np == 0) return;
+        hipLaunchKernelGGL(dav_dots_part, dim3(np, nchunk), dim3(256), 0, st, A, na, B, nb, N, chunk, dpart);
+        hipLaunchKernelGGL(dav_dots_sum, dim3(grid_for(np)), dim3(256), 0, st, dpart, np, nchunk, out);
+    };
+    // the same, brought to the host (one synchronisation)
     auto dots = [&](const double *A, int na, const double *B, int nb, std::vector<double> &out) -> bool {
         const int np = na * nb;
         out.assign(np, 0.0);
         if (np == 0) return true;
-        hipLaunchKernelGGL(dav_dots_part, dim3(np, nchunk), dim3(256), 0, st, A, na, B, nb, N, chunk, dpart);
-        hipLaunchKernelGGL(dav_dots_sum, dim3(grid_for(np)), dim3(256), 0, st, dpart, np, nchunk, ddot);
+        dots_dev(A, na, B, nb, ddot);
         return hipMemcpyAsync(out.data(), ddot, sizeof(double) * np, hipMemcpyDeviceToHost, st) == hipSuccess &&
                hipStreamSynchronize(st) == hipSuccess;
     };
@@ -2250,13 +2256,16 @@ int qp_davidson(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_states, co
     // their sigma-vectors
     auto add_vectors = [&](const std::vector<const double *> &rows) -> int {
         const int m0 = m;
-        std::vector<double> d, nn;
+        std::vector<double> nn;
         for (const double *src : rows) {
             if (m >= max_sub) break;
             double *x = dU + (int64_t)m * N;
             if (hipMemcpyAsync(x, src, sizeof(double) * N, hipMemcpyDeviceToDevice, st) != hipSuccess) return -1;
-            for (int pass = 0; pass < 2 && m > 0; ++pass)
-                if (!dots(dU, m, x, 1, d) || !gemv(dU, m, d, 1, -1.0, true, x)) return -1;
+            // x -= V (V^T x), the coefficients staying on the device
+            for (int pass = 0; pass < 2 && m > 0; ++pass) {
+                dots_dev(dU, m, x, 1, ddot);
+                hipLaunchKernelGGL(dav_gemv, dim3(gN), dim3(256), 0, st, dU, m, N, ddot, 1, -1.0, 1, x);
+            }
             if (!dots(x, 1, x, 1, nn)) return -1;
             const double nrm = std::sqrt(std::max(nn[0], 0.0));
             if (nrm < 1e-10) continue;
@@ -2293,8 +2302,13 @@ int qp_davidson(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_states, co
         // Rayleigh rows of the vectors added since the last iteration
         if (g_done < m) {
             const int k = m - g_done;
-            ok = dots(dU, m, dW + (int64_t)g_done * N, k, D1) && dots(dU + (int64_t)g_done * N, k, dW, m, D2);
+            dots_dev(dU, m, dW + (int64_t)g_done * N, k, ddot);
+            dots_dev(dU + (int64_t)g_done * N, k, dW, m, ddot + (int64_t)m * k);
+            D1.resize((size_t)2 * m * k);
+            ok = hipMemcpyAsync(D1.data(), ddot, sizeof(double) * 2 * m * k, hipMemcpyDeviceToHost, st) == hipSuccess &&
+                 hipStreamSynchronize(st) == hipSuccess;
             if (!ok) break;
+            D2.assign(D1.begin() + (size_t)m * k, D1.end());
             for (int a = 0; a < m; ++a)
                 for (int b = 0; b < k; ++b) {
                     const double g = 0.5 * (D1[(size_t)a * k + b] + D2[(size_t)b * m + a]);
