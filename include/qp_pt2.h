@@ -303,9 +303,13 @@ int qp_sigma(qp_ctx *ctx, const uint64_t *dets, int64_t n_det, int n_vec, const 
              int flags, double *W, void *stream);
 
 /*
- * qp_davidson -- the lowest n_states eigenpairs of H in the space of the
- * given determinants (sec. "Davidson diagonalization"): Davidson iterations
- * with the diagonal preconditioner.  The basis, its sigma vectors (as
+ * qp_davidson -- n_states eigenpairs of H in the space of the given
+ * determinants (sec. "Davidson diagonalization"): Davidson iterations with
+ * the diagonal preconditioner, converged on the lowest Ritz pairs of the
+ * subspace.  From the default start these are the lowest eigenpairs in the
+ * spaces the tests check against a dense eigensolver; from a guess far from
+ * the ground state the iteration can settle on eigenpairs near the guess's
+ * energy instead, as Davidson does.  The basis, its sigma vectors (as
  * qp_sigma), the Ritz vectors, residuals and Gram-Schmidt steps stay on the
  * device; only the m x m Rayleigh matrix (m <= max(8 n_states, 24)) and the
  * norms reach the host, which solves the subspace problem.  Converged when
