@@ -1236,6 +1236,27 @@ int persistent_grid(qp_ctx *c, bool dense, int nint, int ns, bool bwd, size_t ld
     return c->num_cu * per_cu;
 }
 
+// correction rows (and columns) the dense kernel buffers per batch: 6 up to
+// n_orb = 128, 3 above.  Up to 128 orbitals the count drops, to 4 at least,
+// while the LDS it takes would leave room for fewer workgroups per CU than
+// the kernel's registers allow: batches that overflow the buffers go to the
+// general kernel, which costs less than a quarter of the waves (n_orb 128,
+// 14+14 electrons, 10^5 determinants: dense kernel 1616 -> 1362 ms, general
+// kernel 6 -> 36 ms).  The count depends on the system alone.
+int buffer_rows(qp_ctx *c, int n, int nvm, int nint, int ns, bool bwd, bool fp)
+{
+    if (n > 128) return 3;
+    const int regs = persistent_grid(c, true, nint, ns, bwd, 0, fp) / c->num_cu;
+    int cap = 6;
+    while (cap > 4) {
+        const size_t lds = fast_lds_bytes(n, nvm, ns, bwd, cap, cap);
+        const size_t r512 = (lds + 511) / 512 * 512, r1280 = (lds + 1279) / 1280 * 1280;
+        if ((int)(c->lds_per_cu / (r512 > r1280 ? r512 : r1280)) >= regs) break;
+        --cap;
+    }
+    return cap;
+}
+
 template <int NINT, int NS>
 void launch_ns(bool dense, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd, bool fp, size_t lds,
                int grid, hipStream_t st)
@@ -1515,9 +1536,9 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             !r.def_cnt_g || !r.def_off || !r.def_bsum)
             return fail(c, QP_E_OOM, "device allocation failed (sweep buffers)");
         HIPCHK(c, hipMemsetAsync(r.def_bits, 0, sizeof(uint32_t) * n_det * r.nbw, st));
-        const int rscap = n <= 128 ? 6 : 3, cscap = n <= 128 ? 6 : 3;
+        const int nvm = n - std::min(r.P.nup, r.P.ndn);
+        const int rscap = buffer_rows(c, n, nvm, r.nint, ns, bwd, fp), cscap = rscap;
         if (x.n_select > 0) {
-            const int nvm = n - std::min(r.P.nup, r.P.ndn);
             const int grid = std::max(persistent_grid(c, true, r.nint, ns, bwd,
                                                       fast_lds_bytes(n, nvm, ns, bwd, rscap, cscap), fp),
                                       persistent_grid(c, false, r.nint, ns, bwd, sweep_lds_bytes(n, ns, bwd), fp));
