@@ -226,7 +226,10 @@ int qp_pt2_generators(qp_ctx *ctx, const uint64_t *dets, const double *coefs, in
  * W_S eps_K / w_K (W_S the weight outside D), its error the standard error of
  * that mean.  Stops when every state has error <= rel_err |estimate| (the
  * paper's default is 0.002), when D holds every generator (exact, error 0),
- * or when the random numbers run out.
+ * or when the random numbers run out.  The generator order, per-generator
+ * tables and coarse lists are prepared once per call; each round is one sweep
+ * of its list followed by a host decision, and lasts at least one work item's
+ * time, so rounds of a few hundred generators keep the device busy.
  *   uniforms   HOST double [n_uniforms] in [0, 1): the random numbers, one per
  *              draw, consumed in order (the caller owns the generator)
  *   e_est, e_err  HOST double [n_states]; n_computed, n_rounds HOST int64 [1]
