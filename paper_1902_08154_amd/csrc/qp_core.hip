@@ -159,7 +159,7 @@ __global__ void max_c2(const double *coefs, int64_t n_det, int ns, double *out /
         red[threadIdx.x] = m;
         __syncthreads();
         for (int s = 128; s > 0; s >>= 1) {
-            if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+            if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
             __syncthreads();
         }
         if (threadIdx.x == 0) out[k] = red[0];
@@ -333,7 +333,7 @@ __global__ void prep_generators(const uint64_t *dets, const int32_t *perm, int64
     red[threadIdx.x] = hpart;
     __syncthreads();
     for (int s = 64; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) HII[g] = red[0];
