@@ -60,8 +60,8 @@ __global__ void build_Y(const double *eri, int n, double *Y)
     }
 }
 
-// Cj[j][p][q] = (pq|jj), Xj[j][p][q] = (pj|jq), Jm[p][q] = (pp|qq), Km[p][q] = (pq|qp)
-__global__ void build_small(const double *eri, const double *h, int n, double *Cj, double *Xj,
+// Cj[j][p][q] = (pq|jj), CXj[j][p][q] = (pq|jj) - (pj|jq), Jm[p][q] = (pp|qq), Km[p][q] = (pq|qp)
+__global__ void build_small(const double *eri, const double *h, int n, double *Cj, double *CXj,
                             double *Jm, double *Km, double *JK, double *hc)
 {
     const int64_t n3 = (int64_t)n * n * n;
@@ -70,7 +70,7 @@ __global__ void build_small(const double *eri, const double *h, int n, double *C
         int64_t j = i / ((int64_t)n * n), pq = i - j * n * n;
         int64_t p = pq / n, q = pq - p * n;
         Cj[i] = packed_eri(eri, p, q, j, j);
-        Xj[i] = packed_eri(eri, p, j, j, q);
+        CXj[i] = Cj[i] - packed_eri(eri, p, j, j, q);
         if (j == 0) {
             Jm[pq] = packed_eri(eri, p, p, q, q);
             Km[pq] = packed_eri(eri, p, q, q, p);
@@ -924,7 +924,7 @@ struct qp_ctx {
     int device = 0;
     std::string err;
     int n = 0;
-    double *h = nullptr, *X = nullptr, *Y = nullptr, *Cj = nullptr, *Xj = nullptr, *Jm = nullptr, *Km = nullptr,
+    double *h = nullptr, *X = nullptr, *Y = nullptr, *Cj = nullptr, *CXj = nullptr, *Jm = nullptr, *Km = nullptr,
            *JK = nullptr;
     // device scratch, one set per system slot: slot s serves system s of a
     // batched call; single-system calls use slot 0
@@ -1038,7 +1038,7 @@ void launch_layouts(const double *h, const double *eri, int n_orb, const DevInts
     if (P2 > 0)
         hipLaunchKernelGGL(build_Y, dim3(grid_for(P2 * P2, 256, 1 << 16)), dim3(256), 0, st, eri, n_orb, (double *)I.Y);
     hipLaunchKernelGGL(build_small, dim3(grid_for(n3, 256, 1 << 16)), dim3(256), 0, st, eri, h, n_orb, (double *)I.Cj,
-                       (double *)I.Xj, (double *)I.Jm, (double *)I.Km, (double *)I.JK, (double *)I.h);
+                       (double *)I.CXj, (double *)I.Jm, (double *)I.Km, (double *)I.JK, (double *)I.h);
 }
 
 struct LayoutSizes {
@@ -1181,7 +1181,7 @@ int common_checks(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t 
 DevInts dev_ints(const qp_ctx *c)
 {
     DevInts I;
-    I.n = c->n; I.h = c->h; I.X = c->X; I.Y = c->Y; I.Cj = c->Cj; I.Xj = c->Xj; I.Jm = c->Jm; I.Km = c->Km;
+    I.n = c->n; I.h = c->h; I.X = c->X; I.Y = c->Y; I.Cj = c->Cj; I.CXj = c->CXj; I.Jm = c->Jm; I.Km = c->Km;
     I.JK = c->JK;
     return I;
 }
@@ -1856,7 +1856,7 @@ void qp_destroy(qp_ctx *c)
     for (auto &b : c->args) if (b.p) (void)hipFree(b.p);
     if (c->defn.p) (void)hipFree(c->defn.p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
-    double *arrs[] = {c->h, c->X, c->Y, c->Cj, c->Xj, c->Jm, c->Km, c->JK};
+    double *arrs[] = {c->h, c->X, c->Y, c->Cj, c->CXj, c->Jm, c->Km, c->JK};
     for (double *p : arrs) if (p) (void)hipFree(p);
     if (c->host_sc) (void)hipHostFree(c->host_sc);
     if (c->host_det0) (void)hipHostFree(c->host_det0);
@@ -1879,12 +1879,12 @@ int qp_set_integrals(qp_ctx *c, const double *h, const double *eri_packed, int n
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(c, hipStreamSynchronize(st));
-    double **arrs[] = {&c->h, &c->X, &c->Y, &c->Cj, &c->Xj, &c->Jm, &c->Km, &c->JK};
+    double **arrs[] = {&c->h, &c->X, &c->Y, &c->Cj, &c->CXj, &c->Jm, &c->Km, &c->JK};
     for (double **p : arrs) if (*p) { (void)hipFree(*p); *p = nullptr; }
     c->n = 0;
     const LayoutSizes z = layout_sizes(n_orb);
     if (hipMalloc(&c->X, z.nX * 8) != hipSuccess || hipMalloc(&c->Y, z.nY * 8) != hipSuccess ||
-        hipMalloc(&c->Cj, z.n3 * 8) != hipSuccess || hipMalloc(&c->Xj, z.n3 * 8) != hipSuccess ||
+        hipMalloc(&c->Cj, z.n3 * 8) != hipSuccess || hipMalloc(&c->CXj, z.n3 * 8) != hipSuccess ||
         hipMalloc(&c->Jm, z.n2 * 8) != hipSuccess || hipMalloc(&c->Km, z.n2 * 8) != hipSuccess ||
         hipMalloc(&c->JK, z.n2 * 8) != hipSuccess || hipMalloc(&c->h, z.n2 * 8) != hipSuccess) {
         (void)hipGetLastError();
@@ -2149,12 +2149,12 @@ int qp_pt2_batched(qp_ctx *c, int n_sys, const qp_system *sys, int with_backward
         I.X = (double *)scratch(c, s, B_LX, z.nX * 8);
         I.Y = (double *)scratch(c, s, B_LY, z.nY * 8);
         I.Cj = (double *)scratch(c, s, B_LCJ, z.n3 * 8);
-        I.Xj = (double *)scratch(c, s, B_LXJ, z.n3 * 8);
+        I.CXj = (double *)scratch(c, s, B_LXJ, z.n3 * 8);
         I.Jm = (double *)scratch(c, s, B_LJM, z.n2 * 8);
         I.Km = (double *)scratch(c, s, B_LKM, z.n2 * 8);
         I.JK = (double *)scratch(c, s, B_LJK, z.n2 * 8);
         I.h = (double *)scratch(c, s, B_LH, z.n2 * 8);
-        if (!I.X || !I.Y || !I.Cj || !I.Xj || !I.Jm || !I.Km || !I.JK || !I.h)
+        if (!I.X || !I.Y || !I.Cj || !I.CXj || !I.Jm || !I.Km || !I.JK || !I.h)
             return fail(c, QP_E_OOM, "device allocation failed (integral layouts)");
         LayoutKey &key = c->layout_keys[s];
         const bool same = key.h == y.h && key.eri == y.eri_packed && key.n == y.n_orb;

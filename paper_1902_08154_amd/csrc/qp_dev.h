@@ -11,7 +11,7 @@
 //   Y [tris(a,b)][tris(c,d)] = (ac|bd) - (ad|bc), a<b, c<d
 //       same-spin double with holes a<b, particles c<d: one coalesced
 //       antisymmetrised block per hole pair.            (n(n-1)/2)^2
-//   Cj[j][p][q] = (pq|jj),  Xj[j][p][q] = (pj|jq)     n^3 each
+//   Cj[j][p][q] = (pq|jj),  CXj[j][p][q] = (pq|jj) - (pj|jq)     n^3 each
 //       Coulomb/exchange slices for Fock elements F^J_pq of any determinant.
 //   Jm[p][q] = (pp|qq),  Km[p][q] = (pq|qp),  JK = Jm - Km   n^2 each
 //   tri(a,b) = b(b+1)/2 + a (a<=b),  tris(a,b) = b(b-1)/2 + a (a<b)
@@ -30,7 +30,7 @@ struct DevInts {
     const double *X;
     const double *Y;
     const double *Cj;
-    const double *Xj;
+    const double *CXj;
     const double *Jm;
     const double *Km;
     const double *JK;  // Jm - Km: same-spin pair interaction
@@ -146,14 +146,16 @@ __device__ double fock_offdiag(const Ints &I, const uint64_t *J, int s, int p, i
     const int64_t pq = (int64_t)p * n + q;
 #pragma unroll
     for (int ss = 0; ss < 2; ++ss) {
+        // an electron of the excited spin adds Coulomb minus exchange, one
+        // of the other spin Coulomb alone: one integral read per electron
+        const double *A = ss == s ? I.CXj : I.Cj;
 #pragma unroll
         for (int w = 0; w < NINT; ++w) {
             uint64_t x = J[ss * NINT + w];
             while (x) {
                 int j = 64 * w + ctz64(x);
                 x &= x - 1;
-                v += I.Cj[(int64_t)j * n * n + pq];
-                if (ss == s) v -= I.Xj[(int64_t)j * n * n + pq];
+                v += A[(int64_t)j * n * n + pq];
             }
         }
     }
