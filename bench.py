@@ -44,8 +44,8 @@ def log(*a):
 DENSE_SOURCES = ["qp_dev.h", "qp_fast_caps.h", "qp_fast_impl.h", "qp_fast_fwd.hip"]
 MEASURED_TRAFFIC = {
     "c2_n64_10a10b_1e4det_top1000": {
-        "sources_sha256": "09fdb684729ffc4b3d4f0f027dd56a3a61d3f6919b7d60b5e0b2b2e45ed4a9b2",
-        "bytes": 46080333952 + 44651392,
+        "sources_sha256": "8c61be08b0e98c6710e9f768eebd532ced6c590b38247ff447de2ce23b559d5d",
+        "bytes": 45282716416 + 45439232,
     },
 }
 
