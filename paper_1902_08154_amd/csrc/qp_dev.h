@@ -225,7 +225,10 @@ __device__ double sc_offdiag(const Ints &I, const uint64_t *bra, const uint64_t 
     const int lo = h2 < p2 ? h2 : p2, hi = h2 < p2 ? p2 : h2;
     const int sg = between_parity<NINT>(ket, s, h1, p1) ^ between_parity<NINT>(ket, s, h2, p2) ^
                    (int)(lo < h1 && h1 < hi) ^ (int)(lo < p1 && p1 < hi);
-    const double v = eri_x(I, h1, p1, h2, p2) - eri_x(I, h1, p2, h2, p1);
+    // (h1 p1|h2 p2) - (h1 p2|h2 p1) with h1 < h2 and p1 < p2: one read of the
+    // antisymmetrised layout (the same difference, formed when it was built)
+    const int64_t P2 = (int64_t)I.n * (I.n - 1) / 2;
+    const double v = I.Y[qtris(h1, h2) * P2 + qtris(p1, p2)];
     return sg ? -v : v;
 }
 
