@@ -152,10 +152,27 @@ __device__ double fock_offdiag(const Ints &I, const uint64_t *J, int s, int p, i
 #pragma unroll
         for (int w = 0; w < NINT; ++w) {
             uint64_t x = J[ss * NINT + w];
+            // four electrons per step, their reads issued together; a step
+            // past the last electron rereads the first one and adds nothing
             while (x) {
-                int j = 64 * w + ctz64(x);
+                const int j0 = ctz64(x);
                 x &= x - 1;
-                v += A[(int64_t)j * n * n + pq];
+                const bool m1 = x != 0;
+                const int j1 = m1 ? ctz64(x) : j0;
+                x &= x - 1;
+                const bool m2 = x != 0;
+                const int j2 = m2 ? ctz64(x) : j0;
+                x &= x - 1;
+                const bool m3 = x != 0;
+                const int j3 = m3 ? ctz64(x) : j0;
+                x &= x - 1;
+                const int64_t b = (int64_t)64 * w * n * n + pq;
+                const double a0 = A[b + (int64_t)j0 * n * n], a1 = A[b + (int64_t)j1 * n * n];
+                const double a2 = A[b + (int64_t)j2 * n * n], a3 = A[b + (int64_t)j3 * n * n];
+                v += a0;
+                if (m1) v += a1;
+                if (m2) v += a2;
+                if (m3) v += a3;
             }
         }
     }

@@ -8,7 +8,7 @@
 // [adjoint][fingerprint][n_int - 1][n_states - 1]
 constexpr int qpf_caps[2][2][4][4] = {
     {{{4, 3, 3, 2}, {3, 3, 3, 2}, {3, 3, 3, 2}, {2, 2, 2, 2}},
-     {{3, 3, 3, 2}, {3, 3, 3, 2}, {3, 3, 2, 2}, {3, 2, 2, 2}}},
+     {{3, 3, 3, 2}, {3, 3, 3, 2}, {3, 3, 2, 2}, {2, 2, 2, 2}}},
     {{{3, 2, 2, 2}, {3, 2, 2, 2}, {3, 2, 2, 2}, {2, 2, 2, 2}},
      {{3, 2, 2, 2}, {3, 2, 2, 1}, {3, 2, 2, 1}, {2, 2, 2, 1}}},
 };
