@@ -208,8 +208,8 @@ def main():
                          "against which the HBM traffic counters of the sweep are scaled")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (see the sharding note in the "
-              "design document)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (the design notes describe how "
+              "the sweep would shard over generators)", file=sys.stderr)
         sys.exit(2)
 
     import ctypes
