@@ -181,6 +181,8 @@ def next_rows_bench(ctx, dev, s, dets, coefs, E0, steps):
     sig = {}
     for name, U, s2 in (("H_1vec", coefs, False), ("H_4vec", U4, False), ("S2_1vec", coefs, True)):
         sig[name + "_ms"], _ = timed(lambda: ctx.sigma(dets, U, s2=s2))
+    # the same determinants again: the prepared space is reused (QP_SIGMA_REUSE)
+    sig["H_1vec_reuse_ms"], _ = timed(lambda: ctx.sigma(dets, coefs, reuse=True))
     out["sigma"] = sig
     t0 = time.perf_counter()
     r = ctx.davidson(dets, n_states=1, guess=coefs, tol=1e-8, max_iter=400)

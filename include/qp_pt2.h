@@ -76,6 +76,11 @@ extern "C" {
                                    generator indices: an index outside [0, n_det)
                                    is then swept as generator rank 0)            */
 #define QP_SIGMA_S2          8  /* qp_sigma: W = S^2 U instead of H U              */
+#define QP_SIGMA_REUSE      16  /* qp_sigma: the determinants are those of the
+                                   previous qp_sigma call on this context (same
+                                   dets pointer and n_det, contents unchanged, no
+                                   qp_set_integrals since): its generator order
+                                   and coarse lists are reused                   */
 #define QP_FLAG_REUSE_INTEGRALS 4 /* qp_pt2_batched: keep a system's integral layouts
                                      from the previous batched call when its h and
                                      eri_packed pointers and n_orb are the same, and
@@ -299,7 +304,10 @@ int qp_pt2_batched(qp_ctx *ctx, int n_sys, const qp_system *sys, int with_backwa
  * canonical order (up spin-orbitals first).
  *   U, W  device double [n_vec][n_det] (W overwritten)
  * Matrix elements by the Slater-Condon rules as in qp_pt2.  Synchronises
- * once (coarse-list sizes).  Errors: QP_E_ARG, QP_E_NOINT, QP_E_NORB,
+ * once (coarse-list sizes) to prepare the determinant space; with
+ * QP_SIGMA_REUSE and the same dets pointer, n_det and integrals as the
+ * previous qp_sigma call, the preparation is reused and the call only
+ * launches the sigma kernel.  Errors: QP_E_ARG, QP_E_NOINT, QP_E_NORB,
  * QP_E_ELEC, QP_E_DUP, QP_E_OOM, QP_E_HIP.
  */
 int qp_sigma(qp_ctx *ctx, const uint64_t *dets, int64_t n_det, int n_vec, const double *U,

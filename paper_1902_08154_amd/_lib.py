@@ -24,6 +24,7 @@ QP_FLAG_FINGERPRINT = 1
 QP_FLAG_NOCHECK = 2
 QP_FLAG_REUSE_INTEGRALS = 4
 QP_SIGMA_S2 = 8
+QP_SIGMA_REUSE = 16
 QP_MAX_STATES = 4
 QP_MAX_SYSTEMS = 4096
 

@@ -244,12 +244,14 @@ class Context:
         e, err, nc, nr = self.qp_pt2_stochastic(dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round)
         return dict(e_pt2=e, err=err, n_computed=nc, n_rounds=nr)
 
-    def sigma(self, dets, U, s2=False):
-        """W = H U (or S^2 U) for U [n_vec, n_det] on the device."""
+    def sigma(self, dets, U, s2=False, reuse=False):
+        """W = H U (or S^2 U) for U [n_vec, n_det] on the device.  reuse: the
+        caller vouches that `dets` is unchanged since the previous sigma call
+        with the same tensor (QP_SIGMA_REUSE)."""
         _need(dets, torch.int64, "dets", self.device)
         U = U.to(device=self.device, dtype=torch.float64).contiguous()
         W = torch.empty_like(U)
-        self.qp_sigma(dets, U, W, _lib.QP_SIGMA_S2 if s2 else 0)
+        self.qp_sigma(dets, U, W, (_lib.QP_SIGMA_S2 if s2 else 0) | (_lib.QP_SIGMA_REUSE if reuse else 0))
         return W
 
     def davidson(self, dets, n_states=1, guess=None, tol=1e-9, max_iter=200):

@@ -920,6 +920,19 @@ struct LayoutKey {
     int n = 0;
 };
 
+struct Prepared {
+    int nint, nup, ndn, nel;
+    int64_t n_det;
+    int32_t *perm, *rank;
+    double *F, *HII;
+    int64_t *coff;
+    CoarseEnt *cent;
+    Scalars *sc;
+    double *maxc2;
+    double hmax[QPD_MAX_STATES];
+    int64_t coarse_total;
+};
+
 struct qp_ctx {
     int device = 0;
     std::string err;
@@ -934,6 +947,14 @@ struct qp_ctx {
     DevBuf defn;                   // per-system count of handed-over batches
     int num_cu = 256;
     size_t lds_per_cu = 163840;
+    uint64_t ints_gen = 0;         // bumped by every qp_set_integrals
+    // the sigma-build's prepared determinant space, kept in a slot of its own
+    // for QP_SIGMA_REUSE: valid while dets, n_det and the integrals match
+    bool sig_valid = false;
+    const uint64_t *sig_dets = nullptr;
+    int64_t sig_n_det = 0;
+    uint64_t sig_gen = 0;
+    Prepared sig_P;
     Scalars *host_sc = nullptr;    // pinned, one per system
     int host_sc_n = 0;
     uint64_t *host_det0 = nullptr; // pinned
@@ -1053,18 +1074,6 @@ LayoutSizes layout_sizes(int n_orb)
 }
 
 // Everything before the sweep: order, prep, coarse lists.  One host sync.
-struct Prepared {
-    int nint, nup, ndn, nel;
-    int64_t n_det;
-    int32_t *perm, *rank;
-    double *F, *HII;
-    int64_t *coff;
-    CoarseEnt *cent;
-    Scalars *sc;
-    double *maxc2;
-    double hmax[QPD_MAX_STATES];
-    int64_t coarse_total;
-};
 
 template <int NINT>
 int prepare_t(qp_ctx *c, int slot, const DevInts &I, const uint64_t *dets, const double *coefs, int64_t n_det,
@@ -1879,6 +1888,7 @@ int qp_set_integrals(qp_ctx *c, const double *h, const double *eri_packed, int n
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(c, hipStreamSynchronize(st));
+    ++c->ints_gen;
     double **arrs[] = {&c->h, &c->X, &c->Y, &c->Cj, &c->CXj, &c->Jm, &c->Km, &c->JK};
     for (double **p : arrs) if (*p) { (void)hipFree(*p); *p = nullptr; }
     c->n = 0;
@@ -2188,15 +2198,26 @@ int qp_sigma(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_vec, const do
     if (n_det > (int64_t)INT32_MAX / 2) return fail(c, QP_E_ARG, "n_det too large");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
-    // the generator order does not matter here: every weight is 1
-    double *ones = (double *)scratch(c, 0, B_ONES, sizeof(double) * n_det);
-    if (!ones) return fail(c, QP_E_OOM, "device allocation failed");
-    hipLaunchKernelGGL(fill_ones, dim3(grid_for(n_det)), dim3(256), 0, st, ones, n_det);
     const DevInts I = dev_ints(c);
-    Prepared P;
-    int rc = prepare(c, 0, I, dets, ones, n_det, 1, flags & ~QP_SIGMA_S2, st, P);
-    if (rc != QP_OK) return rc;
-    launch_sigma(I, P, dets, n_det, n_vec, (flags & QP_SIGMA_S2) != 0, U, W, st);
+    // the determinant space is prepared in a slot no other call uses, so that
+    // QP_SIGMA_REUSE can find it again
+    const int slot = QP_MAX_SYSTEMS;
+    const bool reuse = (flags & QP_SIGMA_REUSE) && c->sig_valid && c->sig_dets == dets && c->sig_n_det == n_det &&
+                       c->sig_gen == c->ints_gen;
+    if (!reuse) {
+        c->sig_valid = false;
+        // the generator order does not matter here: every weight is 1
+        double *ones = (double *)scratch(c, slot, B_ONES, sizeof(double) * n_det);
+        if (!ones) return fail(c, QP_E_OOM, "device allocation failed");
+        hipLaunchKernelGGL(fill_ones, dim3(grid_for(n_det)), dim3(256), 0, st, ones, n_det);
+        int rc = prepare(c, slot, I, dets, ones, n_det, 1, flags & ~(QP_SIGMA_S2 | QP_SIGMA_REUSE), st, c->sig_P);
+        if (rc != QP_OK) return rc;
+        c->sig_valid = true;
+        c->sig_dets = dets;
+        c->sig_n_det = n_det;
+        c->sig_gen = c->ints_gen;
+    }
+    launch_sigma(I, c->sig_P, dets, n_det, n_vec, (flags & QP_SIGMA_S2) != 0, U, W, st);
     HIPCHK(c, hipGetLastError());
     return QP_OK;
 }

@@ -63,3 +63,17 @@ def test_ctypes_structs_match_the_header(tmp_path):
         size, offs = _c_layout(tmp_path, name, fields)
         assert size == ctypes.sizeof(cls), name
         assert offs == [getattr(cls, f).offset for f in fields], name
+
+
+def test_binding_constants_match_the_header():
+    """Every QP_* integer macro of the header has the same value in the binding."""
+    from paper_1902_08154_amd import _lib
+    txt = open(os.path.join(ROOT, "include", "qp_pt2.h")).read()
+    macros = dict((k, int(v)) for k, v in re.findall(r"#define\s+(QP_[A-Z0-9_]+)\s+(-?\d+)\b", txt))
+    assert "QP_SIGMA_REUSE" in macros and "QP_E_NOCONV" in macros
+    for k, v in macros.items():
+        if hasattr(_lib, k):
+            assert getattr(_lib, k) == v, k
+    for k in ("QP_OK", "QP_FLAG_FINGERPRINT", "QP_FLAG_NOCHECK", "QP_FLAG_REUSE_INTEGRALS", "QP_SIGMA_S2",
+              "QP_SIGMA_REUSE", "QP_MAX_STATES", "QP_MAX_SYSTEMS"):
+        assert k in macros and getattr(_lib, k) == macros[k], k

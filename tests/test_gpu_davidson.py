@@ -40,6 +40,31 @@ def test_sigma_matches_dense_matrices(ctx, name, n, nu, nd, ndet, nv):
     assert np.abs(W2 - U @ S2.T).max() <= 1e-12 * np.abs(U).sum(axis=1).max()
 
 
+def test_sigma_reuse(ctx):
+    """QP_SIGMA_REUSE gives the same bits as a fresh preparation, and a change
+    of integrals or of the determinant list prepares again."""
+    import torch
+    s = synth.make_system("d_n24_4a4b", 3054, 24, 4, 4, 300)
+    dets, _ = gpu_system(ctx, s)
+    U = torch.from_numpy(np.random.default_rng(5).standard_normal((3, 300)))
+    W0 = ctx.sigma(dets, U).cpu().numpy()
+    W1 = ctx.sigma(dets, U, reuse=True).cpu().numpy()
+    W2 = ctx.sigma(dets, U, s2=True, reuse=True).cpu().numpy()
+    assert np.array_equal(W0, W1)
+    assert np.abs(W2 - U.numpy() @ orc.s2_matrix(24, s.dets).T).max() <= 1e-12 * np.abs(U.numpy()).sum(axis=1).max()
+    # other integrals at the same n_orb: the reuse flag must not keep the old diagonal
+    t = synth.make_system("d_n24_4a4b_b", 3055, 24, 4, 4, 300)
+    ctx.qp_set_integrals(torch.from_numpy(t.h).to(ctx.device), torch.from_numpy(t.eri).to(ctx.device))
+    W3 = ctx.sigma(dets, U, reuse=True).cpu().numpy()
+    H = orc.hamiltonian(24, t.h, t.eri, s.dets)
+    assert np.abs(W3 - U.numpy() @ H.T).max() <= 1e-12 * np.abs(H).max() * np.abs(U.numpy()).sum(axis=1).max()
+    # a shorter list at a new address
+    d2, _ = gpu_system(ctx, synth.make_system("d_n24_4a4b_c", 3056, 24, 4, 4, 120))
+    W4 = ctx.sigma(d2, U[:, :120].contiguous(), reuse=True).cpu().numpy()
+    W5 = ctx.sigma(d2, U[:, :120].contiguous()).cpu().numpy()
+    assert np.array_equal(W4, W5)
+
+
 def test_davidson_full_space_matches_dense_eigensolver(ctx):
     """The whole FCI space of n=6, 2+2 electrons: exact eigenpairs."""
     import torch
