@@ -97,6 +97,25 @@ def test_stochastic_matches_oracle_estimator(ctx):
     assert np.all(np.abs(g["err"] - err) <= 1e-8 * scale + 1e-8 * err)
 
 
+def test_stochastic_default_schedule_matches_oracle_estimator(ctx):
+    """The binding's default rounds (n_det / 40 prefix generators, four draws
+    per prefix generator) against the oracle's estimator on the same schedule."""
+    import torch
+    s = _mid()
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    u = synth.uniforms(12, 120)
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    g = ctx.pt2_stochastic(dets, coefs, E0t, u, rel_err=0.05)
+    chunk = max(1, s.n_det // 40)
+    est, err, nc, nr = _oracle_estimate(s, E0, u, 0.05, chunk, max(16, 4 * chunk))
+    assert (g["n_computed"], g["n_rounds"]) == (nc, nr)
+    full = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0)
+    scale = full.abs_e + np.abs(est)
+    assert np.all(np.abs(g["e_pt2"] - est) <= 1e-8 * scale), (g["e_pt2"], est)
+    assert np.all(np.abs(g["err"] - err) <= 1e-8 * scale + 1e-8 * err)
+
+
 def test_stochastic_completes_to_the_deterministic_value(ctx):
     import torch
     s = _mid()
