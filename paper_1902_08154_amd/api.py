@@ -74,16 +74,21 @@ class Context:
         n = h.shape[0]
         self._check(self._lib.qp_set_integrals(self._h, _ptr(h), _ptr(eri_packed), n, _stream(self.device)))
         self.n_orb = n
-        self._ints_key = None
+        self._ints_src = None
 
     def ensure_integrals(self, h: torch.Tensor, eri_packed: torch.Tensor):
-        """qp_set_integrals unless these exact tensors (same storage, same
-        in-place version) were the last ones set."""
+        """qp_set_integrals unless the last tensors set through this method
+        occupy the same memory (address, shape) and have not been modified in
+        place since (same version counter).  The context keeps references to
+        those tensors, so their memory cannot be freed and handed to another
+        tensor at the same address meanwhile: a match is the same storage."""
         key = (h.data_ptr(), h._version, tuple(h.shape), eri_packed.data_ptr(), eri_packed._version,
                eri_packed.numel())
-        if getattr(self, "_ints_key", None) != key:
-            self.qp_set_integrals(h.detach(), eri_packed.detach())
-            self._ints_key = key
+        src = getattr(self, "_ints_src", None)
+        if src is not None and src[2] == key:
+            return
+        self.qp_set_integrals(h.detach(), eri_packed.detach())
+        self._ints_src = (h.detach(), eri_packed.detach(), key)
 
     def qp_pt2(self, dets, coefs, E0, n_select=0, flags=0, e_pt2=None, sel_dets=None, sel_e=None,
                n_sel=None, stats=None, eps_gen=None):
@@ -344,12 +349,16 @@ class PT2Function(torch.autograd.Function):
         context.ensure_integrals(h, eri_packed)
         e = context.pt2(dets, coefs, E0)["e_pt2"]
         fctx.context = context
-        fctx.save_for_backward(dets, coefs, E0)
+        # the integrals travel with the graph node: another forward, or a
+        # qp_set_integrals, between this forward and its backward must not
+        # change the Hamiltonian the backward differentiates
+        fctx.save_for_backward(dets, coefs, E0, h, eri_packed)
         return e
 
     @staticmethod
     def backward(fctx, grad_e):
-        dets, coefs, E0 = fctx.saved_tensors
+        dets, coefs, E0, h, eri_packed = fctx.saved_tensors
+        fctx.context.ensure_integrals(h, eri_packed)
         want = tuple(name for name, need in zip(("coefs", "E0", "h"), fctx.needs_input_grad[2:5]) if need)
         gc, gE, gh = fctx.context.pt2_backward(dets, coefs, E0, grad_e, want=want)
         return None, None, gc, gE, gh, None
