@@ -80,7 +80,8 @@ class System(ctypes.Structure):
 # every entry point declared in include/qp_pt2.h
 EXPORTS = ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
            "qp_pt2_backward", "qp_generator_order", "qp_pt2_generators", "qp_pt2_stochastic",
-           "qp_pt2_batched", "qp_sigma", "qp_davidson", "qp_energy", "qp_set_timing", "qp_last_timing")
+           "qp_pt2_batched", "qp_sigma", "qp_davidson", "qp_energy", "qp_set_timing", "qp_last_timing",
+           "qp_set_split")
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -127,5 +128,7 @@ def load():
     lib.qp_set_timing.restype = _I
     lib.qp_last_timing.argtypes = [_P, ctypes.POINTER(ctypes.c_double)]
     lib.qp_last_timing.restype = _I
+    lib.qp_set_split.argtypes = [_P, _I]
+    lib.qp_set_split.restype = _I
     _lib = lib
     return lib

@@ -160,10 +160,14 @@ class Context:
         self._check(self._lib.qp_set_timing(self._h, 1 if enable else 0))
 
     def qp_last_timing(self):
-        """(dense sweep kernel ms, general kernel ms, whole call ms) of the last timed call."""
-        out = (ctypes.c_double * 3)()
+        """(dense sweep kernel ms, general kernel ms, whole call ms, clean-cell kernel ms)
+        of the last timed call."""
+        out = (ctypes.c_double * 4)()
         self._check(self._lib.qp_last_timing(self._h, out))
-        return float(out[0]), float(out[1]), float(out[2])
+        return float(out[0]), float(out[1]), float(out[2]), float(out[3])
+
+    def qp_set_split(self, enable: bool):
+        self._check(self._lib.qp_set_split(self._h, 1 if enable else 0))
 
     # ---------------------------------------------------------- conveniences
     def _inputs(self, dets, coefs, E0=None):

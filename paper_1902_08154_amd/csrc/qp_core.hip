@@ -448,6 +448,127 @@ __global__ void make_coff(const int64_t *offs, int64_t n_det, int nchunk, const 
     if (g == n_det) { coff[g] = *total; sc->coarse_total = (unsigned long long)*total; }
 }
 
+// ---------------------------------------------------------------- hole-pair lists
+// The clean-cell kernel's items in hole-pair-major order.  Occupation bitsets
+// over the call's generators: bits[(s n + p) nw + w], bit i of word w set when
+// the determinant of generator position 64 w + i has orbital p of spin s.
+template <int NINT>
+__global__ void pair_bits(const uint64_t *dets, const int32_t *perm, const int32_t *gen_list, int64_t n_gen, int n,
+                          int64_t nw, uint64_t *bits)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= nw) return;
+    const int64_t i = w * 64 + lane;
+    uint64_t d[2 * NINT];
+#pragma unroll
+    for (int q = 0; q < 2 * NINT; ++q) d[q] = 0;
+    if (i < n_gen) {
+        const int64_t gr = gen_list ? (int64_t)gen_list[i] : i;
+        const int det = perm[gr];
+#pragma unroll
+        for (int q = 0; q < 2 * NINT; ++q) d[q] = dets[(int64_t)det * 2 * NINT + q];
+    }
+    for (int s = 0; s < 2; ++s)
+        for (int p = 0; p < n; ++p) {
+            const uint64_t m = __ballot(occ_bit<NINT>(d, s, p) != 0);
+            if (lane == 0) bits[((int64_t)s * n + p) * nw + w] = m;
+        }
+}
+
+// the two bitsets of pair key K (see SweepArgs): opposite spins K = a n + b,
+// same spin K = n^2 + s n(n-1)/2 + tris(a, b)
+__device__ __forceinline__ void pair_sets(int K, int n, int64_t nw, const uint64_t *bits, const uint64_t *&x,
+                                          const uint64_t *&y)
+{
+    if (K < n * n) {
+        const int a = K / n, b = K - a * n;
+        x = bits + (int64_t)a * nw;
+        y = bits + ((int64_t)n + b) * nw;
+    } else {
+        const int P2 = n * (n - 1) / 2;
+        const int t = K - n * n, s = t >= P2 ? 1 : 0, u = t - s * P2;
+        int b = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)u)) * 0.5f);
+        while (b * (b - 1) / 2 > u) --b;
+        while ((b + 1) * b / 2 <= u) ++b;
+        const int a = u - b * (b - 1) / 2;
+        x = bits + ((int64_t)s * n + a) * nw;
+        y = bits + ((int64_t)s * n + b) * nw;
+    }
+}
+
+// generators per pair key (one wave per key)
+__global__ void pair_count(const uint64_t *bits, int n, int64_t nw, int n_keys, int32_t *counts)
+{
+    const int lane = threadIdx.x & 63;
+    const int K = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (K >= n_keys) return;
+    const uint64_t *x, *y;
+    pair_sets(K, n, nw, bits, x, y);
+    int c = 0;
+    for (int64_t w = lane; w < nw; w += 64) c += __popcll(x[w] & y[w]);
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) counts[K] = c;
+}
+
+// the generator positions of each key, ascending, at the scanned offsets; a
+// write past `cap` (inconsistent electron counts under QP_FLAG_NOCHECK) is dropped
+__global__ void pair_fill(const uint64_t *bits, int n, int64_t nw, int n_keys, const int64_t *off, int64_t cap,
+                          int32_t *pos)
+{
+    const int lane = threadIdx.x & 63;
+    const int K = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (K >= n_keys) return;
+    const uint64_t *x, *y;
+    pair_sets(K, n, nw, bits, x, y);
+    int64_t o = off[K];
+    for (int64_t w0 = 0; w0 < nw; w0 += 64) {
+        const int64_t w = w0 + lane;
+        uint64_t m = w < nw ? (x[w] & y[w]) : 0ull;
+        int c = __popcll(m);
+        // exclusive scan of the lanes' counts
+        int incl = c;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        int64_t at = o + (incl - c);
+        while (m) {
+            const int b = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            if (at < cap) pos[at] = (int32_t)(w * 64 + b);
+            ++at;
+        }
+        o += __shfl(incl, 63);
+    }
+}
+
+// per generator: the clean-cell kernel's batch slots, in batch order, after
+// the dense kernel's items and the handed-over batches
+__global__ void reduce_lean(const double *lean_eps, const double *lean_S, const unsigned long long *lean_cnt,
+                            const unsigned long long *lean_fp, int64_t n_gen, int n_pairs, int ns,
+                            const int32_t *perm, const int32_t *gen_rank, int64_t n_det, double *eps_g,
+                            double *S_g, uint64_t *cnt_g, uint64_t *fp_g, double *eps_gen)
+{
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i0 >= n_gen) return;
+    for (int k = 0; k < ns; ++k) {
+        double e = eps_g[i0 * ns + k], sv = S_g[i0 * ns + k];
+        for (int b = 0; b < n_pairs; ++b) {
+            e += lean_eps[(i0 * n_pairs + b) * ns + k];
+            sv += lean_S[(i0 * n_pairs + b) * ns + k];
+        }
+        eps_g[i0 * ns + k] = e;
+        S_g[i0 * ns + k] = sv;
+        if (eps_gen) {
+            if (gen_rank) eps_gen[k * n_gen + i0] = e;
+            else eps_gen[k * n_det + perm[i0]] = e;
+        }
+    }
+    cnt_g[i0] += lean_cnt[i0];
+    fp_g[i0] += lean_fp[i0];
+}
+
 // ---------------------------------------------------------------- reductions
 // per generator: sum its items in order; eps_gen in the caller's index
 // Deferred partials of one generator, in increasing batch order (its list is
@@ -907,6 +1028,8 @@ enum BufId {
     B_DCI, B_EPSG, B_SG, B_CNTG, B_FPG, B_SC, B_HIST, B_CAND, B_COMP, B_SKEY, B_SBITS, B_SIDX, B_MAXC2,
     B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFE, B_DEFS, B_DEFC, B_DEFN, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
     B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_GENR,
+    // split sweep: hole-pair lists and the clean-cell kernel's slots
+    B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP,
     // integral layouts of a system of a batched call
     B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
     // Davidson
@@ -943,7 +1066,7 @@ struct qp_ctx {
     // batched call; single-system calls use slot 0
     std::vector<std::vector<DevBuf>> slots;
     std::vector<LayoutKey> layout_keys;
-    DevBuf args[2];                // per-launch system descriptors (dense, general)
+    DevBuf args[3];                // per-launch system descriptors (dense, general, clean-cell)
     DevBuf defn;                   // per-system count of handed-over batches
     int num_cu = 256;
     size_t lds_per_cu = 163840;
@@ -963,8 +1086,10 @@ struct qp_ctx {
     size_t host_stage_bytes = 0;
     bool timing = false;
     bool timed = false;
+    bool split_enabled = true;     // forward sweeps split clean cells off (qp_set_split)
     // call start, dense sweep start, general kernel start, sweep end, call end
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // [5]: between the dense kernel and the clean-cell kernel
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -1219,14 +1344,37 @@ int fast_occ_t(int ns, bool bwd, size_t lds, bool fp)
 }
 
 // persistent grid: every resident one-wavefront workgroup the CUs can hold
-int persistent_grid(qp_ctx *c, bool dense, int nint, int ns, bool bwd, size_t lds, bool fp)
+// the three sweep kernels: the dense kernel, the general kernel on handed-over
+// batches, and the clean-cell kernel of a split sweep
+enum Kind { K_DENSE = 0, K_GENERAL = 1, K_LEAN = 2 };
+
+template <int NINT>
+int lean_occ_t(int ns, size_t lds, bool fp)
+{
+    switch (ns) {
+    case 1: return lean_occupancy<NINT, 1, false>(lds, fp);
+    case 2: return lean_occupancy<NINT, 2, false>(lds, fp);
+    case 3: return lean_occupancy<NINT, 3, false>(lds, fp);
+    default: return lean_occupancy<NINT, 4, false>(lds, fp);
+    }
+}
+
+template <int NINT>
+int kind_occ_t(int kind, int ns, bool bwd, size_t lds, bool fp)
+{
+    if (kind == K_DENSE) return fast_occ_t<NINT>(ns, bwd, lds, fp);
+    if (kind == K_LEAN) return lean_occ_t<NINT>(ns, lds, fp);
+    return sweep_occ_t<NINT>(ns, bwd, lds);
+}
+
+int persistent_grid(qp_ctx *c, int kind, int nint, int ns, bool bwd, size_t lds, bool fp)
 {
     int per_cu = 8;
     switch (nint) {
-    case 1: per_cu = dense ? fast_occ_t<1>(ns, bwd, lds, fp) : sweep_occ_t<1>(ns, bwd, lds); break;
-    case 2: per_cu = dense ? fast_occ_t<2>(ns, bwd, lds, fp) : sweep_occ_t<2>(ns, bwd, lds); break;
-    case 3: per_cu = dense ? fast_occ_t<3>(ns, bwd, lds, fp) : sweep_occ_t<3>(ns, bwd, lds); break;
-    default: per_cu = dense ? fast_occ_t<4>(ns, bwd, lds, fp) : sweep_occ_t<4>(ns, bwd, lds); break;
+    case 1: per_cu = kind_occ_t<1>(kind, ns, bwd, lds, fp); break;
+    case 2: per_cu = kind_occ_t<2>(kind, ns, bwd, lds, fp); break;
+    case 3: per_cu = kind_occ_t<3>(kind, ns, bwd, lds, fp); break;
+    default: per_cu = kind_occ_t<4>(kind, ns, bwd, lds, fp); break;
     }
     // The hardware allocates a workgroup's LDS in granules, which the runtime's
     // occupancy figure does not round to: where the rounded size leaves room
@@ -1255,7 +1403,7 @@ int persistent_grid(qp_ctx *c, bool dense, int nint, int ns, bool bwd, size_t ld
 int buffer_rows(qp_ctx *c, int n, int nvm, int nint, int ns, bool bwd, bool fp)
 {
     if (n > 128) return 3;
-    const int regs = persistent_grid(c, true, nint, ns, bwd, 0, fp) / c->num_cu;
+    const int regs = persistent_grid(c, K_DENSE, nint, ns, bwd, 0, fp) / c->num_cu;
     int cap = 6;
     while (cap > 4) {
         const size_t lds = fast_lds_bytes(n, nvm, ns, bwd, cap, cap);
@@ -1267,10 +1415,12 @@ int buffer_rows(qp_ctx *c, int n, int nvm, int nint, int ns, bool bwd, bool fp)
 }
 
 template <int NINT, int NS>
-void launch_ns(bool dense, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd, bool fp, size_t lds,
+void launch_ns(int kind, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd, bool fp, size_t lds,
                int grid, hipStream_t st)
 {
-    if (dense) {
+    if (kind == K_LEAN) {
+        launch_lean<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
+    } else if (kind == K_DENSE) {
         if (bwd) launch_fast<NINT, NS, true>(sys, end, n_sys, fp, lds, grid, st);
         else launch_fast<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
     } else {
@@ -1280,25 +1430,25 @@ void launch_ns(bool dense, const SweepArgs *sys, const int64_t *end, int n_sys, 
 }
 
 template <int NINT>
-void launch_nint(bool dense, int ns, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd, bool fp,
+void launch_nint(int kind, int ns, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd, bool fp,
                  size_t lds, int grid, hipStream_t st)
 {
     switch (ns) {
-    case 1: launch_ns<NINT, 1>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
-    case 2: launch_ns<NINT, 2>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
-    case 3: launch_ns<NINT, 3>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
-    default: launch_ns<NINT, 4>(dense, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 1: launch_ns<NINT, 1>(kind, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 2: launch_ns<NINT, 2>(kind, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 3: launch_ns<NINT, 3>(kind, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    default: launch_ns<NINT, 4>(kind, sys, end, n_sys, bwd, fp, lds, grid, st); break;
     }
 }
 
-void launch_kernel(bool dense, int nint, int ns, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd,
+void launch_kernel(int kind, int nint, int ns, const SweepArgs *sys, const int64_t *end, int n_sys, bool bwd,
                    bool fp, size_t lds, int grid, hipStream_t st)
 {
     switch (nint) {
-    case 1: launch_nint<1>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
-    case 2: launch_nint<2>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
-    case 3: launch_nint<3>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
-    default: launch_nint<4>(dense, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 1: launch_nint<1>(kind, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 2: launch_nint<2>(kind, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    case 3: launch_nint<3>(kind, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
+    default: launch_nint<4>(kind, ns, sys, end, n_sys, bwd, fp, lds, grid, st); break;
     }
 }
 
@@ -1372,6 +1522,8 @@ struct SysRun {
     int64_t n_def = 0;
     SweepArgs d;
     DefParts dp;
+    bool split = false;         // forward split sweep (clean-cell kernel)
+    int n_pairs = 0;
 };
 
 // the launches of one kernel over several systems: one per (n_int, n_states)
@@ -1384,7 +1536,7 @@ struct LaunchPlan {
     std::vector<int64_t> end;   // running item end per listed system
 };
 
-std::vector<LaunchPlan> plan_launches(qp_ctx *c, bool dense, bool bwd, bool fp, const std::vector<SysIn> &in,
+std::vector<LaunchPlan> plan_launches(qp_ctx *c, int kind, bool bwd, bool fp, const std::vector<SysIn> &in,
                                       const std::vector<SysRun> &run, const std::vector<int64_t> &items)
 {
     std::vector<LaunchPlan> plans;
@@ -1392,12 +1544,10 @@ std::vector<LaunchPlan> plan_launches(qp_ctx *c, bool dense, bool bwd, bool fp, 
         if (items[s] <= 0) continue;
         const int nint = run[s].nint, ns = in[s].ns, n = in[s].I.n;
         size_t lds;
-        if (dense) {
-            const int nvm = n - std::min(run[s].P.nup, run[s].P.ndn);
-            lds = fast_lds_bytes(n, nvm, ns, bwd, run[s].a.rscap, run[s].a.cscap);
-        } else {
-            lds = sweep_lds_bytes(n, ns, bwd);
-        }
+        const int nvm = n - std::min(run[s].P.nup, run[s].P.ndn);
+        if (kind == K_DENSE) lds = fast_lds_bytes(n, nvm, ns, bwd, run[s].a.rscap, run[s].a.cscap);
+        else if (kind == K_LEAN) lds = lean_lds_bytes(n, nvm);
+        else lds = sweep_lds_bytes(n, ns, bwd);
         LaunchPlan *p = nullptr;
         for (auto &q : plans) if (q.nint == nint && q.ns == ns) p = &q;
         if (!p) {
@@ -1408,12 +1558,12 @@ std::vector<LaunchPlan> plan_launches(qp_ctx *c, bool dense, bool bwd, bool fp, 
         p->sys.push_back((int)s);
         p->end.push_back((p->end.empty() ? 0 : p->end.back()) + items[s]);
     }
-    for (auto &p : plans) p.grid = persistent_grid(c, dense, p.nint, p.ns, bwd, p.lds, fp);
+    for (auto &p : plans) p.grid = persistent_grid(c, kind, p.nint, p.ns, bwd, p.lds, fp);
     return plans;
 }
 
 // copy the plans' descriptors to the device in one transfer and launch them
-int launch_plans(qp_ctx *c, bool dense, bool bwd, bool fp, std::vector<LaunchPlan> &plans,
+int launch_plans(qp_ctx *c, int kind, bool bwd, bool fp, std::vector<LaunchPlan> &plans,
                  const std::vector<SysRun> &run, hipStream_t st)
 {
     if (plans.empty()) return QP_OK;
@@ -1423,16 +1573,17 @@ int launch_plans(qp_ctx *c, bool dense, bool bwd, bool fp, std::vector<LaunchPla
     const size_t bytes = args_bytes + sizeof(int64_t) * nsys;
     // the staging area is reused only after a host synchronisation on `st`,
     // which every call performs between its two launch rounds
-    unsigned char *stage = c->host_stage + (dense ? 0 : c->host_stage_bytes / 2);
-    if (bytes > c->host_stage_bytes / 2) return fail(c, QP_E_ARG, "staging area too small");
-    unsigned char *dev = (unsigned char *)grow(c->args[dense ? 0 : 1], bytes);
+    const size_t third = c->host_stage_bytes / 3 / 16 * 16;
+    unsigned char *stage = c->host_stage + kind * third;
+    if (bytes > third) return fail(c, QP_E_ARG, "staging area too small");
+    unsigned char *dev = (unsigned char *)grow(c->args[kind], bytes);
     if (!dev) return fail(c, QP_E_OOM, "device allocation failed (system descriptors)");
     SweepArgs *ha = (SweepArgs *)stage;
     int64_t *he = (int64_t *)(stage + args_bytes);
     size_t k = 0;
     for (auto &p : plans)
         for (size_t i = 0; i < p.sys.size(); ++i, ++k) {
-            ha[k] = dense ? run[p.sys[i]].a : run[p.sys[i]].d;
+            ha[k] = kind == K_GENERAL ? run[p.sys[i]].d : run[p.sys[i]].a;
             he[k] = p.end[i];
         }
     HIPCHK(c, hipMemcpyAsync(dev, stage, bytes, hipMemcpyHostToDevice, st));
@@ -1441,8 +1592,8 @@ int launch_plans(qp_ctx *c, bool dense, bool bwd, bool fp, std::vector<LaunchPla
         const SweepArgs *da = (const SweepArgs *)dev + k;
         const int64_t *de = (const int64_t *)(dev + args_bytes) + k;
         int grid = p.grid;
-        if (!dense) grid = (int)std::min<int64_t>(grid, p.end.back());
-        launch_kernel(dense, p.nint, p.ns, da, de, (int)p.sys.size(), bwd, fp, p.lds, grid, st);
+        if (kind != K_DENSE) grid = (int)std::min<int64_t>(grid, p.end.back());
+        launch_kernel(kind, p.nint, p.ns, da, de, (int)p.sys.size(), bwd, fp, p.lds, grid, st);
         HIPCHK(c, hipGetLastError());
         k += p.sys.size();
     }
@@ -1460,12 +1611,12 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     c->timed = false;
     if (n_sys == 0) return QP_OK;
     {
-        int rc = host_space(c, std::max<size_t>(1 << 16, 2 * (sizeof(SweepArgs) + 8) * (size_t)n_sys + 256), n_sys);
+        int rc = host_space(c, std::max<size_t>(3 << 16, 3 * ((sizeof(SweepArgs) + 8) * (size_t)n_sys + 256)), n_sys);
         if (rc != QP_OK) return rc;
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], st));
     std::vector<SysRun> run(n_sys);
-    std::vector<int64_t> items(n_sys, 0);
+    std::vector<int64_t> items(n_sys, 0), litems(n_sys, 0);
     const bool fp = (flags & QP_FLAG_FINGERPRINT) != 0;
 
     // ------------------------------------------------------------ phase 1
@@ -1548,9 +1699,9 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         const int nvm = n - std::min(r.P.nup, r.P.ndn);
         const int rscap = buffer_rows(c, n, nvm, r.nint, ns, bwd, fp), cscap = rscap;
         if (x.n_select > 0) {
-            const int grid = std::max(persistent_grid(c, true, r.nint, ns, bwd,
+            const int grid = std::max(persistent_grid(c, K_DENSE, r.nint, ns, bwd,
                                                       fast_lds_bytes(n, nvm, ns, bwd, rscap, cscap), fp),
-                                      persistent_grid(c, false, r.nint, ns, bwd, sweep_lds_bytes(n, ns, bwd), fp));
+                                      persistent_grid(c, K_GENERAL, r.nint, ns, bwd, sweep_lds_bytes(n, ns, bwd), fp));
             const int64_t maxcell = std::max<int64_t>((int64_t)(n - r.P.nup) * (n - r.P.ndn),
                                                       (int64_t)(n - r.P.nup) * (n - r.P.nup - 1) / 2);
             r.cand_cap = x.n_select + std::max<int64_t>(1 << 22, 2 * (int64_t)grid * std::min<int64_t>(maxcell, 3072));
@@ -1588,13 +1739,64 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         a.def_bits = r.def_bits; a.nbw = r.nbw;
         a.def_mode = 0;
         items[s] = r.swept ? r.n_items : 0;
+        // split sweep (forward): hole-pair lists for the clean-cell kernel
+        r.split = !bwd && r.swept && nel >= 2 && c->split_enabled;
+        if (r.split) {
+            const int np = nel * (nel - 1) / 2;
+            const int n_keys = n * n + n * (n - 1);
+            const int64_t nw = (n_g + 63) / 64;
+            const int64_t tot = n_g * np;
+            const int64_t nkb = (n_keys + 1023) / 1024;
+            uint64_t *bits = (uint64_t *)scratch(c, s, B_LBITS, sizeof(uint64_t) * 2 * n * nw);
+            int32_t *kcnt = (int32_t *)scratch(c, s, B_LKCNT, sizeof(int32_t) * n_keys);
+            int64_t *koff = (int64_t *)scratch(c, s, B_LKOFF, sizeof(int64_t) * (n_keys + 1));
+            int64_t *kbs = (int64_t *)scratch(c, s, B_LKBS, sizeof(int64_t) * nkb);
+            int32_t *kpos = (int32_t *)scratch(c, s, B_LPOS, sizeof(int32_t) * tot);
+            double *leps = (double *)scratch(c, s, B_LEPS, sizeof(double) * tot * ns);
+            double *lS = (double *)scratch(c, s, B_LS, sizeof(double) * tot * ns);
+            unsigned long long *lcnt = (unsigned long long *)scratch(c, s, B_LCNT, sizeof(unsigned long long) * n_g);
+            unsigned long long *lfp = (unsigned long long *)scratch(c, s, B_LFP, sizeof(unsigned long long) * n_g);
+            if (!bits || !kcnt || !koff || !kbs || !kpos || !leps || !lS || !lcnt || !lfp)
+                return fail(c, QP_E_OOM, "device allocation failed (clean-cell lists)");
+            HIPCHK(c, hipMemsetAsync(lcnt, 0, sizeof(unsigned long long) * n_g, st));
+            HIPCHK(c, hipMemsetAsync(lfp, 0, sizeof(unsigned long long) * n_g, st));
+            switch (r.nint) {
+            case 1: hipLaunchKernelGGL(pair_bits<1>, dim3(grid_for(nw, 4, 1 << 30)), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, n, nw, bits); break;
+            case 2: hipLaunchKernelGGL(pair_bits<2>, dim3(grid_for(nw, 4, 1 << 30)), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, n, nw, bits); break;
+            case 3: hipLaunchKernelGGL(pair_bits<3>, dim3(grid_for(nw, 4, 1 << 30)), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, n, nw, bits); break;
+            default: hipLaunchKernelGGL(pair_bits<4>, dim3(grid_for(nw, 4, 1 << 30)), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, n, nw, bits); break;
+            }
+            hipLaunchKernelGGL(pair_count, dim3((n_keys + 3) / 4), dim3(256), 0, st, bits, n, nw, n_keys, kcnt);
+            hipLaunchKernelGGL(scan_block, dim3((unsigned)nkb), dim3(256), 0, st, kcnt, (int64_t)n_keys, koff, kbs);
+            hipLaunchKernelGGL(scan_bsum, dim3(1), dim3(1), 0, st, kbs, nkb, koff + n_keys);
+            hipLaunchKernelGGL(scan_add, dim3(grid_for(n_keys, 256, 1 << 30)), dim3(256), 0, st, koff, (int64_t)n_keys, kbs);
+            hipLaunchKernelGGL(pair_fill, dim3((n_keys + 3) / 4), dim3(256), 0, st, bits, n, nw, n_keys, koff, tot, kpos);
+            HIPCHK(c, hipGetLastError());
+            a.split = 1;
+            a.n_pairs = np;
+            a.kl_off = koff;
+            a.kl_pos = kpos;
+            a.n_keys = n_keys;
+            a.lean_eps = leps;
+            a.lean_S = lS;
+            a.lean_cnt = lcnt;
+            a.lean_fp = lfp;
+            r.n_pairs = np;
+            litems[s] = tot;
+        }
     }
 
     // ------------------------------------------------- phase 2: dense kernel
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], st));
     {
-        std::vector<LaunchPlan> plans = plan_launches(c, true, bwd, fp, in, run, items);
-        int rc = launch_plans(c, true, bwd, fp, plans, run, st);
+        std::vector<LaunchPlan> plans = plan_launches(c, K_DENSE, bwd, fp, in, run, items);
+        int rc = launch_plans(c, K_DENSE, bwd, fp, plans, run, st);
+        if (rc != QP_OK) return rc;
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], st));
+        // the clean cells of split sweeps, after the dense kernel, whose
+        // selection candidates have raised the threshold by then
+        std::vector<LaunchPlan> lplans = plan_launches(c, K_LEAN, bwd, fp, in, run, litems);
+        rc = launch_plans(c, K_LEAN, bwd, fp, lplans, run, st);
         if (rc != QP_OK) return rc;
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
@@ -1666,8 +1868,8 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     }
     // ------------------------------------------------ phase 4: general kernel
     {
-        std::vector<LaunchPlan> plans = plan_launches(c, false, bwd, fp, in, run, gitems);
-        int rc = launch_plans(c, false, bwd, fp, plans, run, st);
+        std::vector<LaunchPlan> plans = plan_launches(c, K_GENERAL, bwd, fp, in, run, gitems);
+        int rc = launch_plans(c, K_GENERAL, bwd, fp, plans, run, st);
         if (rc != QP_OK) return rc;
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], st));
@@ -1684,7 +1886,11 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
                                r.n_g, r.Q, ns, r.P.perm, (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g,
                                r.cnt_g, r.fp_g, r.conn_g, r.defa_g, bwd ? nullptr : x.eps_gen,
                                bwd ? x.grad_coefs : nullptr, r.dp);
-        else if (r.n_g > 0)
+        if (r.swept && r.split)
+            hipLaunchKernelGGL(reduce_lean, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.a.lean_eps, r.a.lean_S,
+                               r.a.lean_cnt, r.a.lean_fp, r.n_g, r.n_pairs, ns, r.P.perm, (const int32_t *)r.gen_rank,
+                               x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, bwd ? nullptr : x.eps_gen);
+        else if (!r.swept && r.n_g > 0)
             hipLaunchKernelGGL(reduce_empty, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.n_g, ns, r.P.perm,
                                (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
                                r.defa_g, bwd ? nullptr : x.eps_gen);
@@ -2467,13 +2673,23 @@ int qp_last_timing(qp_ctx *c, double *out_ms)
     if (!c || !out_ms) return QP_E_ARG;
     if (!c->timing || !c->timed) return fail(c, QP_E_ARG, "no timed call");
     HIPCHK(c, hipEventSynchronize(c->ev[4]));
-    float a = 0.f, b = 0.f, t = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[2]));
+    float a = 0.f, b = 0.f, t = 0.f, l = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[5]));
+    HIPCHK(c, hipEventElapsedTime(&l, c->ev[5], c->ev[2]));
     HIPCHK(c, hipEventElapsedTime(&b, c->ev[2], c->ev[3]));
     HIPCHK(c, hipEventElapsedTime(&t, c->ev[0], c->ev[4]));
     out_ms[0] = a;
     out_ms[1] = b;
     out_ms[2] = t;
+    out_ms[3] = l;
+    return QP_OK;
+}
+
+int qp_set_split(qp_ctx *c, int enable)
+{
+    if (!c) return QP_E_ARG;
+    c->err.clear();
+    c->split_enabled = enable != 0;
     return QP_OK;
 }
 

@@ -346,6 +346,23 @@ struct SweepArgs {
     double *dc_item;          // [n_items][ns]  generator's own dc share
     double *dc;               // [ns][n_det]    other J (atomics)
     double *dh;               // [n][n]         atomics
+    // split sweep: the clean-cell kernel (qp_lean.hip) takes every cell of a
+    // hole-pair batch that no other determinant touches; the dense kernel then
+    // leaves those cells out (split = 1).  The clean-cell kernel's items are the
+    // (hole pair, generator) batches in hole-pair order: kl_off[K] .. kl_off[K+1]
+    // holds the call positions of the generators whose determinant has both
+    // holes of pair K occupied, ascending.  Pair keys: K = a n + b for the
+    // opposite-spin pair (a up, b down); K = n^2 + s n(n-1)/2 + tris(a, b) for
+    // the same-spin pair a < b of spin s.
+    int split;
+    int n_pairs;              // hole pairs per generator: nel (nel - 1) / 2
+    const int64_t *kl_off;    // [n_keys + 1]
+    const int32_t *kl_pos;    // [n_gen * n_pairs]
+    int n_keys;
+    double *lean_eps;         // [n_gen][n_pairs][ns]  per-batch partial sums
+    double *lean_S;           // [n_gen][n_pairs][ns]
+    unsigned long long *lean_cnt;  // [n_gen] clean cells counted (atomics)
+    unsigned long long *lean_fp;   // [n_gen] fingerprint sums (atomics)
 };
 
 // The sweep kernels read each system's SweepArgs from a table in device
@@ -366,3 +383,14 @@ void launch_fast(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool 
 template <int NINT, int NS, bool BWD>
 int fast_occupancy(size_t lds, bool fp);
 size_t fast_lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap);
+template <int NINT, int NS, bool BWD>
+void launch_lean(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
+                 hipStream_t st);
+template <int NINT, int NS, bool BWD>
+int lean_occupancy(size_t lds, bool fp);
+size_t lean_lds_bytes(int n, int nvm);
+// capacities of the dense kernel's per-batch correction buffers; the clean-cell
+// kernel applies the same limits to decide which batches it takes
+#define QPF_FCAP 32
+#define QPF_L2CAP 64
+#define QPF_PCAP 2

@@ -30,14 +30,18 @@
 // exact and leaves the minimum |delta| untouched.
 #pragma once
 #include "qp_dev.h"
+#if __has_include("qp_fast_caps_gen.h")
+#include "qp_fast_caps_gen.h"
+#else
 #include "qp_fast_caps.h"
+#endif
 
 namespace qpfast {
 
 constexpr int WAVE = 64;
-constexpr int FCAP = 32;      // fine entries per batch
-constexpr int L2CAP = 64;     // m = 2 cells per batch
-constexpr int PCAP = 2;       // m = 0 entries (integral planes) per batch
+constexpr int FCAP = QPF_FCAP;     // fine entries per batch
+constexpr int L2CAP = QPF_L2CAP;   // m = 2 cells per batch
+constexpr int PCAP = QPF_PCAP;     // m = 0 entries (integral planes) per batch
 constexpr uint32_t FR = 1u << 8;    // row (OS) / second index (SS) carries a row or list correction
 constexpr uint32_t FC = 1u << 9;    // column (OS) / first index (SS) carries a column correction
 constexpr uint32_t SGN = 1u << 31;  // phase bit
@@ -996,9 +1000,30 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 }
                 plane_flush();
             } else if (type == BT_OS) {
-                if (lane == 0) cnt += (uint32_t)(nr * nc);
                 const double *Jm = a.I.Jm;
-                for (int c0 = 0; c0 < nc; c0 += WAVE) {
+                // split sweep: the clean cells (unflagged row and column) belong
+                // to the clean-cell kernel; this kernel takes the flagged rows,
+                // every column, and the column pass below
+                const bool split = !BWD && a.split;
+                if (split) {
+                    for (int r = 0; r < nr; ++r) {
+                        const PEnt re = sRT[r];
+                        if (!(rfl(re.info) & FR)) continue;
+                        const int pr = re.info & 255;
+                        for (int c0 = 0; c0 < nc; c0 += WAVE) {
+                            const int l = c0 + lane;
+                            if (l < nc) {
+                                const PEnt ce = sCT[l];
+                                const int pcol = ce.info & 255;
+                                cnt++;
+                                post_cell(r, l, blk[pr * n + pcol], re.info ^ ce.info,
+                                          (ce.G + re.G) + Jm[pr * n + pcol], pr, pcol);
+                            }
+                        }
+                    }
+                }
+                if (!split && lane == 0) cnt += (uint32_t)(nr * nc);
+                for (int c0 = 0; !split && c0 < nc; c0 += WAVE) {
                     const int l = c0 + lane;
                     const bool lok = l < nc;
                     const int lc = lok ? l : nc - 1;
@@ -1092,15 +1117,36 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         if (r < nr && !(re.info & FR)) {
                             const int pr = re.info & 255;
                             const double xj = Jm[pr * n + pcol];
+                            if (split) cnt++;
                             post_cell(r, col, blk[pr * n + pcol], re.info ^ ce.info, (ce.G + re.G) + xj, pr, pcol);
                         }
                     }
                 }
             } else if (type == BT_SS) {
-                if (lane == 0) cnt += (uint32_t)(nr * (nr - 1) / 2);
                 const double *JK = a.I.JK;
                 const uint32_t shb = sH ? SGN : 0u;
-                for (int c0 = 0; c0 < nr; c0 += WAVE) {
+                // split sweep: cells (i1, i2) whose second index is flagged, then
+                // the column pass below; the clean cells go to the clean-cell kernel
+                const bool split = !BWD && a.split;
+                if (split) {
+                    for (int i2 = 1; i2 < nr; ++i2) {
+                        const PEnt e2 = sRT[i2];
+                        if (!(rfl(e2.info) & FR)) continue;
+                        const int p2 = e2.info & 255;
+                        for (int j0 = 0; j0 < i2; j0 += WAVE) {
+                            const int i1 = j0 + lane;
+                            if (i1 < i2) {
+                                const PEnt e1 = sRT[i1];
+                                const int p1 = e1.info & 255;
+                                cnt++;
+                                post_cell(i1, i2, blk[p2 * (p2 - 1) / 2 + p1], e1.info ^ e2.info ^ shb,
+                                          ((D0 + e2.G) + e1.G) + JK[p2 * n + p1], p1, p2);
+                            }
+                        }
+                    }
+                }
+                if (!split && lane == 0) cnt += (uint32_t)(nr * (nr - 1) / 2);
+                for (int c0 = 0; !split && c0 < nr; c0 += WAVE) {
                     const int l = c0 + lane;
                     const bool lok = l < nr;
                     if (BWD || lok) {
@@ -1217,6 +1263,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         if (i2 < nr && !(e2.info & FR)) {
                             const int p2 = e2.info & 255;
                             const double xj = JK[p2 * n + p1];
+                            if (split) cnt++;
                             post_cell(ie, i2, blk[p2 * (p2 - 1) / 2 + p1], e1.info ^ e2.info ^ shb,
                                       ((D0 + e2.G) + e1.G) + xj, p1, p2);
                         }
