@@ -546,9 +546,10 @@ __global__ void pair_fill(const uint64_t *bits, int n, int64_t nw, int n_keys, c
 // per generator: the clean-cell kernel's batch slots, in batch order, after
 // the dense kernel's items and the handed-over batches
 __global__ void reduce_lean(const double *lean_eps, const double *lean_S, const unsigned long long *lean_cnt,
-                            const unsigned long long *lean_fp, int64_t n_gen, int n_pairs, int ns,
-                            const int32_t *perm, const int32_t *gen_rank, int64_t n_det, double *eps_g,
-                            double *S_g, uint64_t *cnt_g, uint64_t *fp_g, double *eps_gen)
+                            const unsigned long long *lean_fp, const unsigned long long *lean_conn, int64_t n_gen,
+                            int n_pairs, int ns, const int32_t *perm, const int32_t *gen_rank, int64_t n_det,
+                            double *eps_g, double *S_g, uint64_t *cnt_g, uint64_t *fp_g, uint64_t *conn_g,
+                            double *eps_gen)
 {
     const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i0 >= n_gen) return;
@@ -567,6 +568,7 @@ __global__ void reduce_lean(const double *lean_eps, const double *lean_S, const 
     }
     cnt_g[i0] += lean_cnt[i0];
     fp_g[i0] += lean_fp[i0];
+    conn_g[i0] += lean_conn[i0];
 }
 
 // ---------------------------------------------------------------- reductions
@@ -1029,7 +1031,7 @@ enum BufId {
     B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFE, B_DEFS, B_DEFC, B_DEFN, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
     B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_GENR,
     // split sweep: hole-pair lists and the clean-cell kernel's slots
-    B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP,
+    B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP, B_LCONN,
     // integral layouts of a system of a batched call
     B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
     // Davidson
@@ -1066,7 +1068,7 @@ struct qp_ctx {
     // batched call; single-system calls use slot 0
     std::vector<std::vector<DevBuf>> slots;
     std::vector<LayoutKey> layout_keys;
-    DevBuf args[3];                // per-launch system descriptors (dense, general, clean-cell)
+    DevBuf args[4];                // per-launch system descriptors (dense, general, clean-cell, split-correction)
     DevBuf defn;                   // per-system count of handed-over batches
     int num_cu = 256;
     size_t lds_per_cu = 163840;
@@ -1346,7 +1348,18 @@ int fast_occ_t(int ns, bool bwd, size_t lds, bool fp)
 // persistent grid: every resident one-wavefront workgroup the CUs can hold
 // the three sweep kernels: the dense kernel, the general kernel on handed-over
 // batches, and the clean-cell kernel of a split sweep
-enum Kind { K_DENSE = 0, K_GENERAL = 1, K_LEAN = 2 };
+enum Kind { K_DENSE = 0, K_GENERAL = 1, K_LEAN = 2, K_CORR = 3 };
+
+template <int NINT>
+int corr_occ_t(int ns, size_t lds, bool fp)
+{
+    switch (ns) {
+    case 1: return corr_occupancy<NINT, 1>(lds, fp);
+    case 2: return corr_occupancy<NINT, 2>(lds, fp);
+    case 3: return corr_occupancy<NINT, 3>(lds, fp);
+    default: return corr_occupancy<NINT, 4>(lds, fp);
+    }
+}
 
 template <int NINT>
 int lean_occ_t(int ns, size_t lds, bool fp)
@@ -1364,6 +1377,7 @@ int kind_occ_t(int kind, int ns, bool bwd, size_t lds, bool fp)
 {
     if (kind == K_DENSE) return fast_occ_t<NINT>(ns, bwd, lds, fp);
     if (kind == K_LEAN) return lean_occ_t<NINT>(ns, lds, fp);
+    if (kind == K_CORR) return corr_occ_t<NINT>(ns, lds, fp);
     return sweep_occ_t<NINT>(ns, bwd, lds);
 }
 
@@ -1420,6 +1434,8 @@ void launch_ns(int kind, const SweepArgs *sys, const int64_t *end, int n_sys, bo
 {
     if (kind == K_LEAN) {
         launch_lean<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
+    } else if (kind == K_CORR) {
+        launch_corr<NINT, NS>(sys, end, n_sys, fp, lds, grid, st);
     } else if (kind == K_DENSE) {
         if (bwd) launch_fast<NINT, NS, true>(sys, end, n_sys, fp, lds, grid, st);
         else launch_fast<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
@@ -1547,6 +1563,7 @@ std::vector<LaunchPlan> plan_launches(qp_ctx *c, int kind, bool bwd, bool fp, co
         const int nvm = n - std::min(run[s].P.nup, run[s].P.ndn);
         if (kind == K_DENSE) lds = fast_lds_bytes(n, nvm, ns, bwd, run[s].a.rscap, run[s].a.cscap);
         else if (kind == K_LEAN) lds = lean_lds_bytes(n, nvm);
+        else if (kind == K_CORR) lds = corr_lds_bytes(n, ns);
         else lds = sweep_lds_bytes(n, ns, bwd);
         LaunchPlan *p = nullptr;
         for (auto &q : plans) if (q.nint == nint && q.ns == ns) p = &q;
@@ -1573,9 +1590,9 @@ int launch_plans(qp_ctx *c, int kind, bool bwd, bool fp, std::vector<LaunchPlan>
     const size_t bytes = args_bytes + sizeof(int64_t) * nsys;
     // the staging area is reused only after a host synchronisation on `st`,
     // which every call performs between its two launch rounds
-    const size_t third = c->host_stage_bytes / 3 / 16 * 16;
-    unsigned char *stage = c->host_stage + kind * third;
-    if (bytes > third) return fail(c, QP_E_ARG, "staging area too small");
+    const size_t quarter = c->host_stage_bytes / 4 / 16 * 16;
+    unsigned char *stage = c->host_stage + kind * quarter;
+    if (bytes > quarter) return fail(c, QP_E_ARG, "staging area too small");
     unsigned char *dev = (unsigned char *)grow(c->args[kind], bytes);
     if (!dev) return fail(c, QP_E_OOM, "device allocation failed (system descriptors)");
     SweepArgs *ha = (SweepArgs *)stage;
@@ -1611,7 +1628,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     c->timed = false;
     if (n_sys == 0) return QP_OK;
     {
-        int rc = host_space(c, std::max<size_t>(3 << 16, 3 * ((sizeof(SweepArgs) + 8) * (size_t)n_sys + 256)), n_sys);
+        int rc = host_space(c, std::max<size_t>(4 << 16, 4 * ((sizeof(SweepArgs) + 8) * (size_t)n_sys + 256)), n_sys);
         if (rc != QP_OK) return rc;
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], st));
@@ -1756,10 +1773,12 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             double *lS = (double *)scratch(c, s, B_LS, sizeof(double) * tot * ns);
             unsigned long long *lcnt = (unsigned long long *)scratch(c, s, B_LCNT, sizeof(unsigned long long) * n_g);
             unsigned long long *lfp = (unsigned long long *)scratch(c, s, B_LFP, sizeof(unsigned long long) * n_g);
-            if (!bits || !kcnt || !koff || !kbs || !kpos || !leps || !lS || !lcnt || !lfp)
+            unsigned long long *lconn = (unsigned long long *)scratch(c, s, B_LCONN, sizeof(unsigned long long) * n_g);
+            if (!bits || !kcnt || !koff || !kbs || !kpos || !leps || !lS || !lcnt || !lfp || !lconn)
                 return fail(c, QP_E_OOM, "device allocation failed (clean-cell lists)");
             HIPCHK(c, hipMemsetAsync(lcnt, 0, sizeof(unsigned long long) * n_g, st));
             HIPCHK(c, hipMemsetAsync(lfp, 0, sizeof(unsigned long long) * n_g, st));
+            HIPCHK(c, hipMemsetAsync(lconn, 0, sizeof(unsigned long long) * n_g, st));
             switch (r.nint) {
             case 1: hipLaunchKernelGGL(pair_bits<1>, dim3(grid_for(nw, 4, 1 << 30)), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, n, nw, bits); break;
             case 2: hipLaunchKernelGGL(pair_bits<2>, dim3(grid_for(nw, 4, 1 << 30)), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, n, nw, bits); break;
@@ -1781,6 +1800,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             a.lean_S = lS;
             a.lean_cnt = lcnt;
             a.lean_fp = lfp;
+            a.lean_conn = lconn;
             r.n_pairs = np;
             litems[s] = tot;
         }
@@ -1797,6 +1817,10 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         // selection candidates have raised the threshold by then
         std::vector<LaunchPlan> lplans = plan_launches(c, K_LEAN, bwd, fp, in, run, litems);
         rc = launch_plans(c, K_LEAN, bwd, fp, lplans, run, st);
+        if (rc != QP_OK) return rc;
+        // then their flagged cells, added to the same batch slots
+        std::vector<LaunchPlan> cplans = plan_launches(c, K_CORR, bwd, fp, in, run, litems);
+        rc = launch_plans(c, K_CORR, bwd, fp, cplans, run, st);
         if (rc != QP_OK) return rc;
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
@@ -1888,8 +1912,9 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
                                bwd ? x.grad_coefs : nullptr, r.dp);
         if (r.swept && r.split)
             hipLaunchKernelGGL(reduce_lean, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.a.lean_eps, r.a.lean_S,
-                               r.a.lean_cnt, r.a.lean_fp, r.n_g, r.n_pairs, ns, r.P.perm, (const int32_t *)r.gen_rank,
-                               x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, bwd ? nullptr : x.eps_gen);
+                               r.a.lean_cnt, r.a.lean_fp, r.a.lean_conn, r.n_g, r.n_pairs, ns, r.P.perm,
+                               (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
+                               bwd ? nullptr : x.eps_gen);
         else if (!r.swept && r.n_g > 0)
             hipLaunchKernelGGL(reduce_empty, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.n_g, ns, r.P.perm,
                                (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,

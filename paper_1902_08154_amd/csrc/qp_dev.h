@@ -363,7 +363,90 @@ struct SweepArgs {
     double *lean_S;           // [n_gen][n_pairs][ns]
     unsigned long long *lean_cnt;  // [n_gen] clean cells counted (atomics)
     unsigned long long *lean_fp;   // [n_gen] fingerprint sums (atomics)
+    unsigned long long *lean_conn; // [n_gen] connections of flagged cells (atomics)
 };
+
+// Split sweep: the cells of the hole-pair batch (holes hc0, hc1 as spin << 8 |
+// orbital) of generator rank g that other determinants touch.  Of the
+// generator's coarse list, the entries J with m = |(I - H) \ J| <= 2 touch
+// the batch: m = 2 entries the cells whose particles are all in J \ I (their
+// rows are flagged: opposite spins the row-spin particle, same spin the
+// larger one), m = 1 entries every cell that has one of J's particles (its
+// row and its column are flagged; same spin, both on each particle).  An m = 0
+// entry touches every cell: then the function returns false and the batch is
+// not split.  rowF and colF are 256-bit masks over virtual indices (row spin,
+// column spin), zeroed by the caller; sVidx maps spin * n + orbital to the
+// orbital's virtual index (0xFFFF when occupied).  One wave; the result is the
+// same on every lane.
+template <class Sys>
+__device__ bool split_flags(const Sys &a, int64_t g, int n, int nup, int ndn, bool os, int rs, int hc0, int hc1,
+                            const uint16_t *sVidx, uint32_t *rowF, uint32_t *colF, int lane)
+{
+    const int64_t cbeg = a.coff[g], cend = a.coff[g + 1];
+    const int nv0 = n - nup, nv1 = n - ndn;
+    bool m0 = false;
+    for (int64_t base = cbeg; base < cend; base += 64) {
+        const int64_t e = base + lane;
+        if (e >= cend) break;
+        const CoarseEnt ce = a.cent[e];
+        int dc = 0, inmask = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int d = ce.D[t];
+            if (d == 0xFFFF) continue;
+            dc++;
+            inmask |= (d == hc0 ? 1 : 0) | (d == hc1 ? 2 : 0);
+        }
+        const int m = dc - __popc(inmask);
+        if (m > 2) continue;
+        if (m == 0) { m0 = true; continue; }
+        int ner = 0, nec = 0, er[4] = {0, 0, 0, 0}, ec[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ecode = ce.E[t];
+            if (ecode == 0xFFFF) continue;
+            const int es = ecode >> 8, ep = ecode & 255;
+            if (ep >= n) continue;
+            const int vi = sVidx[es * n + ep];
+            if (vi >= (es == 0 ? nv0 : nv1)) continue;
+            if (es == rs) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) if (q == ner) er[q] = vi;
+                ner++;
+            } else if (os) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) if (q == nec) ec[q] = vi;
+                nec++;
+            }
+        }
+        if (m == 2) {
+            if (os) {
+                if (nec > 0)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) if (q < ner) atomicOr(&rowF[er[q] >> 5], 1u << (er[q] & 31));
+            } else {
+#pragma unroll
+                for (int q1 = 1; q1 < 4; ++q1)
+#pragma unroll
+                    for (int q0 = 0; q0 < 4; ++q0)
+                        if (q0 < q1 && q1 < ner) {
+                            const int r = er[q0] > er[q1] ? er[q0] : er[q1];
+                            atomicOr(&rowF[r >> 5], 1u << (r & 31));
+                        }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < ner) {
+                    atomicOr(&rowF[er[q] >> 5], 1u << (er[q] & 31));
+                    if (!os) atomicOr(&colF[er[q] >> 5], 1u << (er[q] & 31));
+                }
+                if (os && q < nec) atomicOr(&colF[ec[q] >> 5], 1u << (ec[q] & 31));
+            }
+        }
+    }
+    return __ballot(m0) == 0ull;
+}
 
 // The sweep kernels read each system's SweepArgs from a table in device
 // memory through the constant address space: the table does not change during
@@ -389,6 +472,12 @@ void launch_lean(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool 
 template <int NINT, int NS, bool BWD>
 int lean_occupancy(size_t lds, bool fp);
 size_t lean_lds_bytes(int n, int nvm);
+template <int NINT, int NS>
+void launch_corr(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
+                 hipStream_t st);
+template <int NINT, int NS>
+int corr_occupancy(size_t lds, bool fp);
+size_t corr_lds_bytes(int n, int ns);
 // capacities of the dense kernel's per-batch correction buffers; the clean-cell
 // kernel applies the same limits to decide which batches it takes
 #define QPF_FCAP 32

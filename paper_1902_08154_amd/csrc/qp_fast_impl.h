@@ -206,6 +206,7 @@ inline size_t lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap)
     add(2 * n);                     // occ
     add(2 * n);                     // virt
     add(2 * n);                     // cnt
+    add(4 * 16);                    // split sweep flags
     return b + 16;
 }
 
@@ -260,6 +261,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
         uint8_t *sOcc = carve<uint8_t>(lds, off, 2 * n);
         uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
         uint8_t *sCnt = carve<uint8_t>(lds, off, 2 * n);
+        uint32_t *sSplitF = carve<uint32_t>(lds, off, 16);   // split sweep: row, column flags
 
         double E0[NS], gup[NS], cI[NS], invm[NS];
 #pragma unroll
@@ -350,6 +352,17 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
             const uint8_t *cvirt = sVirt + cs * n;
             const int hrs = type == BT_OS ? (rs == 0 ? h1 : h2) : h1;
             const int hro = type == BT_OS ? (rs == 0 ? h2 : h1) : (type == BT_SS ? h2 : -1);
+
+            // split sweep: a hole-pair batch that no determinant touches in every
+            // cell belongs to the clean-cell and split-correction kernels
+            if (!BWD && a.split && type != BT_SINGLE) {
+                if (lane < 16) sSplitF[lane] = 0u;
+                __syncthreads();
+                const bool taken = split_flags(a, g, n, a.nup, a.ndn, type == BT_OS, rs, hc0, hc1, sVidx, sSplitF,
+                                               sSplitF + 8, lane);
+                __syncthreads();
+                if (taken) continue;
+            }
 
             // particle tables: Fock-diagonal part of H_alpha,alpha and phase
             for (int i = lane; i < nr; i += WAVE) {
@@ -1000,30 +1013,9 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 }
                 plane_flush();
             } else if (type == BT_OS) {
+                if (lane == 0) cnt += (uint32_t)(nr * nc);
                 const double *Jm = a.I.Jm;
-                // split sweep: the clean cells (unflagged row and column) belong
-                // to the clean-cell kernel; this kernel takes the flagged rows,
-                // every column, and the column pass below
-                const bool split = !BWD && a.split;
-                if (split) {
-                    for (int r = 0; r < nr; ++r) {
-                        const PEnt re = sRT[r];
-                        if (!(rfl(re.info) & FR)) continue;
-                        const int pr = re.info & 255;
-                        for (int c0 = 0; c0 < nc; c0 += WAVE) {
-                            const int l = c0 + lane;
-                            if (l < nc) {
-                                const PEnt ce = sCT[l];
-                                const int pcol = ce.info & 255;
-                                cnt++;
-                                post_cell(r, l, blk[pr * n + pcol], re.info ^ ce.info,
-                                          (ce.G + re.G) + Jm[pr * n + pcol], pr, pcol);
-                            }
-                        }
-                    }
-                }
-                if (!split && lane == 0) cnt += (uint32_t)(nr * nc);
-                for (int c0 = 0; !split && c0 < nc; c0 += WAVE) {
+                for (int c0 = 0; c0 < nc; c0 += WAVE) {
                     const int l = c0 + lane;
                     const bool lok = l < nc;
                     const int lc = lok ? l : nc - 1;
@@ -1117,36 +1109,15 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         if (r < nr && !(re.info & FR)) {
                             const int pr = re.info & 255;
                             const double xj = Jm[pr * n + pcol];
-                            if (split) cnt++;
                             post_cell(r, col, blk[pr * n + pcol], re.info ^ ce.info, (ce.G + re.G) + xj, pr, pcol);
                         }
                     }
                 }
             } else if (type == BT_SS) {
+                if (lane == 0) cnt += (uint32_t)(nr * (nr - 1) / 2);
                 const double *JK = a.I.JK;
                 const uint32_t shb = sH ? SGN : 0u;
-                // split sweep: cells (i1, i2) whose second index is flagged, then
-                // the column pass below; the clean cells go to the clean-cell kernel
-                const bool split = !BWD && a.split;
-                if (split) {
-                    for (int i2 = 1; i2 < nr; ++i2) {
-                        const PEnt e2 = sRT[i2];
-                        if (!(rfl(e2.info) & FR)) continue;
-                        const int p2 = e2.info & 255;
-                        for (int j0 = 0; j0 < i2; j0 += WAVE) {
-                            const int i1 = j0 + lane;
-                            if (i1 < i2) {
-                                const PEnt e1 = sRT[i1];
-                                const int p1 = e1.info & 255;
-                                cnt++;
-                                post_cell(i1, i2, blk[p2 * (p2 - 1) / 2 + p1], e1.info ^ e2.info ^ shb,
-                                          ((D0 + e2.G) + e1.G) + JK[p2 * n + p1], p1, p2);
-                            }
-                        }
-                    }
-                }
-                if (!split && lane == 0) cnt += (uint32_t)(nr * (nr - 1) / 2);
-                for (int c0 = 0; !split && c0 < nr; c0 += WAVE) {
+                for (int c0 = 0; c0 < nr; c0 += WAVE) {
                     const int l = c0 + lane;
                     const bool lok = l < nr;
                     if (BWD || lok) {
@@ -1263,7 +1234,6 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                         if (i2 < nr && !(e2.info & FR)) {
                             const int p2 = e2.info & 255;
                             const double xj = JK[p2 * n + p1];
-                            if (split) cnt++;
                             post_cell(ie, i2, blk[p2 * (p2 - 1) / 2 + p1], e1.info ^ e2.info ^ shb,
                                       ((D0 + e2.G) + e1.G) + xj, p1, p2);
                         }

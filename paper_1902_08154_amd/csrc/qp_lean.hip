@@ -255,107 +255,9 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         const int hc0 = (s1 << 8) | h1, hc1 = (s2 << 8) | h2;
 
         // ------------------------------------------------ which cells are clean
-        // The fine filter of the dense kernel: J of the generator's coarse list
-        // with m = |(I - H) \ J| <= 2.  m = 0 (J touches every cell) takes the
-        // batch away from this kernel, so do more entries than the dense
-        // kernel's buffers hold; otherwise m = 2 entries flag the rows of their
-        // cells and m = 1 entries their rows and columns (same spin: both on
-        // each particle), exactly as the dense kernel flags them.
-        bool take = true;
-        {
-            const int64_t cbeg = a.coff[g], cend = a.coff[g + 1];
-            int nfine = 0, nl = 0, nrs = 0, ncs = 0;
-            bool m0 = false;
-            const int nv0 = n - nup, nv1 = n - ndn;
-            for (int64_t base = cbeg; base < cend; base += WAVE) {
-                const int64_t e = base + lane;
-                bool keep = false;
-                int m = 3;
-                CoarseEnt ce;
-                if (e < cend) {
-                    ce = a.cent[e];
-                    int dc = 0, inmask = 0;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int d = ce.D[t];
-                        if (d == 0xFFFF) continue;
-                        dc++;
-                        inmask |= (d == hc0 ? 1 : 0) | (d == hc1 ? 2 : 0);
-                    }
-                    m = dc - __popc(inmask);
-                    keep = m <= 2;
-                }
-                nfine += __popcll(__ballot(keep));
-                int ner = 0, nec = 0, er[4] = {0, 0, 0, 0}, ec[4] = {0, 0, 0, 0};
-                if (keep) {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int ecode = ce.E[t];
-                        if (ecode == 0xFFFF) continue;
-                        const int es = ecode >> 8, ep = ecode & 255;
-                        if (ep >= n) continue;
-                        const int vi = sVidx[es * n + ep];
-                        if (vi >= (es == 0 ? nv0 : nv1)) continue;
-                        if (es == rs) {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) if (q == ner) er[q] = vi;
-                            ner++;
-                        } else if (type == BT_OS) {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) if (q == nec) ec[q] = vi;
-                            nec++;
-                        }
-                    }
-                    if (m == 0) m0 = true;
-                    else if (m == 2) {
-                        if (type == BT_OS) {
-                            nl += ner * nec;
-                            if (nec > 0)
-#pragma unroll
-                                for (int q = 0; q < 4; ++q) if (q < ner) atomicOr(&sRowF[er[q] >> 5], 1u << (er[q] & 31));
-                        } else {
-                            nl += ner * (ner - 1) / 2;
-                            // cells (u, v), u < v, of E's particles: each flags row max(u, v)
-#pragma unroll
-                            for (int q1 = 1; q1 < 4; ++q1)
-#pragma unroll
-                                for (int q0 = 0; q0 < 4; ++q0)
-                                    if (q0 < q1 && q1 < ner) {
-                                        const int r = er[q0] > er[q1] ? er[q0] : er[q1];
-                                        atomicOr(&sRowF[r >> 5], 1u << (r & 31));
-                                    }
-                        }
-                    } else {   // m == 1
-                        if (type == BT_OS) {
-                            nrs += ner;
-                            ncs += nec;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-                                if (q < ner) atomicOr(&sRowF[er[q] >> 5], 1u << (er[q] & 31));
-                                if (q < nec) atomicOr(&sColF[ec[q] >> 5], 1u << (ec[q] & 31));
-                            }
-                        } else {
-                            nrs += ner;
-                            ncs += ner;
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                if (q < ner) {
-                                    atomicOr(&sRowF[er[q] >> 5], 1u << (er[q] & 31));
-                                    atomicOr(&sColF[er[q] >> 5], 1u << (er[q] & 31));
-                                }
-                        }
-                    }
-                }
-            }
-            // wave totals
-            for (int o = 32; o > 0; o >>= 1) {
-                nl += __shfl_xor(nl, o);
-                nrs += __shfl_xor(nrs, o);
-                ncs += __shfl_xor(ncs, o);
-            }
-            const bool any_m0 = __ballot(m0) != 0ull;
-            take = !any_m0 && nfine <= QPF_FCAP && nl <= QPF_L2CAP && nrs <= a.rscap && ncs <= a.cscap;
-        }
+        // the flags of the dense kernel's corrections (split_flags); a batch
+        // with a determinant that touches every cell is not split
+        const bool take = split_flags(a, g, n, nup, ndn, type == BT_OS, rs, hc0, hc1, sVidx, sRowF, sColF, lane);
         __syncthreads();
         if (!take) {
             if (lane < NS) {
@@ -634,6 +536,418 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
     if (total > 0) flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
 }
 
+// ---------------------------------------------------------------------------
+// The split-correction kernel: the flagged cells of the batches the clean-cell
+// kernel split, after it.  Items are the same (hole pair, generator) batches.
+// A flagged cell's numerator is c_I <I|H|alpha> plus c_J <J|H|alpha> of every
+// fine entry J of the generator's coarse list whose particles the cell holds
+// (m = 1: one of them; m = 2: all), each evaluated by the Slater-Condon rules;
+// J earlier in generator order, or J = alpha, bans the cell (alpha belongs to
+// an earlier generator, or is internal).  The batch's sums are added to the
+// slot the clean-cell kernel wrote.  A batch with more fine entries than the
+// LDS list holds is handed to the general kernel (marked in def_bits), which
+// then takes the same flagged cells.
+// ---------------------------------------------------------------------------
+constexpr int FCAPC = 64;   // fine entries a batch may have here
+
+}  // namespace qplean
+
+size_t corr_lds_bytes(int n, int ns)
+{
+    size_t b = 0;
+    auto add = [&](size_t bytes) { b = ((b + 15) & ~(size_t)15) + bytes; };
+    add(2 * 2 * n);                 // sVidx
+    add(2 * n);                     // sVirt
+    add(4 * 16);                    // row and column flags
+    add(4 * qplean::FCAPC);         // fine: J
+    add(4 * qplean::FCAPC);         // fine: E_J's row-spin particles (virtual indices, one per byte)
+    add(4 * qplean::FCAPC);         // fine: E_J's column-spin particles
+    add(4 * qplean::FCAPC);         // fine: m | earlier << 2 | ner << 4 | nec << 8
+    add(8 * qplean::FCAPC * ns);    // fine: c_Jk
+    return b + 16;
+}
+
+namespace qplean {
+
+template <int NINT, int NS, bool FP>
+__global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict__ sys,
+                                                   const int64_t *__restrict__ item_end, int n_sys)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int lane = threadIdx.x;
+    const int64_t total = item_end[n_sys - 1];
+    int sid = 0;
+    int64_t ibase = 0;
+    int K = -1;
+    int64_t kend = 0;
+    double mind = __builtin_inf();
+    auto flush_min = [&](unsigned long long *dst) {
+        double m = mind;
+        for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o));
+        if (m >= 1e299) m = __builtin_inf();
+        const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+        if (lane == 0 && mb < __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMin(dst, mb);
+        mind = __builtin_inf();
+    };
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        if (it >= item_end[sid]) {
+            flush_min(((ConstSys *)sys)[sid].min_delta_bits);
+            while (it >= item_end[sid]) ibase = item_end[sid++];
+            K = -1;
+        }
+        ConstSys &a = ((ConstSys *)sys)[sid];
+        const int64_t item = it - ibase;
+        if (item >= a.kl_off[a.n_keys]) continue;
+        if (K < 0 || item >= kend) {
+            if (K < 0 || item >= kend + (int64_t)WAVE * 1024) {
+                int lo = 0, hi = a.n_keys;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.kl_off[mid] <= item) lo = mid; else hi = mid;
+                }
+                K = lo;
+            }
+            while (a.kl_off[K + 1] <= item) ++K;
+            kend = a.kl_off[K + 1];
+        }
+        const int n = a.n;
+        const int64_t n2 = (int64_t)n * n;
+        const int P2 = n * (n - 1) / 2;
+        const int nup = a.nup, ndn = a.ndn;
+        const bool want_sel = a.n_select > 0;
+
+        unsigned off = 0;
+        uint16_t *sVidx = carve<uint16_t>(lds, off, 2 * n);
+        uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
+        uint32_t *sF = carve<uint32_t>(lds, off, 16);
+        int32_t *sFJ = carve<int32_t>(lds, off, FCAPC);
+        uint32_t *sFer = carve<uint32_t>(lds, off, FCAPC);
+        uint32_t *sFec = carve<uint32_t>(lds, off, FCAPC);
+        uint32_t *sFm = carve<uint32_t>(lds, off, FCAPC);
+        double *sFC = carve<double>(lds, off, FCAPC * NS);
+
+        const int64_t pos = a.kl_pos[item];
+        if (pos < 0 || pos >= a.n_gen) continue;
+        const int64_t g = a.gen_list ? (int64_t)a.gen_list[pos] : pos;
+        const int det = a.perm[g];
+        uint64_t Ib[2 * NINT];
+#pragma unroll
+        for (int w = 0; w < 2 * NINT; ++w) Ib[w] = a.dets[(int64_t)det * 2 * NINT + w];
+
+        int type, s1, h1, s2, h2;
+        if (K < n * n) {
+            type = BT_OS; s1 = 0; h1 = K / n; s2 = 1; h2 = K - h1 * n;
+        } else {
+            const int t = K - n * n;
+            const int s = t >= P2 ? 1 : 0;
+            const int u = t - s * P2;
+            int b = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)u)) * 0.5f);
+            while (b * (b - 1) / 2 > u) --b;
+            while ((b + 1) * b / 2 <= u) ++b;
+            type = BT_SS; s1 = s2 = s; h1 = u - b * (b - 1) / 2; h2 = b;
+        }
+        const int i1h = (s1 ? nup : 0) + occ_below<NINT>(Ib, s1, h1);
+        const int i2h = (s2 ? nup : 0) + occ_below<NINT>(Ib, s2, h2);
+        const int pb = i2h * (i2h - 1) / 2 + i1h;
+        if (pb >= a.n_pairs) continue;
+        const int64_t slot = pos * a.n_pairs + pb;
+
+        for (int x = lane; x < 2 * n; x += WAVE) {
+            const int s = x >= n ? 1 : 0, p = x - s * n;
+            const int c = occ_below<NINT>(Ib, s, p);
+            if (occ_bit<NINT>(Ib, s, p)) sVidx[x] = 0xFFFF;
+            else { sVirt[s * n + p - c] = (uint8_t)p; sVidx[x] = (uint16_t)(p - c); }
+        }
+        if (lane < 16) sF[lane] = 0u;
+        __syncthreads();
+
+        const bool os = type == BT_OS;
+        int rs, cs;
+        if (os) { rs = h1 <= h2 ? 0 : 1; cs = 1 - rs; }
+        else { rs = cs = s1; }
+        const int hc0 = (s1 << 8) | h1, hc1 = (s2 << 8) | h2;
+        const bool take = split_flags(a, g, n, nup, ndn, os, rs, hc0, hc1, sVidx, sF, sF + 8, lane);
+        __syncthreads();
+        if (!take) continue;
+        bool anyf = false;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) anyf |= sF[w] != 0u;
+        if (!anyf) continue;
+
+        // the fine entries (m = 1 or 2; a taken batch has no m = 0 entry)
+        const int nv0 = n - nup, nv1 = n - ndn;
+        int nfine = 0;
+        {
+            const int64_t cbeg = a.coff[g], cend = a.coff[g + 1];
+            for (int64_t base = cbeg; base < cend; base += WAVE) {
+                const int64_t e = base + lane;
+                bool keep = false;
+                CoarseEnt ce;
+                int m = 3;
+                if (e < cend) {
+                    ce = a.cent[e];
+                    int dc = 0, inmask = 0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int d = ce.D[t];
+                        if (d == 0xFFFF) continue;
+                        dc++;
+                        inmask |= (d == hc0 ? 1 : 0) | (d == hc1 ? 2 : 0);
+                    }
+                    m = dc - __popc(inmask);
+                    keep = m <= 2;
+                }
+                const uint64_t mk = __ballot(keep);
+                const int at = nfine + __popcll(mk & ((1ull << lane) - 1ull));
+                if (keep && at < FCAPC) {
+                    uint32_t er = 0u, ec = 0u;
+                    int ner = 0, nec = 0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int ecode = ce.E[t];
+                        if (ecode == 0xFFFF) continue;
+                        const int es = ecode >> 8, ep = ecode & 255;
+                        if (ep >= n) continue;
+                        const int vi = sVidx[es * n + ep];
+                        if (vi >= (es == 0 ? nv0 : nv1)) continue;
+                        if (es == rs) { er |= (uint32_t)vi << (8 * ner); ner++; }
+                        else if (os) { ec |= (uint32_t)vi << (8 * nec); nec++; }
+                    }
+                    sFJ[at] = ce.j;
+                    sFer[at] = er;
+                    sFec[at] = ec;
+                    sFm[at] = (uint32_t)m | ((uint32_t)(ce.flags & 1) << 2) | ((uint32_t)ner << 4) | ((uint32_t)nec << 8);
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) sFC[at * NS + k] = a.coefs[(int64_t)k * a.n_det + ce.j];
+                }
+                nfine += __popcll(mk);
+            }
+        }
+        if (nfine > FCAPC) {
+            // the general kernel takes this batch's flagged cells
+            if (lane == 0) {
+                const int b = a.nel + pb;
+                atomicOr(&a.def_bits[g * a.nbw + (b >> 5)], 1u << (b & 31));
+            }
+            continue;
+        }
+        __syncthreads();
+
+        const double *Fg = a.F + g * 2 * n;
+        const double HII = a.HII[g];
+        const uint8_t *rvirt = sVirt + rs * n, *cvirt = sVirt + cs * n;
+        const int nr = n - (rs ? ndn : nup), nc = n - (cs ? ndn : nup);
+        // holes of the row and column spins (opposite spins), or both holes
+        const int hu = h1, hd = h2;   // opposite spins: h1 up, h2 down
+        const int hrs = os ? (rs == 0 ? hu : hd) : h1, hro = os ? (rs == 0 ? hd : hu) : h2;
+        const int hcs = os ? hro : h1, hco = os ? hrs : h2;
+        const double *blk = os ? a.I.X + (h1 <= h2 ? qtri(h1, h2) : qtri(h2, h1)) * n2
+                               : a.I.Y + qtris(h1, h2) * (int64_t)P2;
+        const double D0 = os ? HII - Fg[h1] - Fg[n + h2] + a.I.Jm[h1 * n + h2]
+                             : HII - Fg[s1 * n + h1] - Fg[s1 * n + h2] + a.I.JK[h1 * n + h2];
+        double E0[NS], cI[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            E0[k] = a.E0[k];
+            cI[k] = a.coefs[(int64_t)k * a.n_det + det];
+        }
+        const uint64_t tau_key = want_sel ? bin_edge(__atomic_load_n(a.tau_bin, __ATOMIC_RELAXED)) : ~0ull;
+        double esum[NS], ssum[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) { esum[k] = 0.0; ssum[k] = 0.0; }
+        uint32_t cnt = 0, conn = 0;
+        uint64_t fpsum = 0;
+        bool appended = false;
+        auto has4 = [](uint32_t v, int nv, int x) {
+            bool r = false;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) r |= (t < nv) && ((int)((v >> (8 * t)) & 255u) == x);
+            return r;
+        };
+        auto fl = [&](int which, int i) -> bool { return (sF[which * 8 + (i >> 5)] >> (i & 31)) & 1u; };
+
+        // lines: flagged rows (opposite spins: every column; same spin: the cells
+        // below the flagged second index), then flagged columns (opposite spins:
+        // the unflagged rows; same spin: the cells above the flagged first index
+        // whose second index is unflagged)
+        const int nlin = os ? nr + nc : 2 * nr;
+        for (int li = 0; li < nlin; ++li) {
+            const bool colline = li >= nr;
+            const int idx = colline ? li - nr : li;
+            if (!fl(colline ? 1 : 0, idx)) continue;
+            const int len = os ? (colline ? nr : nc) : (colline ? nr - 1 - idx : idx);
+            for (int p0 = 0; p0 < len; p0 += WAVE) {
+                const int p = p0 + lane;
+                int ia, ib;   // opposite spins: row, column; same spin: first < second
+                if (os) { ia = colline ? p : idx; ib = colline ? idx : p; }
+                else { ia = colline ? idx : p; ib = colline ? idx + 1 + p : idx; }
+                const bool act = p < len && !(colline && fl(0, os ? ia : ib));
+                bool live = act;
+                double A[NS], D = DEAD_D;
+                int pa = 0, pbb = 0;
+#pragma unroll
+                for (int k = 0; k < NS; ++k) A[k] = 0.0;
+                uint32_t nco = 0;
+                if (act) {
+                    pa = rvirt[ia];
+                    pbb = os ? cvirt[ib] : rvirt[ib];
+                    double x, Ga, Gb;
+                    int sg;
+                    if (os) {
+                        // pa: particle of the row spin, pbb: of the column spin
+                        x = blk[(int64_t)pa * n + pbb];
+                        Ga = Fg[rs * n + pa] - a.I.JK[hrs * n + pa];
+                        Ga -= a.I.Jm[hro * n + pa];
+                        Gb = D0 + Fg[cs * n + pbb] - a.I.JK[hcs * n + pbb] - a.I.Jm[hco * n + pbb];
+                        D = Gb + (Ga + a.I.Jm[pa * n + pbb]);
+                        sg = between_parity<NINT>(Ib, rs, hrs, pa) ^ between_parity<NINT>(Ib, cs, hcs, pbb);
+                    } else {
+                        // pa < pbb, holes h1 < h2 of spin s1
+                        x = blk[(int64_t)pbb * (pbb - 1) / 2 + pa];
+                        Ga = Fg[rs * n + pa] - a.I.JK[h1 * n + pa];
+                        Ga -= a.I.JK[h2 * n + pa];
+                        Gb = Fg[rs * n + pbb] - a.I.JK[h1 * n + pbb];
+                        Gb -= a.I.JK[h2 * n + pbb];
+                        D = ((D0 + Gb) + Ga) + a.I.JK[pbb * n + pa];
+                        // h1 -> pa, then h2 -> pbb on the intermediate determinant
+                        const int lo = h2 < pbb ? h2 : pbb, hi = h2 < pbb ? pbb : h2;
+                        sg = between_parity<NINT>(Ib, s1, h1, pa) ^ between_parity<NINT>(Ib, s1, h2, pbb) ^
+                             (int)(lo < h1 && h1 < hi) ^ (int)(lo < pa && pa < hi);
+                    }
+                    const double Hv = sg ? -x : x;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
+                    for (int f = 0; f < nfine; ++f) {
+                        const uint32_t fm = sFm[f];
+                        const int m = fm & 3, ner = (fm >> 4) & 15, nec = (fm >> 8) & 15;
+                        const uint32_t er = sFer[f];
+                        const bool inA = has4(er, ner, ia);
+                        const bool inB = os ? has4(sFec[f], nec, ib) : has4(er, ner, ib);
+                        const bool touch = m == 1 ? (inA || inB) : (inA && inB);
+                        if (!touch || !live) continue;
+                        if ((fm >> 2) & 1u) { live = false; continue; }
+                        uint64_t al[2 * NINT], jb[2 * NINT];
+                        const uint64_t *Jp = a.dets + (int64_t)sFJ[f] * 2 * NINT;
+#pragma unroll
+                        for (int w = 0; w < 2 * NINT; ++w) {
+                            al[w] = alpha_word<NINT>(Ib, w, hc0, hc1, pa, rs, pbb, cs);
+                            jb[w] = Jp[w];
+                        }
+                        int deg;
+                        const double v = sc_offdiag<NINT>(a.I, al, jb, &deg, nullptr);
+                        if (deg == 0) { live = false; continue; }
+                        if (deg > 2) continue;
+                        nco++;
+#pragma unroll
+                        for (int k = 0; k < NS; ++k) A[k] = fma(sFC[f * NS + k], v, A[k]);
+                    }
+                }
+                double ek[NS];
+                double tsel = 0.0;
+                if (live) {
+                    cnt++;
+                    conn += nco;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) {
+                        const double delta = E0[k] - D;
+                        const double rc = rcp1(delta);
+                        const double e = (A[k] * A[k]) * rc;
+                        ek[k] = e;
+                        esum[k] += e;
+                        ssum[k] = fma(e, rc, ssum[k]);
+                        mind = min_abs(mind, delta);
+                        tsel += e / a.maxc2[k];
+                    }
+                    if (FP) {
+                        uint64_t al[2 * NINT];
+#pragma unroll
+                        for (int w = 0; w < 2 * NINT; ++w) al[w] = alpha_word<NINT>(Ib, w, hc0, hc1, pa, rs, pbb, cs);
+                        fpsum += det_fold<NINT>(al);
+                    }
+                }
+                const uint64_t key = (uint64_t)__double_as_longlong(fabs(tsel));
+                const bool cand = want_sel && live && key >= tau_key;
+                const uint64_t mask = __ballot(cand);
+                if (mask) {
+                    const int leader = ctz64(mask);
+                    unsigned long long bse = 0;
+                    if (lane == leader) bse = atomicAdd(a.cand_count, (unsigned long long)__popcll(mask));
+                    bse = __shfl(bse, leader);
+                    appended = true;
+                    if (cand) {
+                        const unsigned long long sc = bse + __popcll(mask & ((1ull << lane) - 1ull));
+                        atomicAdd(&a.hist[key_bin(key)], 1u);
+                        if ((int64_t)sc < a.cand_cap) {
+                            Cand *cd = a.cand + sc;
+                            const int up = os ? (rs == 0 ? pa : pbb) : pa;
+                            const int dn = os ? (rs == 0 ? pbb : pa) : pbb;
+                            cd->key = key;
+                            cd->code = pack_code(type, s1, h1, h2, up, dn);
+                            cd->g = (uint32_t)g;
+                            cd->pad = 0;
+#pragma unroll
+                            for (int k = 0; k < QPD_MAX_STATES; ++k) cd->e[k] = k < NS ? ek[k] : 0.0;
+                        } else {
+                            atomicOr(a.overflow, 1ull);
+                        }
+                    }
+                }
+            }
+        }
+
+        // add to the clean-cell kernel's slot (it ran before: one writer at a time)
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const double es = wsum(esum[k]), ss = wsum(ssum[k]);
+            if (lane == 0) {
+                a.lean_eps[slot * NS + k] += es;
+                a.lean_S[slot * NS + k] += ss;
+            }
+        }
+        uint32_t ct = cnt, cn = conn;
+        uint64_t ff = fpsum;
+        for (int o = 32; o > 0; o >>= 1) {
+            ct += __shfl_xor(ct, o);
+            cn += __shfl_xor(cn, o);
+            if (FP) ff += __shfl_xor(ff, o);
+        }
+        if (lane == 0) {
+            if (ct) atomicAdd(&a.lean_cnt[pos], (unsigned long long)ct);
+            if (cn) atomicAdd(&a.lean_conn[pos], (unsigned long long)cn);
+            if (FP && ff) atomicAdd(&a.lean_fp[pos], (unsigned long long)ff);
+        }
+        if (want_sel && __ballot(appended)) {
+            constexpr int PER = QP_HIST_BINS / WAVE;
+            const unsigned int *hb = a.hist + lane * PER;
+            uint32_t tot = 0;
+#pragma unroll 1
+            for (int t = 0; t < PER; ++t) tot += __atomic_load_n(hb + t, __ATOMIC_RELAXED);
+            uint32_t incl = tot;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const uint32_t v = __shfl_down(incl, o);
+                if (lane + o < WAVE) incl += v;
+            }
+            asm volatile("" ::: "memory");
+            uint64_t cum = incl - tot;
+            int best = -1;
+            if (cum < (uint64_t)a.n_select && cum + tot >= (uint64_t)a.n_select) {
+#pragma unroll 1
+                for (int t = PER - 1; t >= 0; --t) {
+                    cum += __atomic_load_n(hb + t, __ATOMIC_RELAXED);
+                    if (cum >= (uint64_t)a.n_select) { best = lane * PER + t; break; }
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const int ob = __shfl_xor(best, o);
+                best = ob > best ? ob : best;
+            }
+            if (lane == 0 && best > 0) atomicMax(a.tau_bin, best);
+        }
+        __syncthreads();
+    }
+    if (total > 0) flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
+}
+
 }  // namespace qplean
 
 template <int NINT, int NS, bool BWD>
@@ -660,10 +974,36 @@ int lean_occupancy(size_t lds, bool fp)
     return blocks > 0 ? blocks : 1;
 }
 
+template <int NINT, int NS>
+void launch_corr(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
+                 hipStream_t st)
+{
+    if (fp)
+        hipLaunchKernelGGL((qplean::corr_kernel<NINT, NS, true>), dim3(grid), dim3(qplean::WAVE), lds, st, sys,
+                           item_end, n_sys);
+    else
+        hipLaunchKernelGGL((qplean::corr_kernel<NINT, NS, false>), dim3(grid), dim3(qplean::WAVE), lds, st, sys,
+                           item_end, n_sys);
+}
+
+template <int NINT, int NS>
+int corr_occupancy(size_t lds, bool fp)
+{
+    int blocks = 0;
+    const hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &blocks, qplean::corr_kernel<NINT, NS, true>, qplean::WAVE, lds)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &blocks, qplean::corr_kernel<NINT, NS, false>, qplean::WAVE, lds);
+    if (e != hipSuccess) return 8;
+    return blocks > 0 ? blocks : 1;
+}
+
 #define QPL_INST(NI, NS)                                                                                        \
     template void launch_lean<NI, NS, false>(const SweepArgs *, const int64_t *, int, bool, size_t, int,         \
                                              hipStream_t);                                                       \
-    template int lean_occupancy<NI, NS, false>(size_t, bool);
+    template int lean_occupancy<NI, NS, false>(size_t, bool);                                                   \
+    template void launch_corr<NI, NS>(const SweepArgs *, const int64_t *, int, bool, size_t, int, hipStream_t); \
+    template int corr_occupancy<NI, NS>(size_t, bool);
 
 QPL_INST(1, 1) QPL_INST(1, 2) QPL_INST(1, 3) QPL_INST(1, 4)
 QPL_INST(2, 1) QPL_INST(2, 2) QPL_INST(2, 3) QPL_INST(2, 4)

@@ -165,6 +165,7 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
         uint8_t *sCnt = carve<uint8_t>(lds_raw, lo_, 2 * n);
         uint8_t *sRS = carve<uint8_t>(lds_raw, lo_, QPD_MAX_ORB);          // row vector: phase bit
         uint64_t *sRowBits = carve<uint64_t>(lds_raw, lo_, 4);             // rows holding m = 2 cells
+        uint32_t *sSplit = carve<uint32_t>(lds_raw, lo_, 16);              // split sweep: row, column flags
 
         double E0[NS], gup[NS], cI[NS];
 #pragma unroll
@@ -269,6 +270,20 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
             // same-spin and other-spin hole of the row spin
             const int hrs = B.type == BT_OS ? (B.rs == 0 ? B.h1 : B.h2) : B.h1;
             const int hro = B.type == BT_OS ? (B.rs == 0 ? B.h2 : B.h1) : (B.type == BT_SS ? B.h2 : -1);
+
+            // split sweep: a hole-pair batch handed over by the split-correction
+            // kernel (more fine entries than it holds) has its clean cells taken by
+            // the clean-cell kernel; this kernel then keeps the flagged rows and
+            // columns only
+            bool skipc = false;
+            if (a.split && B.type != BT_SINGLE) {
+                if (lane < 16) sSplit[lane] = 0u;
+                __syncthreads();
+                skipc = split_flags(a, g, n, a.nup, a.ndn, B.type == BT_OS, B.rs, hc0, hc1, sVidx, sSplit,
+                                    sSplit + 8, lane);
+                __syncthreads();
+            }
+            auto flagged = [&](const uint32_t *m, int i) -> bool { return (m[i >> 5] >> (i & 31)) & 1u; };
 
             // row vector: phase bit and diagonal offset per row-spin particle
             for (int i = lane; i < B.nr; i += WAVE) {
@@ -467,6 +482,7 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
                     if (B.type == BT_OS) {
                         i1 = r; i2 = l;
                         pa = rvirt[r]; pb = pcol;
+                        if (skipc) act = act && (flagged(sSplit, r) || flagged(sSplit + 8, l));
                         if (act) {
                             const double x = B.blk[(int64_t)pa * n + pb];
                             const double jj = a.I.Jm[(int64_t)pa * n + pb];
@@ -478,6 +494,7 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
                         i1 = partA ? l : l - r;
                         i2 = partA ? r : B.nr - r;
                         act = act && (partA || (B.nr - r > r));
+                        if (skipc) act = act && (flagged(sSplit, i2) || flagged(sSplit + 8, i1));
                         pa = rvirt[act ? i1 : 0]; pb = rvirt[act ? i2 : 0]; sb = B.rs;
                         if (act) {
                             const double x = B.blk[qtris(pa, pb)];
@@ -494,6 +511,8 @@ __global__ __launch_bounds__(WAVE) void sweep_kernel(const SweepArgs *__restrict
                             D = B.D0 + sRG[l];
                         }
                     }
+                    // split sweep: a row with no flagged cell has nothing here
+                    if (skipc && __ballot(act) == 0ull) continue;
                     double A[NS];
 #pragma unroll
                     for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hval;
@@ -861,7 +880,7 @@ size_t sweep_lds_bytes(int n, int ns, bool bwd)
     add(8 * 2 * n); add(8 * QPD_MAX_ORB); add(8 * CSCAP * QPD_MAX_ORB); add(8 * FCAP * ns); add(8 * L2CAP);
     add(8 * (bwd ? FCAP * ns : 1)); add(8 * (bwd ? n : 1)); add(8 * 2 * QPD_MAX_NINT); add(sizeof(FineE) * FCAP);
     add(4 * L2CAP); add(4 * CSCAP); add(ICAP); add(2 * 2 * n); add(2 * QPD_MAX_ORB); add(2 * QPD_MAX_ORB); add(2 * n);
-    add(QPD_MAX_ORB); add(8 * 4);
+    add(QPD_MAX_ORB); add(8 * 4); add(4 * 16);
     return b + 16;
 }
 
