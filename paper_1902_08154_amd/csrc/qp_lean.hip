@@ -28,6 +28,8 @@
 // per-generator reduction adds them in a fixed order.
 #include "qp_dev.h"
 
+#include <type_traits>
+
 namespace qplean {
 
 constexpr int WAVE = 64;
@@ -95,13 +97,29 @@ __device__ __forceinline__ int occ_below(const uint64_t *d, int s, int p)
     return c;
 }
 
+// The items of a launch in XCD-major blocks: the workgroups that the hardware
+// places on one XCD (block index mod 8) walk one contiguous eighth of the item
+// range, so that the items sharing a hole pair, which are consecutive, meet in
+// that XCD's L2 instead of every XCD's.
+__device__ __forceinline__ void xcd_items(int64_t total, int64_t &first, int64_t &end, int64_t &step)
+{
+    const int nx = (gridDim.x % 8u) == 0u ? 8 : 1;
+    const int64_t per = (total + nx - 1) / nx;
+    const int64_t lo = (int64_t)(blockIdx.x % nx) * per;
+    end = lo + per < total ? lo + per : total;
+    first = lo + blockIdx.x / nx;
+    step = gridDim.x / nx;
+}
+
 __device__ __forceinline__ bool bit_of(const uint32_t *m, int i) { return (m[i >> 5] >> (i & 31)) & 1u; }
 
-// a clean row: the row part of H_alpha,alpha, and orbital | virtual index << 8
+// a clean row: the row part of H_alpha,alpha and the byte offsets of the row
+// in the integral block and in the pair-term matrix (its orbital and virtual
+// index are kept apart, for the few places that need them)
 struct __align__(16) RowE {
     double G;
-    uint32_t info;
-    uint32_t pad;
+    uint32_t xo;
+    uint32_t jo;
 };
 
 // an FP64 load through a buffer resource: per-lane byte offset, scalar offset
@@ -124,6 +142,7 @@ size_t lean_lds_bytes(int n, int nvm)
     add(4 * 8);         // row flags
     add(4 * 8);         // column flags
     add(16 * nvm);      // clean rows
+    add(4 * nvm);       // their orbital and virtual index
     add(4 * qplean::CL_CAP);   // cells passing the selection pretest
     return b + 16;
 }
@@ -132,7 +151,7 @@ namespace qplean {
 
 // waves per SIMD the register allocation aims for
 template <int NINT, int NS, bool BWD, bool FP>
-constexpr int lean_waves() { return FP || NS == 4 ? 3 : (NS == 1 ? 5 : 4); }
+constexpr int lean_waves() { return FP && NS == 4 && NINT >= 3 ? 2 : (FP || NS == 4 ? 3 : (NS == 1 ? 5 : 4)); }
 
 template <int NINT, int NS, bool BWD, bool FP>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(lean_waves<NINT, NS, BWD, FP>(), 8)))
@@ -157,7 +176,9 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         if (lane == 0 && mb < __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMin(dst, mb);
         mind = __builtin_inf();
     };
-    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    int64_t it0, iend, istep;
+    xcd_items(total, it0, iend, istep);
+    for (int64_t it = it0; it < iend; it += istep) {
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
             while (it >= item_end[sid]) ibase = item_end[sid++];
@@ -194,6 +215,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         uint32_t *sRowF = carve<uint32_t>(lds, off, 8);
         uint32_t *sColF = carve<uint32_t>(lds, off, 8);
         RowE *sRow = carve<RowE>(lds, off, nvm);
+        uint32_t *sRi = carve<uint32_t>(lds, off, nvm);
         uint32_t *sCl = carve<uint32_t>(lds, off, CL_CAP);
 
         const int64_t pos = a.kl_pos[item];                    // generator position in the call
@@ -283,9 +305,10 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 // both kernels round every diagonal alike: opposite spins
                 // Gcol + (Grow + pair), same spin ((D0 + Gsecond) + Gfirst) + pair
                 re.G = type == BT_OS ? gv : D0 + gv;
-                re.info = (uint32_t)(p | (r << 8));
-                re.pad = 0u;
+                re.xo = (uint32_t)(type == BT_OS ? p * n : p * (p - 1) / 2) * 8u;
+                re.jo = (uint32_t)(p * n) * 8u;
                 sRow[at] = re;
+                sRi[at] = (uint32_t)(p | (r << 8));
             }
             nrow += __popcll(mk);
         }
@@ -317,7 +340,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         };
         // the energy terms of one cell; true if its selection value passes the
         // running threshold's lower bound (the exact test comes later)
-        auto cell = [&](double x, double D, bool live, int pa, int pb) -> bool {
+        auto cell = [&](double x, double D, bool live, int pa, int pb, double thr) -> bool {
             const double x2 = x * x;
             double tsel = 0.0;
 #pragma unroll
@@ -331,7 +354,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 tsel = k == 0 ? cw[0] * t : fma(cw[k], t, tsel);
             }
             if (FP && live) fpsum += fold(pa, pb);
-            return fabs(tsel) >= tau_val;
+            return fabs(tsel) >= thr;
         };
 
         // The cell loop.  Lanes run over a chunk of 64 columns (virtual indices
@@ -339,20 +362,22 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         // over the clean rows (same spin: the second particle, above the
         // chunk's first column).  A lane past the last column or on a flagged
         // column has no cell (okc false, diagonal DEAD_D).  Same spin, rows
-        // inside the chunk's span (r < dlim) hold cells only for the lanes
-        // below them.  The loads go through buffer resources (block, pair-term
-        // matrix): the row offset is a scalar, the lane's column offset a
-        // per-chunk constant; a row's loads are issued one row ahead, its
-        // table entry two rows ahead.  Cells whose selection value passes the
-        // threshold's lower bound are listed in LDS as (row, lane) and
-        // appended after the loop, which keeps the loop's registers few.
+        // inside the chunk's span hold cells only for the lanes below them and
+        // take a simple loop of their own; every other row, a cell per active
+        // lane, takes the main loop.  Loads go through buffer resources (block,
+        // pair-term matrix): the row offset is a scalar, the lane's column
+        // offset a per-chunk constant.  The main loop holds two rows in two
+        // register sets that it refills in turn, one row ahead, and each row's
+        // table entry one row before its loads.  Cells whose selection value
+        // passes the threshold's lower bound are listed in LDS as (row, lane)
+        // and appended after the rows (flush), which keeps the loop's registers
+        // few; a list about to fill ends the loop early and restarts it.
         const bool os = type == BT_OS;
         const uint32_t xbytes = (uint32_t)((os ? n2 : (int64_t)P2) * 8);
         const __amdgpu_buffer_rsrc_t rX = __builtin_amdgcn_make_buffer_rsrc((void *)blk, (short)0, xbytes, 0x00020000);
         const __amdgpu_buffer_rsrc_t rJ =
             __builtin_amdgcn_make_buffer_rsrc((void *)Jp, (short)0, (uint32_t)(n2 * 8), 0x00020000);
         const double *Jco = os ? a.I.Jm : a.I.JK;
-        auto xoff = [&](int pr) -> uint32_t { return (uint32_t)(os ? pr * n : pr * (pr - 1) / 2) * 8u; };
         auto col_G = [&](int pc) -> double {
             return os ? D0 + Fg[cs * n + pc] - a.I.JK[hcs * n + pc] - Jco[hco * n + pc]
                       : Fg[cs * n + pc] - a.I.JK[hcs * n + pc] - Jco[hco * n + pc];
@@ -360,14 +385,127 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         auto diag = [&](double Gc, double Grow, double j) -> double {
             return os ? Gc + (Grow + j) : (Grow + Gc) + j;
         };
-        int td = 0;
+        // the listed cells of chunk c0, recomputed with the loop's arithmetic:
+        // the exact key test and the append
+        auto flush = [&](int c0, uint32_t ncand) {
+            __syncthreads();
+            for (uint32_t i0 = 0; i0 < ncand; i0 += WAVE) {
+                const uint32_t i = i0 + lane;
+                bool cand = false;
+                uint64_t key = 0;
+                double ek[NS];
+                int pa = 0, pb = 0;
+                if (i < ncand) {
+                    const uint32_t en = sCl[i];
+                    const int tt = (int)(en & 0xFFFF), cl = c0 + (int)(en >> 16);
+                    const RowE re = sRow[tt];
+                    const int pr = (int)(sRi[tt] & 255u);
+                    const int pcl = cvirt[cl];
+                    const uint32_t ol = (uint32_t)pcl * 8u;
+                    const double x = bload(rX, ol + re.xo, 0u), j = bload(rJ, ol + re.jo, 0u);
+                    const double D = diag(col_G(pcl), re.G, j);
+                    const double x2 = x * x;
+                    double tsel = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) {
+                        const double rc = rcp1(E0[k] - D);
+                        const double tk = x2 * rc;
+                        ek[k] = cc[k] * tk;
+                        tsel = k == 0 ? cw[0] * tk : fma(cw[k], tk, tsel);
+                    }
+                    key = (uint64_t)__double_as_longlong(fabs(tsel));
+                    cand = key >= tau_key;
+                    pa = os ? pr : pcl;
+                    pb = os ? pcl : pr;
+                }
+                const uint64_t mask = __ballot(cand);
+                if (!mask) continue;
+                const int leader = ctz64(mask);
+                unsigned long long bse = 0;
+                if (lane == leader) bse = atomicAdd(a.cand_count, (unsigned long long)__popcll(mask));
+                bse = __shfl(bse, leader);
+                appended = true;
+                if (cand) {
+                    const unsigned long long sc = bse + __popcll(mask & ((1ull << lane) - 1ull));
+                    atomicAdd(&a.hist[key_bin(key)], 1u);
+                    if ((int64_t)sc < a.cand_cap) {
+                        Cand *cd = a.cand + sc;
+                        const int up = os ? (rs == 0 ? pa : pb) : pa;
+                        const int dn = os ? (rs == 0 ? pb : pa) : pb;
+                        cd->key = key;
+                        cd->code = pack_code(type, s1, h1, h2, up, dn);
+                        cd->g = (uint32_t)g;
+                        cd->pad = 0;
+#pragma unroll
+                        for (int k = 0; k < QPD_MAX_STATES; ++k) cd->e[k] = k < NS ? ek[k] : 0.0;
+                    } else {
+                        atomicOr(a.overflow, 1ull);
+                    }
+                }
+            }
+            __syncthreads();
+        };
+        // list the lanes of row t whose cell passed the pretest
+        auto note = [&](bool cnd, int t, uint32_t &ncand) {
+            const uint64_t mk = __builtin_amdgcn_ballot_w64(cnd);
+            if (mk) {
+                if (cnd) sCl[ncand + __popcll(mk & ((1ull << lane) - 1ull))] = (uint32_t)t | ((uint32_t)lane << 16);
+                ncand += (uint32_t)__popcll(mk);
+            }
+        };
+        // the main loop over rows [tb, te), specialised on the batch type
+        auto main_rows = [&](auto OSC, int c0, int tb, int te, double Gcl, uint32_t off8, bool okc, int pc) {
+            constexpr bool OS_ = decltype(OSC)::value;
+            // a lane with no cell takes an infinite threshold: its value, x^2
+            // times about 1e-300, never reaches it
+            const double thr = okc ? tau_val : __builtin_inf();
+            auto load = [&](const RowE &e, double &G, double &x, double &j) {
+                G = e.G;
+                x = bload(rX, off8, rfl(e.xo));
+                j = bload(rJ, off8, rfl(e.jo));
+            };
+            // the row's orbital, for the fingerprint only
+            auto orb = [&](int t) -> int { return FP ? (int)(rfl(sRi[t]) & 255u) : 0; };
+            int t = tb;
+            while (t < te) {
+                uint32_t ncand = 0;
+                // two register sets, each refilled right after its cell with the
+                // row two ahead (the last row again past the end: no path through
+                // the loop leaves one set's loads pending behind the other's);
+                // the table entry of that row is read before the cell
+                double GA, GB, xA, xB, jA, jB;
+                load(sRow[t], GA, xA, jA);
+                load(sRow[t + 1 < te ? t + 1 : t], GB, xB, jB);
+                for (; t < te; t += 2) {
+                    {
+                        const RowE nx = sRow[t + 2 < te ? t + 2 : te - 1];
+                        const int pr = orb(t);
+                        const double D = OS_ ? Gcl + (GA + jA) : (GA + Gcl) + jA;
+                        note(cell(xA, D, okc, OS_ ? pr : pc, OS_ ? pc : pr, thr), t, ncand);
+                        load(nx, GA, xA, jA);
+                    }
+                    {
+                        const RowE nx = sRow[t + 3 < te ? t + 3 : te - 1];
+                        if (t + 1 < te) {
+                            const int pr = orb(t + 1);
+                            const double D = OS_ ? Gcl + (GB + jB) : (GB + Gcl) + jB;
+                            note(cell(xB, D, okc, OS_ ? pr : pc, OS_ ? pc : pr, thr), t + 1, ncand);
+                        }
+                        load(nx, GB, xB, jB);
+                    }
+                    if (ncand > (uint32_t)(CL_CAP - 2 * WAVE)) { t += 2; break; }
+                }
+                if (ncand) flush(c0, ncand);
+            }
+            ncell += okc ? (uint32_t)(te - tb) : 0u;
+        };
+        int td = 0, tf = 0;
         for (int c0 = 0; os ? c0 < nc : c0 + 1 < nc; c0 += WAVE) {
             const int c = c0 + lane;
             const bool okc = c < nc && !bit_of(sColF, c);
-            int dlim = -1;
             if (!os) {
-                while (td < nrow && (int)(sRow[td].info >> 8) <= c0) ++td;
-                dlim = c0 + WAVE;
+                while (td < nrow && (int)(sRi[td] >> 8) <= c0) ++td;
+                while (tf < nrow && (int)(sRi[tf] >> 8) < c0 + WAVE) ++tf;
             }
             if (__ballot(okc) == 0ull || td >= nrow) continue;
             // a lane past the last column reads a valid column: the last one, or
@@ -375,110 +513,27 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
             const int pc = cvirt[c < nc ? c : (os ? nc - 1 : 0)];
             const double Gcl = okc ? col_G(pc) : DEAD_D;
             const uint32_t off8 = (uint32_t)pc * 8u;
-            auto lane_off = [&](int r) -> uint32_t { return (r >= dlim || c < r) ? off8 : 0u; };
-            int t = td;
-            while (t < nrow) {
-                uint32_t ncand = 0;
-                RowE e = sRow[t];
-                uint32_t rp = rfl(e.info);
-                double Gr = e.G;
-                uint32_t o8 = lane_off((int)(rp >> 8));
-                double xc = bload(rX, o8, xoff(rp & 255));
-                double jc = bload(rJ, o8, (uint32_t)((rp & 255) * n) * 8u);
-                e = sRow[t + 1 < nrow ? t + 1 : t];
-                for (; t < nrow; ++t) {
-                    const int pr = rp & 255, r = (int)(rp >> 8);
-                    const double x = xc, j = jc, G = Gr;
-                    if (t + 1 < nrow) {
-                        rp = rfl(e.info);
-                        Gr = e.G;
-                        const int pn = rp & 255;
-                        o8 = lane_off((int)(rp >> 8));
-                        xc = bload(rX, o8, xoff(pn));
-                        jc = bload(rJ, o8, (uint32_t)(pn * n) * 8u);
-                        e = sRow[t + 2 < nrow ? t + 2 : t + 1];
-                    }
-                    double D = diag(Gcl, G, j);
-                    bool ok = okc;
-                    if (r < dlim) {
-                        ok = okc && c < r;
-                        D = ok ? D : DEAD_D;
-                        ncell += ok ? 1u : 0u;
-                    }
-                    const bool cnd = cell(x, D, ok, os ? pr : pc, os ? pc : pr) && ok;
-                    const uint64_t mk = __builtin_amdgcn_ballot_w64(cnd);
-                    if (mk) {
-                        if (cnd) sCl[ncand + __popcll(mk & ((1ull << lane) - 1ull))] = (uint32_t)t | ((uint32_t)lane << 16);
-                        ncand += (uint32_t)__popcll(mk);
-                        if (ncand > (uint32_t)(CL_CAP - WAVE)) { ++t; break; }
-                    }
-                }
-                if (ncand) {
-                    __syncthreads();
-                    // the listed cells, recomputed with the loop's arithmetic: the
-                    // exact key test and the append
-                    for (uint32_t i0 = 0; i0 < ncand; i0 += WAVE) {
-                        const uint32_t i = i0 + lane;
-                        bool cand = false;
-                        uint64_t key = 0;
-                        double ek[NS];
-                        int pa = 0, pb = 0;
-                        if (i < ncand) {
-                            const uint32_t en = sCl[i];
-                            const int tt = (int)(en & 0xFFFF), cl = c0 + (int)(en >> 16);
-                            const RowE re = sRow[tt];
-                            const int pr = re.info & 255;
-                            const int pcl = cvirt[cl];
-                            const uint32_t ol = (uint32_t)pcl * 8u;
-                            const double x = bload(rX, ol, xoff(pr)), j = bload(rJ, ol, (uint32_t)(pr * n) * 8u);
-                            const double D = diag(col_G(pcl), re.G, j);
-                            const double x2 = x * x;
-                            double tsel = 0.0;
-#pragma unroll
-                            for (int k = 0; k < NS; ++k) {
-                                const double rc = rcp1(E0[k] - D);
-                                const double tk = x2 * rc;
-                                ek[k] = cc[k] * tk;
-                                tsel = k == 0 ? cw[0] * tk : fma(cw[k], tk, tsel);
-                            }
-                            key = (uint64_t)__double_as_longlong(fabs(tsel));
-                            cand = key >= tau_key;
-                            pa = os ? pr : pcl;
-                            pb = os ? pcl : pr;
-                        }
-                        const uint64_t mask = __ballot(cand);
-                        if (!mask) continue;
-                        const int leader = ctz64(mask);
-                        unsigned long long bse = 0;
-                        if (lane == leader) bse = atomicAdd(a.cand_count, (unsigned long long)__popcll(mask));
-                        bse = __shfl(bse, leader);
-                        appended = true;
-                        if (cand) {
-                            const unsigned long long sc = bse + __popcll(mask & ((1ull << lane) - 1ull));
-                            atomicAdd(&a.hist[key_bin(key)], 1u);
-                            if ((int64_t)sc < a.cand_cap) {
-                                Cand *cd = a.cand + sc;
-                                const int up = os ? (rs == 0 ? pa : pb) : pa;
-                                const int dn = os ? (rs == 0 ? pb : pa) : pb;
-                                cd->key = key;
-                                cd->code = pack_code(type, s1, h1, h2, up, dn);
-                                cd->g = (uint32_t)g;
-                                cd->pad = 0;
-#pragma unroll
-                                for (int k = 0; k < QPD_MAX_STATES; ++k) cd->e[k] = k < NS ? ek[k] : 0.0;
-                            } else {
-                                atomicOr(a.overflow, 1ull);
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
+            if (os) {
+                main_rows(std::integral_constant<bool, true>(), c0, 0, nrow, Gcl, off8, okc, pc);
+                continue;
             }
-            // rows at or above dlim: one cell per active lane each
-            int tf = td;
-            if (!os)
-                while (tf < nrow && (int)(sRow[tf].info >> 8) < dlim) ++tf;
-            ncell += okc ? (uint32_t)(nrow - tf) : 0u;
+            // same spin, rows inside the chunk's span
+            uint32_t ncand = 0;
+            for (int t = td; t < tf; ++t) {
+                const RowE e = sRow[t];
+                const uint32_t rp = rfl(sRi[t]);
+                const int pr = rp & 255, r = (int)(rp >> 8);
+                const bool ok = okc && c < r;
+                const uint32_t o8 = ok ? off8 : 0u;
+                const double x = bload(rX, o8, rfl(e.xo));
+                const double j = bload(rJ, o8, rfl(e.jo));
+                const double D = ok ? diag(Gcl, e.G, j) : DEAD_D;
+                ncell += ok ? 1u : 0u;
+                note(cell(x, D, ok, pc, pr, ok ? tau_val : __builtin_inf()), t, ncand);
+                if (ncand > (uint32_t)(CL_CAP - WAVE)) { flush(c0, ncand); ncand = 0; }
+            }
+            if (ncand) flush(c0, ncand);
+            main_rows(std::integral_constant<bool, false>(), c0, tf, nrow, Gcl, off8, okc, pc);
         }
 
         // batch sums: e = c^2 x^2 / delta, S = c^2 x^2 / delta^2
@@ -589,7 +644,9 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
         if (lane == 0 && mb < __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMin(dst, mb);
         mind = __builtin_inf();
     };
-    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    int64_t it0, iend, istep;
+    xcd_items(total, it0, iend, istep);
+    for (int64_t it = it0; it < iend; it += istep) {
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
             while (it >= item_end[sid]) ibase = item_end[sid++];
@@ -770,11 +827,14 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
         // below the flagged second index), then flagged columns (opposite spins:
         // the unflagged rows; same spin: the cells above the flagged first index
         // whose second index is unflagged)
-        const int nlin = os ? nr + nc : 2 * nr;
-        for (int li = 0; li < nlin; ++li) {
-            const bool colline = li >= nr;
-            const int idx = colline ? li - nr : li;
-            if (!fl(colline ? 1 : 0, idx)) continue;
+        // the set bits of the flag words, rows then columns, in ascending order
+        for (int wi = 0; wi < 16; ++wi) {
+          uint32_t bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)sF[wi]);
+          while (bits) {
+            const bool colline = wi >= 8;
+            const int idx = (wi & 7) * 32 + __builtin_ctz(bits);
+            bits &= bits - 1u;
+            if (idx >= (colline && os ? nc : nr)) continue;
             const int len = os ? (colline ? nr : nc) : (colline ? nr - 1 - idx : idx);
             for (int p0 = 0; p0 < len; p0 += WAVE) {
                 const int p = p0 + lane;
@@ -893,6 +953,7 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
                     }
                 }
             }
+          }
         }
 
         // add to the clean-cell kernel's slot (it ran before: one writer at a time)
