@@ -356,22 +356,24 @@ int qp_energy(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_
  * qp_last_timing waits for the last recorded event and writes, in ms:
  * out_ms[0] = the dense sweep kernel, out_ms[1] = the general kernel on the
  * batches handed over to it, out_ms[2] = the call's first enqueued kernel to
- * its last, out_ms[3] = the clean-cell kernel of a split sweep (0 when the
- * call did not split).  out_ms must hold 4 doubles.  Errors: QP_E_ARG when
+ * its last, out_ms[3] = the clean-cell and split-correction kernels of a
+ * split sweep (0 when the call did not split).  out_ms must hold 4 doubles.  Errors: QP_E_ARG when
  * timing is off or no call has been timed, QP_E_HIP.
  */
 int qp_set_timing(qp_ctx *ctx, int enable);
 int qp_last_timing(qp_ctx *ctx, double *out_ms);
 
 /*
- * qp_set_split -- how forward sweeps (qp_pt2, qp_pt2_generators, the forward
- * of qp_pt2_batched and the rounds of qp_pt2_stochastic) divide their cells
- * between kernels.  enable = 1 (the default): the cells of a hole-pair batch
- * that no other determinant touches go to the clean-cell kernel, in
- * hole-pair-major order, and the dense kernel keeps the rest; enable = 0:
- * the dense kernel takes every cell.  Both give the same alpha set, counts
- * and selection, and energies equal to rounding (the sums run in another
- * order).  No device work.  Errors: QP_E_ARG.
+ * qp_set_split -- how sweeps (qp_pt2, qp_pt2_backward, qp_pt2_generators,
+ * qp_pt2_batched and the rounds of qp_pt2_stochastic) divide their cells
+ * between kernels.  enable = 1 (the default): the hole-pair batches that no
+ * determinant touches in every cell go to the clean-cell kernel, in
+ * hole-pair-major order, for the cells no other determinant touches, and to
+ * the split-correction kernel for the rest; the dense kernel keeps the other
+ * batches.  enable = 0: the dense kernel takes every batch.  Both give the
+ * same alpha set, counts and selection, and energies and gradients equal to
+ * rounding (the sums run in another order).  An adjoint call with
+ * QP_FLAG_FINGERPRINT is not split.  No device work.  Errors: QP_E_ARG.
  */
 int qp_set_split(qp_ctx *ctx, int enable);
 

@@ -546,21 +546,25 @@ __global__ void pair_fill(const uint64_t *bits, int n, int64_t nw, int n_keys, c
 // per generator: the clean-cell kernel's batch slots, in batch order, after
 // the dense kernel's items and the handed-over batches
 __global__ void reduce_lean(const double *lean_eps, const double *lean_S, const unsigned long long *lean_cnt,
-                            const unsigned long long *lean_fp, const unsigned long long *lean_conn, int64_t n_gen,
-                            int n_pairs, int ns, const int32_t *perm, const int32_t *gen_rank, int64_t n_det,
-                            double *eps_g, double *S_g, uint64_t *cnt_g, uint64_t *fp_g, uint64_t *conn_g,
-                            double *eps_gen)
+                            const unsigned long long *lean_fp, const unsigned long long *lean_conn,
+                            const double *lean_dc, int64_t n_gen, int n_pairs, int ns, const int32_t *perm,
+                            const int32_t *gen_rank, int64_t n_det, double *eps_g, double *S_g, uint64_t *cnt_g,
+                            uint64_t *fp_g, uint64_t *conn_g, double *eps_gen, double *dc)
 {
     const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i0 >= n_gen) return;
     for (int k = 0; k < ns; ++k) {
-        double e = eps_g[i0 * ns + k], sv = S_g[i0 * ns + k];
+        double e = eps_g[i0 * ns + k], sv = S_g[i0 * ns + k], d = 0.0;
         for (int b = 0; b < n_pairs; ++b) {
             e += lean_eps[(i0 * n_pairs + b) * ns + k];
             sv += lean_S[(i0 * n_pairs + b) * ns + k];
+            if (lean_dc) d += lean_dc[(i0 * n_pairs + b) * ns + k];
         }
         eps_g[i0 * ns + k] = e;
         S_g[i0 * ns + k] = sv;
+        // adjoint: the generator's own dE/dc from its split batches (the
+        // general reduction has already added the rest)
+        if (lean_dc && dc) dc[(int64_t)k * n_det + perm[gen_rank ? (int64_t)gen_rank[i0] : i0]] += d;
         if (eps_gen) {
             if (gen_rank) eps_gen[k * n_gen + i0] = e;
             else eps_gen[k * n_det + perm[i0]] = e;
@@ -1031,7 +1035,7 @@ enum BufId {
     B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFE, B_DEFS, B_DEFC, B_DEFN, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
     B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_GENR,
     // split sweep: hole-pair lists and the clean-cell kernel's slots
-    B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP, B_LCONN,
+    B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP, B_LCONN, B_LDC, B_LTAKEN,
     // integral layouts of a system of a batched call
     B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
     // Davidson
@@ -1091,7 +1095,7 @@ struct qp_ctx {
     bool split_enabled = true;     // forward sweeps split clean cells off (qp_set_split)
     // call start, dense sweep start, general kernel start, sweep end, call end
     // [5]: between the dense kernel and the clean-cell kernel
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -1350,25 +1354,25 @@ int fast_occ_t(int ns, bool bwd, size_t lds, bool fp)
 // batches, and the clean-cell kernel of a split sweep
 enum Kind { K_DENSE = 0, K_GENERAL = 1, K_LEAN = 2, K_CORR = 3 };
 
-template <int NINT>
+template <int NINT, bool BWD>
 int corr_occ_t(int ns, size_t lds, bool fp)
 {
     switch (ns) {
-    case 1: return corr_occupancy<NINT, 1>(lds, fp);
-    case 2: return corr_occupancy<NINT, 2>(lds, fp);
-    case 3: return corr_occupancy<NINT, 3>(lds, fp);
-    default: return corr_occupancy<NINT, 4>(lds, fp);
+    case 1: return corr_occupancy<NINT, 1, BWD>(lds, fp);
+    case 2: return corr_occupancy<NINT, 2, BWD>(lds, fp);
+    case 3: return corr_occupancy<NINT, 3, BWD>(lds, fp);
+    default: return corr_occupancy<NINT, 4, BWD>(lds, fp);
     }
 }
 
-template <int NINT>
+template <int NINT, bool BWD>
 int lean_occ_t(int ns, size_t lds, bool fp)
 {
     switch (ns) {
-    case 1: return lean_occupancy<NINT, 1, false>(lds, fp);
-    case 2: return lean_occupancy<NINT, 2, false>(lds, fp);
-    case 3: return lean_occupancy<NINT, 3, false>(lds, fp);
-    default: return lean_occupancy<NINT, 4, false>(lds, fp);
+    case 1: return lean_occupancy<NINT, 1, BWD>(lds, fp);
+    case 2: return lean_occupancy<NINT, 2, BWD>(lds, fp);
+    case 3: return lean_occupancy<NINT, 3, BWD>(lds, fp);
+    default: return lean_occupancy<NINT, 4, BWD>(lds, fp);
     }
 }
 
@@ -1376,8 +1380,8 @@ template <int NINT>
 int kind_occ_t(int kind, int ns, bool bwd, size_t lds, bool fp)
 {
     if (kind == K_DENSE) return fast_occ_t<NINT>(ns, bwd, lds, fp);
-    if (kind == K_LEAN) return lean_occ_t<NINT>(ns, lds, fp);
-    if (kind == K_CORR) return corr_occ_t<NINT>(ns, lds, fp);
+    if (kind == K_LEAN) return bwd ? lean_occ_t<NINT, true>(ns, lds, fp) : lean_occ_t<NINT, false>(ns, lds, fp);
+    if (kind == K_CORR) return bwd ? corr_occ_t<NINT, true>(ns, lds, fp) : corr_occ_t<NINT, false>(ns, lds, fp);
     return sweep_occ_t<NINT>(ns, bwd, lds);
 }
 
@@ -1433,9 +1437,11 @@ void launch_ns(int kind, const SweepArgs *sys, const int64_t *end, int n_sys, bo
                int grid, hipStream_t st)
 {
     if (kind == K_LEAN) {
-        launch_lean<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
+        if (bwd) launch_lean<NINT, NS, true>(sys, end, n_sys, fp, lds, grid, st);
+        else launch_lean<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
     } else if (kind == K_CORR) {
-        launch_corr<NINT, NS>(sys, end, n_sys, fp, lds, grid, st);
+        if (bwd) launch_corr<NINT, NS, true>(sys, end, n_sys, fp, lds, grid, st);
+        else launch_corr<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
     } else if (kind == K_DENSE) {
         if (bwd) launch_fast<NINT, NS, true>(sys, end, n_sys, fp, lds, grid, st);
         else launch_fast<NINT, NS, false>(sys, end, n_sys, fp, lds, grid, st);
@@ -1562,8 +1568,8 @@ std::vector<LaunchPlan> plan_launches(qp_ctx *c, int kind, bool bwd, bool fp, co
         size_t lds;
         const int nvm = n - std::min(run[s].P.nup, run[s].P.ndn);
         if (kind == K_DENSE) lds = fast_lds_bytes(n, nvm, ns, bwd, run[s].a.rscap, run[s].a.cscap);
-        else if (kind == K_LEAN) lds = lean_lds_bytes(n, nvm);
-        else if (kind == K_CORR) lds = corr_lds_bytes(n, ns);
+        else if (kind == K_LEAN) lds = lean_lds_bytes(n, nvm, bwd);
+        else if (kind == K_CORR) lds = corr_lds_bytes(n, ns, bwd);
         else lds = sweep_lds_bytes(n, ns, bwd);
         LaunchPlan *p = nullptr;
         for (auto &q : plans) if (q.nint == nint && q.ns == ns) p = &q;
@@ -1757,7 +1763,9 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         a.def_mode = 0;
         items[s] = r.swept ? r.n_items : 0;
         // split sweep (forward): hole-pair lists for the clean-cell kernel
-        r.split = !bwd && r.swept && nel >= 2 && c->split_enabled;
+        // (a fingerprinted adjoint is not split: the adjoint kernels have no
+        // fingerprint variant)
+        r.split = r.swept && nel >= 2 && c->split_enabled && !(bwd && fp);
         if (r.split) {
             const int np = nel * (nel - 1) / 2;
             const int n_keys = n * n + n * (n - 1);
@@ -1774,7 +1782,9 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             unsigned long long *lcnt = (unsigned long long *)scratch(c, s, B_LCNT, sizeof(unsigned long long) * n_g);
             unsigned long long *lfp = (unsigned long long *)scratch(c, s, B_LFP, sizeof(unsigned long long) * n_g);
             unsigned long long *lconn = (unsigned long long *)scratch(c, s, B_LCONN, sizeof(unsigned long long) * n_g);
-            if (!bits || !kcnt || !koff || !kbs || !kpos || !leps || !lS || !lcnt || !lfp || !lconn)
+            double *ldc = bwd ? (double *)scratch(c, s, B_LDC, sizeof(double) * tot * ns) : nullptr;
+            uint32_t *ltaken = bwd ? (uint32_t *)scratch(c, s, B_LTAKEN, sizeof(uint32_t) * n_det * r.nbw) : nullptr;
+            if (!bits || !kcnt || !koff || !kbs || !kpos || !leps || !lS || !lcnt || !lfp || !lconn || (bwd && (!ldc || !ltaken)))
                 return fail(c, QP_E_OOM, "device allocation failed (clean-cell lists)");
             HIPCHK(c, hipMemsetAsync(lcnt, 0, sizeof(unsigned long long) * n_g, st));
             HIPCHK(c, hipMemsetAsync(lfp, 0, sizeof(unsigned long long) * n_g, st));
@@ -1801,6 +1811,9 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             a.lean_cnt = lcnt;
             a.lean_fp = lfp;
             a.lean_conn = lconn;
+            a.lean_dc = ldc;
+            a.taken_bits = ltaken;
+            if (bwd) HIPCHK(c, hipMemsetAsync(ltaken, 0, sizeof(uint32_t) * n_det * r.nbw, st));
             r.n_pairs = np;
             litems[s] = tot;
         }
@@ -1809,19 +1822,29 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     // ------------------------------------------------- phase 2: dense kernel
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], st));
     {
-        std::vector<LaunchPlan> plans = plan_launches(c, K_DENSE, bwd, fp, in, run, items);
-        int rc = launch_plans(c, K_DENSE, bwd, fp, plans, run, st);
-        if (rc != QP_OK) return rc;
+        // forward: the dense kernel first, whose selection candidates raise the
+        // threshold before the clean cells of split sweeps; adjoint: the
+        // clean-cell kernel first, which marks the batches it takes for the
+        // dense kernel (the flagged cells follow it, added to the same slots)
+        int rc = QP_OK;
+        if (!bwd) {
+            std::vector<LaunchPlan> plans = plan_launches(c, K_DENSE, bwd, fp, in, run, items);
+            rc = launch_plans(c, K_DENSE, bwd, fp, plans, run, st);
+            if (rc != QP_OK) return rc;
+        }
         if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], st));
-        // the clean cells of split sweeps, after the dense kernel, whose
-        // selection candidates have raised the threshold by then
         std::vector<LaunchPlan> lplans = plan_launches(c, K_LEAN, bwd, fp, in, run, litems);
         rc = launch_plans(c, K_LEAN, bwd, fp, lplans, run, st);
         if (rc != QP_OK) return rc;
-        // then their flagged cells, added to the same batch slots
         std::vector<LaunchPlan> cplans = plan_launches(c, K_CORR, bwd, fp, in, run, litems);
         rc = launch_plans(c, K_CORR, bwd, fp, cplans, run, st);
         if (rc != QP_OK) return rc;
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[6], st));
+        if (bwd) {
+            std::vector<LaunchPlan> plans = plan_launches(c, K_DENSE, bwd, fp, in, run, items);
+            rc = launch_plans(c, K_DENSE, bwd, fp, plans, run, st);
+            if (rc != QP_OK) return rc;
+        }
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], st));
 
@@ -1912,9 +1935,10 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
                                bwd ? x.grad_coefs : nullptr, r.dp);
         if (r.swept && r.split)
             hipLaunchKernelGGL(reduce_lean, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.a.lean_eps, r.a.lean_S,
-                               r.a.lean_cnt, r.a.lean_fp, r.a.lean_conn, r.n_g, r.n_pairs, ns, r.P.perm,
-                               (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
-                               bwd ? nullptr : x.eps_gen);
+                               r.a.lean_cnt, r.a.lean_fp, r.a.lean_conn, bwd ? r.a.lean_dc : (const double *)nullptr,
+                               r.n_g, r.n_pairs, ns, r.P.perm, (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g,
+                               r.cnt_g, r.fp_g, r.conn_g, bwd ? nullptr : x.eps_gen,
+                               bwd ? x.grad_coefs : nullptr);
         else if (!r.swept && r.n_g > 0)
             hipLaunchKernelGGL(reduce_empty, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.n_g, ns, r.P.perm,
                                (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
@@ -2698,12 +2722,15 @@ int qp_last_timing(qp_ctx *c, double *out_ms)
     if (!c || !out_ms) return QP_E_ARG;
     if (!c->timing || !c->timed) return fail(c, QP_E_ARG, "no timed call");
     HIPCHK(c, hipEventSynchronize(c->ev[4]));
-    float a = 0.f, b = 0.f, t = 0.f, l = 0.f;
+    // the dense kernel runs before the clean-cell and split-correction kernels
+    // in the forward sweep and after them in the adjoint
+    float a = 0.f, a2 = 0.f, b = 0.f, t = 0.f, l = 0.f;
     HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[5]));
-    HIPCHK(c, hipEventElapsedTime(&l, c->ev[5], c->ev[2]));
+    HIPCHK(c, hipEventElapsedTime(&a2, c->ev[6], c->ev[2]));
+    HIPCHK(c, hipEventElapsedTime(&l, c->ev[5], c->ev[6]));
     HIPCHK(c, hipEventElapsedTime(&b, c->ev[2], c->ev[3]));
     HIPCHK(c, hipEventElapsedTime(&t, c->ev[0], c->ev[4]));
-    out_ms[0] = a;
+    out_ms[0] = a + a2;
     out_ms[1] = b;
     out_ms[2] = t;
     out_ms[3] = l;

@@ -364,6 +364,8 @@ struct SweepArgs {
     unsigned long long *lean_cnt;  // [n_gen] clean cells counted (atomics)
     unsigned long long *lean_fp;   // [n_gen] fingerprint sums (atomics)
     unsigned long long *lean_conn; // [n_gen] connections of flagged cells (atomics)
+    double *lean_dc;          // [n_gen][n_pairs][ns]  adjoint: the generator's dc share per batch
+    uint32_t *taken_bits;     // [n_det][nbw]  adjoint: batches the clean-cell kernel takes (bit nel + pair)
 };
 
 // Split sweep: the cells of the hole-pair batch (holes hc0, hc1 as spin << 8 |
@@ -471,13 +473,13 @@ void launch_lean(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool 
                  hipStream_t st);
 template <int NINT, int NS, bool BWD>
 int lean_occupancy(size_t lds, bool fp);
-size_t lean_lds_bytes(int n, int nvm);
-template <int NINT, int NS>
+size_t lean_lds_bytes(int n, int nvm, bool bwd);
+template <int NINT, int NS, bool BWD>
 void launch_corr(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
                  hipStream_t st);
-template <int NINT, int NS>
+template <int NINT, int NS, bool BWD>
 int corr_occupancy(size_t lds, bool fp);
-size_t corr_lds_bytes(int n, int ns);
+size_t corr_lds_bytes(int n, int ns, bool bwd);
 // capacities of the dense kernel's per-batch correction buffers; the clean-cell
 // kernel applies the same limits to decide which batches it takes
 #define QPF_FCAP 32

@@ -363,6 +363,10 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 __syncthreads();
                 if (taken) continue;
             }
+            // the adjoint runs the clean-cell kernel first, which marks the
+            // batches it takes
+            if (BWD && a.split && type != BT_SINGLE && ((a.taken_bits[g * a.nbw + (b >> 5)] >> (b & 31)) & 1u))
+                continue;
 
             // particle tables: Fock-diagonal part of H_alpha,alpha and phase
             for (int i = lane; i < nr; i += WAVE) {

@@ -74,6 +74,37 @@ __device__ __forceinline__ double wsum(double v)
     return v;
 }
 
+// v moved DPP-wise across lanes (0 where the source lane is outside the row
+// or the row is masked off)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dppd(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The sums over the wave of two values at once: one exchange of the wave's
+// halves (lanes 32-63 of the first operand with lanes 0-31 of the second)
+// leaves u's pairwise sums in lanes 0-31 and w's in lanes 32-63; a DPP scan
+// within each half then puts u's total in lane 31 and w's in lane 63.
+__device__ __forceinline__ double sum2(double u, double w)
+{
+    const long long ub = __double_as_longlong(u), wb = __double_as_longlong(w);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)(ub & 0xffffffffll), (unsigned)(wb & 0xffffffffll),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(ub >> 32), (unsigned)(wb >> 32), false, false);
+    double v = __longlong_as_double(((long long)hi[0] << 32) | lo[0]) +
+               __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+    v += dppd<0x111, 0xf>(v);   // row_shr:1
+    v += dppd<0x112, 0xf>(v);   // row_shr:2
+    v += dppd<0x114, 0xf>(v);   // row_shr:4
+    v += dppd<0x118, 0xf>(v);   // row_shr:8
+    v += dppd<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T *carve(unsigned char *base, unsigned &off, int count)
 {
@@ -133,9 +164,9 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t voff,
 }  // namespace qplean
 
 // LDS of one workgroup (nvm = largest virtual count of a spin)
-size_t lean_lds_bytes(int n, int nvm)
+size_t lean_lds_bytes(int n, int nvm, bool bwd)
 {
-    size_t b = 0;
+    size_t b = bwd ? 8 * QPD_MAX_ORB : 0;   // adjoint: the wave's dE/dh_pp
     auto add = [&](size_t bytes) { b = ((b + 15) & ~(size_t)15) + bytes; };
     add(2 * 2 * n);     // sVidx
     add(2 * n);         // sVirt
@@ -151,7 +182,11 @@ namespace qplean {
 
 // waves per SIMD the register allocation aims for
 template <int NINT, int NS, bool BWD, bool FP>
-constexpr int lean_waves() { return FP && NS == 4 && NINT >= 3 ? 2 : (FP || NS == 4 ? 3 : (NS == 1 ? 5 : 4)); }
+constexpr int lean_waves()
+{
+    if (BWD) return NS == 1 ? 4 : (NS == 2 ? 3 : 2);
+    return FP && NS == 4 && NINT >= 3 ? 2 : (FP || NS == 4 ? 3 : (NS == 1 ? 5 : 4));
+}
 
 template <int NINT, int NS, bool BWD, bool FP>
 __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(lean_waves<NINT, NS, BWD, FP>(), 8)))
@@ -176,11 +211,25 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         if (lane == 0 && mb < __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMin(dst, mb);
         mind = __builtin_inf();
     };
+    // adjoint: this wave's share of dE/dh_pp, kept in LDS across its items and
+    // added to the system's dh when the wave moves on and at the end
+    double *sDH = reinterpret_cast<double *>(lds);
+    if (BWD)
+        for (int p = lane; p < QPD_MAX_ORB; p += WAVE) sDH[p] = 0.0;
+    auto flush_dh = [&](ConstSys &s) {
+        if (!BWD) return;
+        for (int p = lane; p < s.n; p += WAVE) {
+            const double v = sDH[p];
+            if (v != 0.0 && s.dh) atomicAdd(&s.dh[(int64_t)p * s.n + p], v);
+            sDH[p] = 0.0;
+        }
+    };
     int64_t it0, iend, istep;
     xcd_items(total, it0, iend, istep);
     for (int64_t it = it0; it < iend; it += istep) {
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
+            flush_dh(((ConstSys *)sys)[sid]);
             while (it >= item_end[sid]) ibase = item_end[sid++];
             K = -1;
         }
@@ -209,7 +258,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         const int nvm = n - (nup < ndn ? nup : ndn);
         const bool want_sel = a.n_select > 0;
 
-        unsigned off = 0;
+        unsigned off = BWD ? 8u * QPD_MAX_ORB : 0u;
         uint16_t *sVidx = carve<uint16_t>(lds, off, 2 * n);
         uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
         uint32_t *sRowF = carve<uint32_t>(lds, off, 8);
@@ -281,10 +330,17 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         // with a determinant that touches every cell is not split
         const bool take = split_flags(a, g, n, nup, ndn, type == BT_OS, rs, hc0, hc1, sVidx, sRowF, sColF, lane);
         __syncthreads();
+        // the adjoint's dense kernel runs after this one and leaves out what it
+        // takes
+        if (BWD && take && lane == 0) {
+            const int b = a.nel + pb;
+            atomicOr(&a.taken_bits[g * a.nbw + (b >> 5)], 1u << (b & 31));
+        }
         if (!take) {
             if (lane < NS) {
                 a.lean_eps[slot * NS + lane] = 0.0;
                 a.lean_S[slot * NS + lane] = 0.0;
+                if (BWD) a.lean_dc[slot * NS + lane] = 0.0;
             }
             continue;
         }
@@ -314,7 +370,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         }
         __syncthreads();
 
-        double E0[NS], cc[NS], cw[NS], q[NS], sq[NS];
+        double E0[NS], cc[NS], cw[NS], q[NS], sq[NS], gc[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             E0[k] = a.E0[k];
@@ -323,6 +379,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
             cw[k] = cc[k] * a.inv_maxc2[k];
             q[k] = 0.0;
             sq[k] = 0.0;
+            gc[k] = BWD ? a.gup[k] * cc[k] : 0.0;
         }
         const uint64_t tau_key = want_sel ? bin_edge(__atomic_load_n(a.tau_bin, __ATOMIC_RELAXED)) : ~0ull;
         const double tau_val = (want_sel ? __longlong_as_double((long long)tau_key) * (1.0 - 1e-12)
@@ -340,7 +397,9 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         };
         // the energy terms of one cell; true if its selection value passes the
         // running threshold's lower bound (the exact test comes later)
-        auto cell = [&](double x, double D, bool live, int pa, int pb, double thr) -> bool {
+        // adjoint: v gains the cell's sum over states of g c^2 x^2 / delta^2, its
+        // share of dE/dh_pp for every orbital the external determinant holds
+        auto cell = [&](double x, double D, bool live, int pa, int pb, double thr, double &v) -> bool {
             const double x2 = x * x;
             double tsel = 0.0;
 #pragma unroll
@@ -350,6 +409,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 const double t = x2 * rc;
                 q[k] += t;
                 sq[k] = fma(t, rc, sq[k]);
+                if (BWD) v = fma(t * gc[k], rc, v);
                 mind = min_abs(mind, delta);
                 tsel = k == 0 ? cw[0] * t : fma(cw[k], t, tsel);
             }
@@ -454,7 +514,8 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
             }
         };
         // the main loop over rows [tb, te), specialised on the batch type
-        auto main_rows = [&](auto OSC, int c0, int tb, int te, double Gcl, uint32_t off8, bool okc, int pc) {
+        auto main_rows = [&](auto OSC, int c0, int tb, int te, double Gcl, uint32_t off8, bool okc, int pc,
+                             double &colacc) {
             constexpr bool OS_ = decltype(OSC)::value;
             // a lane with no cell takes an infinite threshold: its value, x^2
             // times about 1e-300, never reaches it
@@ -464,8 +525,8 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 x = bload(rX, off8, rfl(e.xo));
                 j = bload(rJ, off8, rfl(e.jo));
             };
-            // the row's orbital, for the fingerprint only
-            auto orb = [&](int t) -> int { return FP ? (int)(rfl(sRi[t]) & 255u) : 0; };
+            // the row's orbital, for the fingerprint and the adjoint only
+            auto orb = [&](int t) -> int { return FP || BWD ? (int)(rfl(sRi[t]) & 255u) : 0; };
             int t = tb;
             while (t < te) {
                 uint32_t ncand = 0;
@@ -477,21 +538,31 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 load(sRow[t], GA, xA, jA);
                 load(sRow[t + 1 < te ? t + 1 : t], GB, xB, jB);
                 for (; t < te; t += 2) {
+                    double vA = 0.0, vB = 0.0;
+                    const int prA = orb(t), prB = orb(t + 1 < te ? t + 1 : t);
                     {
                         const RowE nx = sRow[t + 2 < te ? t + 2 : te - 1];
-                        const int pr = orb(t);
                         const double D = OS_ ? Gcl + (GA + jA) : (GA + Gcl) + jA;
-                        note(cell(xA, D, okc, OS_ ? pr : pc, OS_ ? pc : pr, thr), t, ncand);
+                        note(cell(xA, D, okc, OS_ ? prA : pc, OS_ ? pc : prA, thr, vA), t, ncand);
                         load(nx, GA, xA, jA);
                     }
                     {
                         const RowE nx = sRow[t + 3 < te ? t + 3 : te - 1];
                         if (t + 1 < te) {
-                            const int pr = orb(t + 1);
                             const double D = OS_ ? Gcl + (GB + jB) : (GB + Gcl) + jB;
-                            note(cell(xB, D, okc, OS_ ? pr : pc, OS_ ? pc : pr, thr), t + 1, ncand);
+                            note(cell(xB, D, okc, OS_ ? prB : pc, OS_ ? pc : prB, thr, vB), t + 1, ncand);
                         }
                         load(nx, GB, xB, jB);
+                    }
+                    if (BWD) {
+                        // the two rows' totals to their orbitals, each lane's
+                        // cells to its column
+                        colacc += vA + vB;
+                        // (lane 31 holds row t's total, lane 63 row t + 1's; past
+                        // the last row the second set holds row t again, whose
+                        // total must not be written twice)
+                        const double rt = sum2(vA, vB);
+                        if ((lane & 31) == 31 && (lane < 32 || t + 1 < te)) sDH[lane < 32 ? prA : prB] += rt;
                     }
                     if (ncand > (uint32_t)(CL_CAP - 2 * WAVE)) { t += 2; break; }
                 }
@@ -513,8 +584,10 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
             const int pc = cvirt[c < nc ? c : (os ? nc - 1 : 0)];
             const double Gcl = okc ? col_G(pc) : DEAD_D;
             const uint32_t off8 = (uint32_t)pc * 8u;
+            double colacc = 0.0;   // adjoint: this lane's cells, for its column's orbital
             if (os) {
-                main_rows(std::integral_constant<bool, true>(), c0, 0, nrow, Gcl, off8, okc, pc);
+                main_rows(std::integral_constant<bool, true>(), c0, 0, nrow, Gcl, off8, okc, pc, colacc);
+                if (BWD && okc) sDH[pc] += colacc;
                 continue;
             }
             // same spin, rows inside the chunk's span
@@ -529,20 +602,41 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 const double j = bload(rJ, o8, rfl(e.jo));
                 const double D = ok ? diag(Gcl, e.G, j) : DEAD_D;
                 ncell += ok ? 1u : 0u;
-                note(cell(x, D, ok, pc, pr, ok ? tau_val : __builtin_inf()), t, ncand);
+                double v = 0.0;
+                note(cell(x, D, ok, pc, pr, ok ? tau_val : __builtin_inf(), v), t, ncand);
+                if (BWD) {
+                    colacc += v;
+                    const double rt = wsum(v);
+                    if (lane == 0) sDH[pr] += rt;
+                }
                 if (ncand > (uint32_t)(CL_CAP - WAVE)) { flush(c0, ncand); ncand = 0; }
             }
             if (ncand) flush(c0, ncand);
-            main_rows(std::integral_constant<bool, false>(), c0, tf, nrow, Gcl, off8, okc, pc);
+            main_rows(std::integral_constant<bool, false>(), c0, tf, nrow, Gcl, off8, okc, pc, colacc);
+            if (BWD && okc) sDH[pc] += colacc;
         }
 
-        // batch sums: e = c^2 x^2 / delta, S = c^2 x^2 / delta^2
+        // batch sums: e = c^2 x^2 / delta, S = c^2 x^2 / delta^2; adjoint: the
+        // generator's dE/dc_I = 2 g c_I sum x^2 / delta (its cells have no
+        // other determinant), and the batch's total of v for the orbitals
+        // every cell holds, the generator's occupied ones but the two holes
+        double vb = 0.0;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const double qs = wsum(q[k]), ss = wsum(sq[k]);
+            if (BWD) vb = fma(gc[k], ss, vb);
             if (lane == 0) {
                 a.lean_eps[slot * NS + k] = cc[k] * qs;
                 a.lean_S[slot * NS + k] = cc[k] * ss;
+                if (BWD) a.lean_dc[slot * NS + k] = 2.0 * a.gup[k] * a.coefs[(int64_t)k * a.n_det + det] * qs;
+            }
+        }
+        if (BWD && vb != 0.0) {
+            for (int p = lane; p < n; p += WAVE) {
+                const int np = (sVidx[p] == 0xFFFF ? 1 : 0) + (sVidx[n + p] == 0xFFFF ? 1 : 0) -
+                               ((s1 == 0 ? p == h1 : false) || (s2 == 0 ? p == h2 : false) ? 1 : 0) -
+                               ((s1 == 1 ? p == h1 : false) || (s2 == 1 ? p == h2 : false) ? 1 : 0);
+                if (np) sDH[p] += np * vb;
             }
         }
         uint32_t ct = ncell;
@@ -588,7 +682,10 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         }
         __syncthreads();
     }
-    if (total > 0) flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
+    if (total > 0) {
+        flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
+        flush_dh(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -607,9 +704,9 @@ constexpr int FCAPC = 64;   // fine entries a batch may have here
 
 }  // namespace qplean
 
-size_t corr_lds_bytes(int n, int ns)
+size_t corr_lds_bytes(int n, int ns, bool bwd)
 {
-    size_t b = 0;
+    size_t b = bwd ? 8 * QPD_MAX_ORB : 0;   // adjoint: the wave's dE/dh_pp
     auto add = [&](size_t bytes) { b = ((b + 15) & ~(size_t)15) + bytes; };
     add(2 * 2 * n);                 // sVidx
     add(2 * n);                     // sVirt
@@ -619,12 +716,13 @@ size_t corr_lds_bytes(int n, int ns)
     add(4 * qplean::FCAPC);         // fine: E_J's column-spin particles
     add(4 * qplean::FCAPC);         // fine: m | earlier << 2 | ner << 4 | nec << 8
     add(8 * qplean::FCAPC * ns);    // fine: c_Jk
+    if (bwd) add(8 * qplean::FCAPC * ns);   // adjoint: dE/dc_Jk
     return b + 16;
 }
 
 namespace qplean {
 
-template <int NINT, int NS, bool FP>
+template <int NINT, int NS, bool BWD, bool FP>
 __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict__ sys,
                                                    const int64_t *__restrict__ item_end, int n_sys)
 {
@@ -644,11 +742,23 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
         if (lane == 0 && mb < __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMin(dst, mb);
         mind = __builtin_inf();
     };
+    double *sDH = reinterpret_cast<double *>(lds);   // adjoint: as in the clean-cell kernel
+    if (BWD)
+        for (int p = lane; p < QPD_MAX_ORB; p += WAVE) sDH[p] = 0.0;
+    auto flush_dh = [&](ConstSys &s) {
+        if (!BWD) return;
+        for (int p = lane; p < s.n; p += WAVE) {
+            const double v = sDH[p];
+            if (v != 0.0 && s.dh) atomicAdd(&s.dh[(int64_t)p * s.n + p], v);
+            sDH[p] = 0.0;
+        }
+    };
     int64_t it0, iend, istep;
     xcd_items(total, it0, iend, istep);
     for (int64_t it = it0; it < iend; it += istep) {
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
+            flush_dh(((ConstSys *)sys)[sid]);
             while (it >= item_end[sid]) ibase = item_end[sid++];
             K = -1;
         }
@@ -673,7 +783,7 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
         const int nup = a.nup, ndn = a.ndn;
         const bool want_sel = a.n_select > 0;
 
-        unsigned off = 0;
+        unsigned off = BWD ? 8u * QPD_MAX_ORB : 0u;
         uint16_t *sVidx = carve<uint16_t>(lds, off, 2 * n);
         uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
         uint32_t *sF = carve<uint32_t>(lds, off, 16);
@@ -682,6 +792,7 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
         uint32_t *sFec = carve<uint32_t>(lds, off, FCAPC);
         uint32_t *sFm = carve<uint32_t>(lds, off, FCAPC);
         double *sFC = carve<double>(lds, off, FCAPC * NS);
+        double *sDCF = carve<double>(lds, off, BWD ? FCAPC * NS : 1);
 
         const int64_t pos = a.kl_pos[item];
         if (pos < 0 || pos >= a.n_gen) continue;
@@ -788,6 +899,8 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
             }
             continue;
         }
+        if (BWD)
+            for (int x = lane; x < nfine * NS; x += WAVE) sDCF[x] = 0.0;
         __syncthreads();
 
         const double *Fg = a.F + g * 2 * n;
@@ -802,12 +915,15 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
                                : a.I.Y + qtris(h1, h2) * (int64_t)P2;
         const double D0 = os ? HII - Fg[h1] - Fg[n + h2] + a.I.Jm[h1 * n + h2]
                              : HII - Fg[s1 * n + h1] - Fg[s1 * n + h2] + a.I.JK[h1 * n + h2];
-        double E0[NS], cI[NS];
+        double E0[NS], cI[NS], gup[NS], dcI[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             E0[k] = a.E0[k];
             cI[k] = a.coefs[(int64_t)k * a.n_det + det];
+            gup[k] = BWD ? a.gup[k] : 0.0;
+            dcI[k] = 0.0;
         }
+        double vbat = 0.0;   // adjoint: the item's total of v
         const uint64_t tau_key = want_sel ? bin_edge(__atomic_load_n(a.tau_bin, __ATOMIC_RELAXED)) : ~0ull;
         double esum[NS], ssum[NS];
 #pragma unroll
@@ -848,6 +964,7 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
 #pragma unroll
                 for (int k = 0; k < NS; ++k) A[k] = 0.0;
                 uint32_t nco = 0;
+                double Hv0 = 0.0;   // <I|H|alpha>
                 if (act) {
                     pa = rvirt[ia];
                     pbb = os ? cvirt[ib] : rvirt[ib];
@@ -875,6 +992,7 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
                              (int)(lo < h1 && h1 < hi) ^ (int)(lo < pa && pa < hi);
                     }
                     const double Hv = sg ? -x : x;
+                    Hv0 = Hv;
 #pragma unroll
                     for (int k = 0; k < NS; ++k) A[k] = cI[k] * Hv;
                     for (int f = 0; f < nfine; ++f) {
@@ -904,9 +1022,11 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
                 }
                 double ek[NS];
                 double tsel = 0.0;
+                double vc = 0.0;   // adjoint: sum over states of g A^2 / delta^2
                 if (live) {
                     cnt++;
                     conn += nco;
+                    double w[NS];
 #pragma unroll
                     for (int k = 0; k < NS; ++k) {
                         const double delta = E0[k] - D;
@@ -917,6 +1037,46 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
                         ssum[k] = fma(e, rc, ssum[k]);
                         mind = min_abs(mind, delta);
                         tsel += e / a.maxc2[k];
+                        if (BWD) {
+                            w[k] = 2.0 * gup[k] * A[k] * rc;
+                            vc = fma(gup[k] * e, rc, vc);
+                            dcI[k] = fma(w[k], Hv0, dcI[k]);
+                        }
+                    }
+                    if (BWD) {
+                        // dE/dc_J for the determinants connected to this cell,
+                        // and the one-electron part of a single excitation J ->
+                        // alpha for dE/dh_pq (the matrix elements again, now
+                        // that the numerator is known)
+                        for (int f = 0; f < nfine; ++f) {
+                            const uint32_t fm = sFm[f];
+                            const int m = fm & 3, ner = (fm >> 4) & 15, nec = (fm >> 8) & 15;
+                            const uint32_t er = sFer[f];
+                            const bool inA = has4(er, ner, ia);
+                            const bool inB = os ? has4(sFec[f], nec, ib) : has4(er, ner, ib);
+                            if (!(m == 1 ? (inA || inB) : (inA && inB))) continue;
+                            uint64_t al[2 * NINT], jb[2 * NINT];
+                            const uint64_t *Jp = a.dets + (int64_t)sFJ[f] * 2 * NINT;
+#pragma unroll
+                            for (int ww = 0; ww < 2 * NINT; ++ww) {
+                                al[ww] = alpha_word<NINT>(Ib, ww, hc0, hc1, pa, rs, pbb, cs);
+                                jb[ww] = Jp[ww];
+                            }
+                            int deg, sgl[4];
+                            const double v = sc_offdiag<NINT>(a.I, al, jb, &deg, sgl);
+                            if (deg < 1 || deg > 2) continue;
+                            double gs = 0.0;
+#pragma unroll
+                            for (int k = 0; k < NS; ++k) {
+                                atomicAdd(&sDCF[f * NS + k], w[k] * v);
+                                gs = fma(w[k], sFC[f * NS + k], gs);
+                            }
+                            if (deg == 1 && sgl[0] >= 0 && a.dh) {
+                                const double gg = 0.5 * (sgl[3] < 0 ? -gs : gs);
+                                atomicAdd(&a.dh[(int64_t)sgl[0] * n + sgl[1]], gg);
+                                atomicAdd(&a.dh[(int64_t)sgl[1] * n + sgl[0]], gg);
+                            }
+                        }
                     }
                     if (FP) {
                         uint64_t al[2 * NINT];
@@ -924,6 +1084,15 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
                         for (int w = 0; w < 2 * NINT; ++w) al[w] = alpha_word<NINT>(Ib, w, hc0, hc1, pa, rs, pbb, cs);
                         fpsum += det_fold<NINT>(al);
                     }
+                }
+                if (BWD) {
+                    // v to the external determinant's two particles: the line's
+                    // own orbital once per line chunk, the other one per lane
+                    vbat += vc;
+                    const bool pa_line = os != colline;
+                    if (vc != 0.0) sDH[pa_line ? pbb : pa] += vc;
+                    const double tl = wsum(vc);
+                    if (lane == 0 && tl != 0.0) sDH[os && colline ? cvirt[idx] : rvirt[idx]] += tl;
                 }
                 const uint64_t key = (uint64_t)__double_as_longlong(fabs(tsel));
                 const bool cand = want_sel && live && key >= tau_key;
@@ -960,9 +1129,28 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             const double es = wsum(esum[k]), ss = wsum(ssum[k]);
+            const double ds = BWD ? wsum(dcI[k]) : 0.0;
             if (lane == 0) {
                 a.lean_eps[slot * NS + k] += es;
                 a.lean_S[slot * NS + k] += ss;
+                if (BWD) a.lean_dc[slot * NS + k] += ds;
+            }
+        }
+        if (BWD) {
+            // v to the orbitals every cell holds, and dE/dc_J to the connected J
+            const double vb = wsum(vbat);
+            if (vb != 0.0) {
+                for (int p = lane; p < n; p += WAVE) {
+                    const int np = (sVidx[p] == 0xFFFF ? 1 : 0) + (sVidx[n + p] == 0xFFFF ? 1 : 0) -
+                                   ((s1 == 0 ? p == h1 : false) || (s2 == 0 ? p == h2 : false) ? 1 : 0) -
+                                   ((s1 == 1 ? p == h1 : false) || (s2 == 1 ? p == h2 : false) ? 1 : 0);
+                    if (np) sDH[p] += np * vb;
+                }
+            }
+            __syncthreads();
+            for (int x = lane; x < nfine * NS; x += WAVE) {
+                const double v = sDCF[x];
+                if (v != 0.0 && a.dc) atomicAdd(&a.dc[(int64_t)(x % NS) * a.n_det + sFJ[x / NS]], v);
             }
         }
         uint32_t ct = cnt, cn = conn;
@@ -1006,16 +1194,23 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
         }
         __syncthreads();
     }
-    if (total > 0) flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
+    if (total > 0) {
+        flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
+        flush_dh(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1]);
+    }
 }
 
 }  // namespace qplean
 
+// the adjoint has no fingerprint variant: a fingerprinted adjoint is not split
 template <int NINT, int NS, bool BWD>
 void launch_lean(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
                  hipStream_t st)
 {
-    if (fp)
+    if constexpr (BWD)
+        hipLaunchKernelGGL((qplean::lean_kernel<NINT, NS, true, false>), dim3(grid), dim3(qplean::WAVE), lds, st,
+                           sys, item_end, n_sys);
+    else if (fp)
         hipLaunchKernelGGL((qplean::lean_kernel<NINT, NS, BWD, true>), dim3(grid), dim3(qplean::WAVE), lds, st, sys,
                            item_end, n_sys);
     else
@@ -1027,34 +1222,41 @@ template <int NINT, int NS, bool BWD>
 int lean_occupancy(size_t lds, bool fp)
 {
     int blocks = 0;
-    const hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                  &blocks, qplean::lean_kernel<NINT, NS, BWD, true>, qplean::WAVE, lds)
+    const hipError_t e = BWD ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &blocks, qplean::lean_kernel<NINT, NS, BWD, false>, qplean::WAVE, lds)
+                       : fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &blocks, qplean::lean_kernel<NINT, NS, false, true>, qplean::WAVE, lds)
                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                  &blocks, qplean::lean_kernel<NINT, NS, BWD, false>, qplean::WAVE, lds);
+                                  &blocks, qplean::lean_kernel<NINT, NS, false, false>, qplean::WAVE, lds);
     if (e != hipSuccess) return 8;
     return blocks > 0 ? blocks : 1;
 }
 
-template <int NINT, int NS>
+template <int NINT, int NS, bool BWD>
 void launch_corr(const SweepArgs *sys, const int64_t *item_end, int n_sys, bool fp, size_t lds, int grid,
                  hipStream_t st)
 {
-    if (fp)
-        hipLaunchKernelGGL((qplean::corr_kernel<NINT, NS, true>), dim3(grid), dim3(qplean::WAVE), lds, st, sys,
-                           item_end, n_sys);
+    if constexpr (BWD)
+        hipLaunchKernelGGL((qplean::corr_kernel<NINT, NS, true, false>), dim3(grid), dim3(qplean::WAVE), lds, st,
+                           sys, item_end, n_sys);
+    else if (fp)
+        hipLaunchKernelGGL((qplean::corr_kernel<NINT, NS, false, true>), dim3(grid), dim3(qplean::WAVE), lds, st,
+                           sys, item_end, n_sys);
     else
-        hipLaunchKernelGGL((qplean::corr_kernel<NINT, NS, false>), dim3(grid), dim3(qplean::WAVE), lds, st, sys,
-                           item_end, n_sys);
+        hipLaunchKernelGGL((qplean::corr_kernel<NINT, NS, false, false>), dim3(grid), dim3(qplean::WAVE), lds, st,
+                           sys, item_end, n_sys);
 }
 
-template <int NINT, int NS>
+template <int NINT, int NS, bool BWD>
 int corr_occupancy(size_t lds, bool fp)
 {
     int blocks = 0;
-    const hipError_t e = fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                  &blocks, qplean::corr_kernel<NINT, NS, true>, qplean::WAVE, lds)
+    const hipError_t e = BWD ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &blocks, qplean::corr_kernel<NINT, NS, BWD, false>, qplean::WAVE, lds)
+                       : fp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                  &blocks, qplean::corr_kernel<NINT, NS, false, true>, qplean::WAVE, lds)
                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                  &blocks, qplean::corr_kernel<NINT, NS, false>, qplean::WAVE, lds);
+                                  &blocks, qplean::corr_kernel<NINT, NS, false, false>, qplean::WAVE, lds);
     if (e != hipSuccess) return 8;
     return blocks > 0 ? blocks : 1;
 }
@@ -1063,8 +1265,15 @@ int corr_occupancy(size_t lds, bool fp)
     template void launch_lean<NI, NS, false>(const SweepArgs *, const int64_t *, int, bool, size_t, int,         \
                                              hipStream_t);                                                       \
     template int lean_occupancy<NI, NS, false>(size_t, bool);                                                   \
-    template void launch_corr<NI, NS>(const SweepArgs *, const int64_t *, int, bool, size_t, int, hipStream_t); \
-    template int corr_occupancy<NI, NS>(size_t, bool);
+    template void launch_lean<NI, NS, true>(const SweepArgs *, const int64_t *, int, bool, size_t, int,          \
+                                            hipStream_t);                                                        \
+    template int lean_occupancy<NI, NS, true>(size_t, bool);                                                    \
+    template void launch_corr<NI, NS, false>(const SweepArgs *, const int64_t *, int, bool, size_t, int,         \
+                                             hipStream_t);                                                       \
+    template int corr_occupancy<NI, NS, false>(size_t, bool);                                                   \
+    template void launch_corr<NI, NS, true>(const SweepArgs *, const int64_t *, int, bool, size_t, int,          \
+                                            hipStream_t);                                                        \
+    template int corr_occupancy<NI, NS, true>(size_t, bool);
 
 QPL_INST(1, 1) QPL_INST(1, 2) QPL_INST(1, 3) QPL_INST(1, 4)
 QPL_INST(2, 1) QPL_INST(2, 2) QPL_INST(2, 3) QPL_INST(2, 4)

@@ -111,3 +111,67 @@ def test_split_generator_list_matches_full(ctx):
     gens = rng.choice(s.n_det, 57, replace=False)
     r = ctx.pt2_generators(dets, coefs, E0t, torch.from_numpy(gens.astype(np.int32)))
     assert np.array_equal(r["eps"].cpu().numpy(), full[:, gens])
+
+
+G_RTOL = 1e-7
+
+
+def _bwd(ctx, s, E0, gup):
+    import torch
+    from gpu_helpers import gpu_system
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    g = torch.tensor(gup, device=ctx.device)
+    gc, gE, gh = ctx.pt2_backward(dets, coefs, E0t, g)
+    torch.cuda.synchronize()
+    return gc.cpu().numpy(), gE.cpu().numpy(), gh.cpu().numpy()
+
+
+def _check_bwd(ctx, s):
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    gup = np.array([1.0, -0.7, 0.3, 0.5][:s.n_states])
+    o = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, grad_up=gup)
+    ctx.qp_set_split(False)
+    u = _bwd(ctx, s, E0, gup)
+    ctx.qp_set_split(True)
+    g = _bwd(ctx, s, E0, gup)
+    for name, x, y, ref in zip(("dc", "dE0", "dh"), g, u, (o.dc, o.dE0, o.dh)):
+        scale = np.abs(ref).max()
+        err, uerr = np.abs(x - ref).max() / scale, np.abs(y - ref).max() / scale
+        print(f"{s.name} {name}: split max rel err {err:.2e}, unsplit {uerr:.2e}")
+        assert err <= G_RTOL, name
+        assert uerr <= G_RTOL, name
+    assert np.abs(g[2] - g[2].T).max() <= 1e-12 * np.abs(g[2]).max()
+
+
+@pytest.mark.parametrize("n,nu,nd,ndet,ns,seed", [(20, 5, 4, 300, 2, 52), (16, 4, 4, 250, 1, 51)])
+def test_split_backward_dense_connectivity(ctx, n, nu, nd, ndet, ns, seed):
+    """The adjoint of split batches (clean cells: the generator's dc, dE0 and
+    dh's diagonal; flagged cells: dc of every connected J and the one-electron
+    part of single excitations) against the oracle's gradients."""
+    _check_bwd(ctx, synth.make_system(f"bdense_n{n}", seed, n, nu, nd, ndet, n_states=ns))
+
+
+@pytest.mark.parametrize("n,nu,nd,ndet,ns", [(96, 4, 4, 120, 2), (130, 3, 3, 150, 3)])
+def test_split_backward_grown(ctx, n, nu, nd, ndet, ns):
+    _check_bwd(ctx, synth.make_system(f"bgrown_n{n}", 7100 + n, n, nu, nd, ndet, n_states=ns))
+
+
+def test_split_backward_n256_top_orbitals(ctx):
+    """Four words per spin, two states, particles and holes on orbitals 254
+    and 255."""
+    n = 256
+    rng = np.random.default_rng(2561)
+    h, eri = synth.make_integrals(rng, n, 8)
+    occs = {((0, 63, 64, 255), (1, 127, 128, 254))}
+    pool = [0, 1, 2, 62, 63, 64, 65, 126, 127, 128, 129, 190, 191, 192, 193, 250, 253, 254, 255]
+    while len(occs) < 8:
+        up = tuple(sorted(rng.choice(pool, 4, replace=False).tolist()))
+        dn = tuple(sorted(rng.choice(pool, 4, replace=False).tolist()))
+        occs.add((up, dn))
+    occs = sorted(occs)
+    dets = _dets_from_orbitals(n, occs)
+    c = rng.standard_normal((2, len(occs)))
+    c[:, 0] += 3.0
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    _check_bwd(ctx, synth.System("bn256_top", 2561, n, 4, 4, h, eri, dets, c))
