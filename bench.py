@@ -1,19 +1,25 @@
 #!/usr/bin/env python
 """Throughput of the MI355X EN-PT2 / CIPSI-selection sweep.
 
-A step is one qp_pt2 call (generator ordering, per-generator preparation,
-coarse filter, the batch sweep, reductions and the top-N selection) over the
-seeded synthetic workload, with all inputs already resident in HBM.  The
-metric is external determinants (|A|) per second.  Besides the one JSON line
-on stdout, progress goes to stderr.
+A step is one pass of the whole hot path over the seeded synthetic workload,
+with all inputs already resident in HBM: the forward sweep with its top-N
+selection (qp_pt2: generator ordering, per-generator preparation, coarse
+filter, the batch sweep, reductions and selection) followed by the adjoint
+sweep (qp_pt2_backward: dE/dc, dE/dE0, dE/dh).  The headline workload is the
+largest single-GPU one: n_orb 256 (four words per spin), 16+16 electrons,
+10^6 determinants, 2 states, top-10^5.  The metric is external determinants
+(|A|) per second of the step.  Besides the one JSON line on stdout, progress
+goes to stderr.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
 
-Besides the headline forward sweep it reports, in "extra": the forward +
-adjoint throughput of the same workload, and the batched workload (64
-independent systems, n_orb in {32,48,64,96}, 4-12 electrons per spin,
-100-20,000 determinants, 1-3 states) run as one qp_pt2_batched call, forward
-and forward + adjoint, against one qp_pt2 call per system on the same GPU.
+In "extra": the forward sweep alone, the n_orb 64 workload (10+10 electrons,
+10^4 determinants, top-1000: forward, forward + adjoint, the dense kernel's
+roofline and measured traffic), the batched workload (64 independent
+systems, n_orb in {32,48,64,96}, 4-12 electrons per spin, 100-20,000
+determinants, 1-3 states) as one qp_pt2_batched call against one qp_pt2 call
+per system, and the rows built on the sweep (semi-stochastic PT2,
+sigma-build, Davidson) on the n_orb 64 workload.
 """
 from __future__ import annotations
 
@@ -38,50 +44,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# HBM traffic of one dense-kernel launch, from two rocprofv3 --pmc runs (FETCH_SIZE, then
-# WRITE_SIZE) scaled by the same counters on a 1 GiB device copy.  Valid only for the kernel
-# sources it was measured on (SHA-256 of DENSE_SOURCES); reported as null otherwise.
-DENSE_SOURCES = ["qp_dev.h", "qp_fast_caps.h", "qp_fast_impl.h", "qp_fast_fwd.hip"]
-MEASURED_TRAFFIC = {
-    "c2_n64_10a10b_1e4det_top1000": {
-        "sources_sha256": "136aac2bf4ee8ed9b10794d64b97884de7437c521ccd2e8cb316910538bdfffc",
-        "bytes": 44599648000 + 46649760,
-    },
-}
+# HBM traffic of one launch of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE) scaled by the same counters on a device copy of known size.  Valid only for
+# the kernel sources it was measured on (SHA-256 of CLEAN_SOURCES); reported as null otherwise.
+CLEAN_SOURCES = ["qp_dev.h", "qp_lean.hip"]
+MEASURED_TRAFFIC = {}
 
 
-def dense_sources_sha256():
+def clean_sources_sha256():
     import hashlib
     h = hashlib.sha256()
-    for f in DENSE_SOURCES:
+    for f in CLEAN_SOURCES:
         with open(os.path.join(ROOT, "paper_1902_08154_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def ops_per_alpha(stats, ns, nint):
-    """Method-intrinsic lane operations per external determinant: the ban test
-    (3), the per-state FP64 work (15: the element's phase and scaling, the
-    diagonal update, the denominator, the energy and its two accumulations, the
-    selection test) and, for each connection to a non-generator J, the
-    excitation analysis on 2*n_int words (12 per word) plus 2 FP64 per state
-    (connections per alpha averaged over the sweep)."""
-    conn = stats["n_connections"] / max(stats["n_alpha"], 1)
-    return 3.0 + 15.0 * ns + (12.0 * nint + 2.0 * ns) * conn
+def clean_ops_per_alpha(ns, adjoint):
+    """Method-intrinsic lane operations per external determinant that only its
+    generator reaches (a clean cell): the per-state FP64 work of the forward
+    sweep (15, as in ops_per_alpha; no ban test and no connection: the batch's
+    filter has settled both), and for the adjoint 4 more per state (the weight
+    2 g A / delta and the diagonal share g A^2 / delta^2) plus 2 (that share's
+    row and column accumulation)."""
+    return 15.0 * ns + ((4.0 * ns + 2.0) if adjoint else 0.0)
 
 
-def cpu_baseline(s, E0, n_gen):
+def cpu_baseline(s, E0, n_gen, visit_cap=0):
+    """The oracle's per-generator sweep on n_gen generators evenly spaced in
+    generator order; visit_cap > 0 bounds each to its first visit_cap
+    excitations (enumeration order), for workloads whose generators take
+    minutes each on one core."""
     from oracle import oracle
     rank = oracle.generator_rank(s.dets, s.coefs)
     order = np.argsort(rank)
     pick = order[np.linspace(0, s.n_det - 1, n_gen).astype(np.int64)]
     t0 = time.perf_counter()
-    r = oracle.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, pick)
+    r = oracle.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, pick, visit_cap=visit_cap)
     dt = time.perf_counter() - t0
+    what = f"the first {visit_cap} excitations of each of " if visit_cap else ""
     return dict(value=float(r.count.sum()) / dt, unit="alpha/s",
                 cores=int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))),
                 kind="oracle",
-                sample=f"{n_gen} generators evenly spaced in generator order ({int(r.count.sum())} alpha, {dt:.1f} s)")
+                sample=f"{what}{n_gen} generators evenly spaced in generator order "
+                       f"({int(r.count.sum())} alpha, {dt:.1f} s)")
 
 
 def batched_bench(ctx, dev, steps):
@@ -193,14 +199,111 @@ def next_rows_bench(ctx, dev, s, dets, coefs, E0, steps):
     return out
 
 
+def load_workload(ctx, dev, idx):
+    import torch
+    from paper_1902_08154_amd import synth
+    from paper_1902_08154_amd.api import to_device_dets
+    t0 = time.perf_counter()
+    s = synth.workload(idx)
+    log(f"workload {s.name}: n_orb={s.n_orb} {s.n_up}+{s.n_dn} e-, n_det={s.n_det}, "
+        f"states={s.n_states}, n_select={s.n_select} (generated in {time.perf_counter() - t0:.1f} s)")
+    ctx.qp_set_integrals(torch.from_numpy(s.h).to(dev), torch.from_numpy(s.eri).to(dev))
+    dets = to_device_dets(s.dets, dev)
+    coefs = torch.from_numpy(s.coefs).to(dev)
+    E0 = ctx.energy(dets, coefs)
+    torch.cuda.synchronize()
+    log(f"E0 = {E0.cpu().numpy()}")
+    return s, dets, coefs, E0
+
+
+class Sweep:
+    """Output buffers of one workload's forward and adjoint calls, allocated
+    once, outside the timed region."""
+
+    def __init__(self, ctx, dev, s, dets, coefs, E0):
+        import ctypes
+        import torch
+        from paper_1902_08154_amd import _lib
+        self.ctx, self.s, self.dets, self.coefs, self.E0 = ctx, s, dets, coefs, E0
+        ns, nd, nint, nsel = s.n_states, s.n_det, s.n_int, s.n_select
+        self.e_out = torch.empty(ns, dtype=torch.float64, device=dev)
+        self.sd = torch.empty((max(nsel, 1), 2, nint), dtype=torch.int64, device=dev)
+        self.se = torch.empty((max(nsel, 1), ns), dtype=torch.float64, device=dev)
+        self.nsl = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.st = torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev)
+        self.gup = torch.ones(ns, dtype=torch.float64, device=dev)
+        self.gc = torch.empty((ns, nd), dtype=torch.float64, device=dev)
+        self.gE = torch.empty(ns, dtype=torch.float64, device=dev)
+        self.gh = torch.empty((s.n_orb, s.n_orb), dtype=torch.float64, device=dev)
+
+    def forward(self):
+        self.ctx.qp_pt2(self.dets, self.coefs, self.E0, self.s.n_select, 0, self.e_out, self.sd, self.se,
+                        self.nsl, self.st, None)
+
+    def backward(self):
+        self.ctx.qp_pt2_backward(self.dets, self.coefs, self.E0, self.gup, 0, self.gc, self.gE, self.gh, None)
+
+    def stats(self):
+        from paper_1902_08154_amd.api import stats_to_dict
+        return stats_to_dict(self.st, self.s.n_states)
+
+
+def filter_figures(s, stats):
+    """The coarse and fine filters' reductions (the paper's filtering figure):
+    coarse entries per generator against |Psi|, fine entries per hole batch
+    against the coarse entries per generator."""
+    nel = s.n_up + s.n_dn
+    batches = s.n_det * (nel + nel * (nel - 1) // 2)
+    coarse = stats["n_coarse"] / s.n_det
+    fine = stats["n_fine"] / batches
+    return {"coarse_per_generator": coarse, "coarse_over_psi": coarse / s.n_det,
+            "fine_per_batch": fine, "fine_over_coarse": fine / coarse if coarse else None,
+            "clean_alpha_fraction": stats["n_alpha_clean"] / max(stats["n_alpha"], 1)}
+
+
+def small_leg(ctx, dev, steps, bwd_steps):
+    """The n_orb 64 workload: forward steps and forward + adjoint steps."""
+    import torch
+    s, dets, coefs, E0 = load_workload(ctx, dev, 2)
+    w = Sweep(ctx, dev, s, dets, coefs, E0)
+    w.forward()
+    w.backward()
+    torch.cuda.synchronize()
+    tms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w.forward()
+        tms.append(ctx.qp_last_timing())
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / steps
+    stats = w.stats()
+    t1 = time.perf_counter()
+    for _ in range(bwd_steps):
+        w.forward()
+        w.backward()
+    torch.cuda.synchronize()
+    tfb = (time.perf_counter() - t1) / max(bwd_steps, 1)
+    out = {"workload": s.name, "n_alpha": stats["n_alpha"], "fwd_ms": 1e3 * tf,
+           "fwd_alpha_per_s": stats["n_alpha"] / tf, "fwd_bwd_ms": 1e3 * tfb,
+           "fwd_bwd_alpha_per_s": stats["n_alpha"] / tfb,
+           "kernel_ms": {"dense": float(np.mean([t[0] for t in tms])),
+                         "general": float(np.mean([t[1] for t in tms])),
+                         "clean_cell": float(np.mean([t[4] for t in tms])),
+                         "clean_cell_and_split_correction": float(np.mean([t[3] for t in tms]))},
+           "filter": filter_figures(s, stats), "e_pt2": w.e_out.cpu().tolist()}
+    log(f"{s.name}: fwd {1e3 * tf:.2f} ms, fwd+bwd {1e3 * tfb:.2f} ms, |A| = {stats['n_alpha']}")
+    return out, (s, dets, coefs, E0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--bwd-steps", type=int, default=2)
+    ap.add_argument("--small-steps", type=int, default=5,
+                    help="timed forward steps of the n_orb 64 workload (0: skip it and the legs below)")
     ap.add_argument("--batched-steps", type=int, default=2,
                     help="timed repetitions of the 64-system batched workload (0: skip it)")
     ap.add_argument("--next-steps", type=int, default=1,
@@ -214,89 +317,92 @@ def main():
               "the sweep would shard over generators)", file=sys.stderr)
         sys.exit(2)
 
-    import ctypes
     import torch
-    from paper_1902_08154_amd import _lib, synth
-    from paper_1902_08154_amd.api import Context, to_device_dets
+    from paper_1902_08154_amd.api import Context
 
-    idx = int(args.workload[1:])
-    t0 = time.perf_counter()
-    s = synth.workload(idx)
-    log(f"workload {s.name}: n_orb={s.n_orb} {s.n_up}+{s.n_dn} e-, n_det={s.n_det}, "
-        f"states={s.n_states}, n_select={s.n_select} (generated in {time.perf_counter() - t0:.1f} s)")
     dev = torch.device("cuda", 0)
     ctx = Context(0)
-    ctx.qp_set_integrals(torch.from_numpy(s.h).to(dev), torch.from_numpy(s.eri).to(dev))
-    dets = to_device_dets(s.dets, dev)
-    coefs = torch.from_numpy(s.coefs).to(dev)
-    E0 = ctx.energy(dets, coefs)
-    torch.cuda.synchronize()
-    log(f"E0 = {E0.cpu().numpy()}")
-
-    ns, nd, nint = s.n_states, s.n_det, s.n_int
-    nsel = s.n_select
-    e_out = torch.empty(ns, dtype=torch.float64, device=dev)
-    sd = torch.empty((max(nsel, 1), 2, nint), dtype=torch.int64, device=dev)
-    se = torch.empty((max(nsel, 1), ns), dtype=torch.float64, device=dev)
-    nsl = torch.zeros(1, dtype=torch.int64, device=dev)
-    st = torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev)
-
-    def step():
-        ctx.qp_pt2(dets, coefs, E0, nsel, 0, e_out, sd, se, nsl, st, None)
+    s, dets, coefs, E0 = load_workload(ctx, dev, int(args.workload[1:]))
+    ns, nint = s.n_states, s.n_int
+    w = Sweep(ctx, dev, s, dets, coefs, E0)
 
     ctx.qp_set_timing(True)
     for i in range(args.warmup):
-        step()
+        w.forward()
+        w.backward()
         torch.cuda.synchronize()
-        tm = ctx.qp_last_timing()
-        log(f"warmup {i}: dense kernel {tm[0]:.2f} ms, general kernel {tm[1]:.2f} ms, call {tm[2]:.2f} ms")
-    timings = []
+        log(f"warmup {i} done")
+    tf_list, tb_list, wall_f = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step()
-        timings.append(ctx.qp_last_timing())
+        ta = time.perf_counter()
+        w.forward()
+        tf_list.append(ctx.qp_last_timing())   # waits for the forward's last event
+        wall_f.append(time.perf_counter() - ta)
+        log(f"step {i}: forward {wall_f[-1]:.2f} s")
+        w.backward()
+        tb_list.append(ctx.qp_last_timing())
+        log(f"step {i}: adjoint {tb_list[-1][2] / 1e3:.2f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    from paper_1902_08154_amd.api import stats_to_dict
-    stats = stats_to_dict(st, ns)
+    stats = w.stats()
     ms_per_step = 1e3 * elapsed / args.steps
     value = stats["n_alpha"] * args.steps / elapsed
-    # the dominant kernel: the dense sweep, timed with HIP events on its stream
-    kern_s = float(np.mean([t[0] for t in timings])) * 1e-3
-    gen_ms = float(np.mean([t[1] for t in timings]))
-    alpha_dense = stats["n_alpha"] - stats["n_alpha_general"]
-    per_alpha = ops_per_alpha(stats, ns, nint)
-    ops = alpha_dense * per_alpha
-    log(f"E_PT2 = {e_out.cpu().numpy()}  |A| = {stats['n_alpha']} (general kernel {stats['n_alpha_general']})  "
-        f"cells = {stats['n_cells']}  step {ms_per_step:.2f} ms  dense kernel {1e3 * kern_s:.2f} ms  "
-        f"general kernel {gen_ms:.2f} ms")
 
-    # forward + backward throughput
-    extra = {"general_kernel_ms": gen_ms, "alpha_general_kernel": stats["n_alpha_general"],
-             "e_pt2": e_out.cpu().tolist(), "rpt2_Z": stats["Z"], "e_rpt2": stats["e_rpt2"]}
-    if args.bwd_steps > 0:
-        gup = torch.ones(ns, dtype=torch.float64, device=dev)
-        gc = torch.empty((ns, nd), dtype=torch.float64, device=dev)
-        gE = torch.empty(ns, dtype=torch.float64, device=dev)
-        gh = torch.empty((s.n_orb, s.n_orb), dtype=torch.float64, device=dev)
-        ctx.qp_pt2_backward(dets, coefs, E0, gup, 0, gc, gE, gh, None)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for i in range(args.bwd_steps):
-            step()
-            ctx.qp_pt2_backward(dets, coefs, E0, gup, 0, gc, gE, gh, None)
-        torch.cuda.synchronize()
-        fb = (time.perf_counter() - t1) / args.bwd_steps
-        extra["fwd_bwd_alpha_per_s"] = stats["n_alpha"] / fb
-        extra["fwd_bwd_ms_per_step"] = 1e3 * fb
-        log(f"fwd+bwd {1e3 * fb:.2f} ms/step")
+    # the dominant kernel: the clean-cell kernel of the adjoint, timed with HIP
+    # events on the library's stream, on which it is launched
+    kb = float(np.mean([t[4] for t in tb_list])) * 1e-3
+    kf = float(np.mean([t[4] for t in tf_list])) * 1e-3
+    alpha_clean = stats["n_alpha_clean"]
+    ops_b = alpha_clean * clean_ops_per_alpha(ns, True)
+    ops_f = alpha_clean * clean_ops_per_alpha(ns, False)
+    log(f"E_PT2 = {w.e_out.cpu().numpy()}  |A| = {stats['n_alpha']} (clean {alpha_clean}, general kernel "
+        f"{stats['n_alpha_general']})  step {ms_per_step / 1e3:.2f} s  clean-cell kernel: forward "
+        f"{kf:.2f} s, adjoint {kb:.2f} s")
 
-    if args.batched_steps > 0:
-        extra["batched"] = batched_bench(ctx, dev, args.batched_steps)
+    def kms(tl):
+        return {"dense": float(np.mean([t[0] for t in tl])), "general": float(np.mean([t[1] for t in tl])),
+                "clean_cell": float(np.mean([t[4] for t in tl])),
+                "split_correction": float(np.mean([t[3] - t[4] for t in tl])),
+                "call": float(np.mean([t[2] for t in tl]))}
 
-    if args.next_steps > 0:
-        extra["next"] = next_rows_bench(ctx, dev, s, dets, coefs, E0, args.next_steps)
+    extra = {
+        "forward_ms": 1e3 * float(np.mean(wall_f)), "forward_alpha_per_s": stats["n_alpha"] / float(np.mean(wall_f)),
+        "forward_kernel_ms": kms(tf_list), "adjoint_kernel_ms": kms(tb_list),
+        "alpha_clean": alpha_clean, "alpha_general_kernel": stats["n_alpha_general"],
+        "clean_cell_forward_roofline": {"achieved": ops_f / kf / 1e12, "frac": ops_f / kf / ALU_PEAK_OPS,
+                                        "kernel_ms": 1e3 * kf,
+                                        "ops_per_alpha": clean_ops_per_alpha(ns, False)},
+        "filter": filter_figures(s, stats),
+        "e_pt2": w.e_out.cpu().tolist(), "rpt2_Z": stats["Z"], "e_rpt2": stats["e_rpt2"],
+        "n_selected": int(w.nsl.item()), "n_candidates": stats["n_candidates"],
+        "dE_dE0": w.gE.cpu().tolist(),
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's OpenMP team: OMP_NUM_THREADS if set, else every CPU of the
+        # affinity mask; one generator per thread, each bounded to its first
+        # 10^6 excitations (about 15 s), since a whole generator of this
+        # workload takes the oracle several minutes
+        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        cap = 1000000 if s.n_orb >= 128 else 0
+        cpu = cpu_baseline(s, E0.cpu().numpy(), threads if cap else 12 * threads, visit_cap=cap)
+        log(f"cpu baseline: {cpu}")
+
+    config = {"workload": s.name, "n_orb": s.n_orb, "n_up": s.n_up, "n_dn": s.n_dn, "n_det": s.n_det,
+              "n_states": ns, "n_select": s.n_select, "seed": s.seed, "n_alpha": stats["n_alpha"],
+              "n_cells": stats["n_cells"], "step": "forward with top-N selection, then adjoint"}
+    del w, dets, coefs, E0
+    torch.cuda.empty_cache()
+
+    if args.small_steps > 0 and s.name != "c2_n64_10a10b_1e4det_top1000":
+        extra["small"], c2 = small_leg(ctx, dev, args.small_steps, 2)
+        if args.batched_steps > 0:
+            extra["batched"] = batched_bench(ctx, dev, args.batched_steps)
+        if args.next_steps > 0:
+            extra["next"] = next_rows_bench(ctx, dev, *c2, args.next_steps)
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8
@@ -308,16 +414,8 @@ def main():
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del src, dst
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        # the oracle's OpenMP team: OMP_NUM_THREADS if set, else every CPU of the affinity mask;
-        # about 12 generators per thread keep the sample near 15 s of CPU work
-        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-        cpu = cpu_baseline(s, E0.cpu().numpy(), 12 * threads)
-        log(f"cpu baseline: {cpu}")
-
     mt = MEASURED_TRAFFIC.get(s.name)
-    traffic = mt["bytes"] if mt and mt["sources_sha256"] == dense_sources_sha256() else None
+    traffic = mt["bytes"] if mt and mt["sources_sha256"] == clean_sources_sha256() else None
 
     out = {
         "metric": METRIC,
@@ -332,13 +430,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": s.name, "n_orb": s.n_orb, "n_up": s.n_up, "n_dn": s.n_dn,
-                   "n_det": s.n_det, "n_states": ns, "n_select": nsel, "seed": s.seed,
-                   "n_alpha": stats["n_alpha"], "n_cells": stats["n_cells"]},
-        "roofline": {"bound": "alu", "achieved": ops / kern_s / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": ops / kern_s / ALU_PEAK_OPS, "traffic": traffic,
-                     "kernel": "qpfast::fast_kernel", "kernel_ms": 1e3 * kern_s, "ops_per_launch": ops,
-                     "alpha_per_launch": alpha_dense, "ops_per_alpha": per_alpha},
+        "config": config,
+        "roofline": {"bound": "alu", "achieved": ops_b / kb / 1e12, "peak": ALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": ops_b / kb / ALU_PEAK_OPS, "traffic": traffic,
+                     "kernel": "qplean::lean_kernel (adjoint)", "kernel_ms": 1e3 * kb, "ops_per_launch": ops_b,
+                     "alpha_per_launch": alpha_clean, "ops_per_alpha": clean_ops_per_alpha(ns, True)},
         "cpu_baseline": cpu,
         "extra": extra,
     }

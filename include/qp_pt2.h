@@ -108,6 +108,13 @@ typedef struct {
      * renormalised energy is E0_k + Z_k E_PT2,k                             */
     double   Z[QP_MAX_STATES];
     double   e_rpt2[QP_MAX_STATES];
+    /* fine filter (sec. "Fast filtering of determinants"): over every hole
+     * batch evaluated, the coarse entries J of its generator that lack at
+     * most two of the generator's electrons outside the batch's holes (the J
+     * that can reach one of its cells)                                      */
+    uint64_t n_fine;
+    uint64_t n_alpha_clean;  /* of n_alpha, the cells no determinant but the
+                                generator touches (split sweeps)              */
 } qp_pt2_stats;
 /* fold(alpha): h = 0; for each word x of alpha (up words 0..n_int-1, then down
  * words 0..n_int-1): h = splitmix64_mix(h ^ x), where splitmix64_mix is the
@@ -357,7 +364,8 @@ int qp_energy(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_
  * out_ms[0] = the dense sweep kernel, out_ms[1] = the general kernel on the
  * batches handed over to it, out_ms[2] = the call's first enqueued kernel to
  * its last, out_ms[3] = the clean-cell and split-correction kernels of a
- * split sweep (0 when the call did not split).  out_ms must hold 4 doubles.  Errors: QP_E_ARG when
+ * split sweep (0 when the call did not split), out_ms[4] = the clean-cell
+ * kernel alone.  out_ms must hold 5 doubles.  Errors: QP_E_ARG when
  * timing is off or no call has been timed, QP_E_HIP.
  */
 int qp_set_timing(qp_ctx *ctx, int enable);

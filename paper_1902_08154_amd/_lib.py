@@ -49,6 +49,8 @@ class Stats(ctypes.Structure):
         ("min_abs_delta", ctypes.c_double),
         ("Z", ctypes.c_double * QP_MAX_STATES),
         ("e_rpt2", ctypes.c_double * QP_MAX_STATES),
+        ("n_fine", ctypes.c_uint64),
+        ("n_alpha_clean", ctypes.c_uint64),
     ]
 
 

@@ -160,11 +160,11 @@ class Context:
         self._check(self._lib.qp_set_timing(self._h, 1 if enable else 0))
 
     def qp_last_timing(self):
-        """(dense sweep kernel ms, general kernel ms, whole call ms, clean-cell kernel ms)
-        of the last timed call."""
-        out = (ctypes.c_double * 4)()
+        """(dense sweep kernel ms, general kernel ms, whole call ms, clean-cell and
+        split-correction kernels ms, clean-cell kernel ms) of the last timed call."""
+        out = (ctypes.c_double * 5)()
         self._check(self._lib.qp_last_timing(self._h, out))
-        return float(out[0]), float(out[1]), float(out[2]), float(out[3])
+        return tuple(float(out[i]) for i in range(5))
 
     def qp_set_split(self, enable: bool):
         self._check(self._lib.qp_set_split(self._h, 1 if enable else 0))
@@ -381,7 +381,8 @@ def stats_to_dict(st: torch.Tensor, ns: int) -> dict:
                 n_connections=int(s.n_connections), n_alpha_general=int(s.n_alpha_general),
                 S=[float(s.S[k]) for k in range(ns)],
                 min_abs_delta=float(s.min_abs_delta),
-                Z=[float(s.Z[k]) for k in range(ns)], e_rpt2=[float(s.e_rpt2[k]) for k in range(ns)])
+                Z=[float(s.Z[k]) for k in range(ns)], e_rpt2=[float(s.e_rpt2[k]) for k in range(ns)],
+                n_fine=int(s.n_fine), n_alpha_clean=int(s.n_alpha_clean))
 
 
 def to_device_dets(dets_u64, device) -> torch.Tensor:

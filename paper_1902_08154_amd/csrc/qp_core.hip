@@ -106,6 +106,8 @@ struct Scalars {
     unsigned long long coarse_total;
     unsigned long long comp_count;
     long long pad1;
+    unsigned long long fine_total;    // fine-filter entries of the batches evaluated
+    unsigned long long clean_total;   // alpha of the clean-cell kernel
     int bad_bits;     // a bit set at >= n_orb
     int bad_elec;     // electron counts differ from det 0
     int dup;          // duplicate determinant
@@ -122,6 +124,8 @@ __global__ void reset_sweep_scalars(Scalars *sc)
         sc->overflow = 0ull;
         sc->min_delta_bits = 0x7ff0000000000000ull;
         sc->comp_count = 0ull;
+        sc->fine_total = 0ull;
+        sc->clean_total = 0ull;
         sc->bad_gen = 0;
     }
 }
@@ -549,9 +553,16 @@ __global__ void reduce_lean(const double *lean_eps, const double *lean_S, const 
                             const unsigned long long *lean_fp, const unsigned long long *lean_conn,
                             const double *lean_dc, int64_t n_gen, int n_pairs, int ns, const int32_t *perm,
                             const int32_t *gen_rank, int64_t n_det, double *eps_g, double *S_g, uint64_t *cnt_g,
-                            uint64_t *fp_g, uint64_t *conn_g, double *eps_gen, double *dc)
+                            uint64_t *fp_g, uint64_t *conn_g, double *eps_gen, double *dc,
+                            unsigned long long *clean_total)
 {
     const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    {
+        // the clean-cell kernel's alpha, summed over each wave first
+        unsigned long long v = i0 < n_gen ? lean_cnt[i0] : 0ull;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(clean_total, v);
+    }
     if (i0 >= n_gen) return;
     for (int k = 0; k < ns; ++k) {
         double e = eps_g[i0 * ns + k], sv = S_g[i0 * ns + k], d = 0.0;
@@ -735,6 +746,8 @@ __global__ void reduce_total(const double *eps_g, const double *S_g, const uint6
             stats->overflow = sc->overflow;
             stats->n_connections = sn[0];
             stats->n_alpha_general = sd[0];
+            stats->n_fine = sc->fine_total;
+            stats->n_alpha_clean = sc->clean_total;
             for (int k = 0; k < QPD_MAX_STATES; ++k) stats->S[k] = k < ns ? ss[0][k] : 0.0;
             stats->min_abs_delta = __longlong_as_double((long long)sc->min_delta_bits);
             // rPT2 (eq. Z): Z = 1 / (1 - dSigma/dE) with dSigma/dE = -S at E0
@@ -1095,7 +1108,7 @@ struct qp_ctx {
     bool split_enabled = true;     // forward sweeps split clean cells off (qp_set_split)
     // call start, dense sweep start, general kernel start, sweep end, call end
     // [5]: between the dense kernel and the clean-cell kernel
-    hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -1750,6 +1763,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         a.eps_item = r.eps_item; a.S_item = r.S_item; a.cnt_item = r.cnt_item; a.fp_item = r.fp_item;
         a.conn_item = r.conn_item;
         a.min_delta_bits = &r.P.sc->min_delta_bits;
+        a.fine_total = &r.P.sc->fine_total;
         a.n_select = x.n_select;
         for (int k = 0; k < QPD_MAX_STATES; ++k) {
             a.maxc2[k] = k < ns ? r.P.hmax[k] : 1.0;
@@ -1836,6 +1850,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         std::vector<LaunchPlan> lplans = plan_launches(c, K_LEAN, bwd, fp, in, run, litems);
         rc = launch_plans(c, K_LEAN, bwd, fp, lplans, run, st);
         if (rc != QP_OK) return rc;
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[7], st));
         std::vector<LaunchPlan> cplans = plan_launches(c, K_CORR, bwd, fp, in, run, litems);
         rc = launch_plans(c, K_CORR, bwd, fp, cplans, run, st);
         if (rc != QP_OK) return rc;
@@ -1938,7 +1953,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
                                r.a.lean_cnt, r.a.lean_fp, r.a.lean_conn, bwd ? r.a.lean_dc : (const double *)nullptr,
                                r.n_g, r.n_pairs, ns, r.P.perm, (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g,
                                r.cnt_g, r.fp_g, r.conn_g, bwd ? nullptr : x.eps_gen,
-                               bwd ? x.grad_coefs : nullptr);
+                               bwd ? x.grad_coefs : nullptr, &r.P.sc->clean_total);
         else if (!r.swept && r.n_g > 0)
             hipLaunchKernelGGL(reduce_empty, dim3(grid_for(r.n_g)), dim3(256), 0, st, r.n_g, ns, r.P.perm,
                                (const int32_t *)r.gen_rank, x.n_det, r.eps_g, r.S_g, r.cnt_g, r.fp_g, r.conn_g,
@@ -2724,16 +2739,18 @@ int qp_last_timing(qp_ctx *c, double *out_ms)
     HIPCHK(c, hipEventSynchronize(c->ev[4]));
     // the dense kernel runs before the clean-cell and split-correction kernels
     // in the forward sweep and after them in the adjoint
-    float a = 0.f, a2 = 0.f, b = 0.f, t = 0.f, l = 0.f;
+    float a = 0.f, a2 = 0.f, b = 0.f, t = 0.f, l = 0.f, l1 = 0.f;
     HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[5]));
     HIPCHK(c, hipEventElapsedTime(&a2, c->ev[6], c->ev[2]));
     HIPCHK(c, hipEventElapsedTime(&l, c->ev[5], c->ev[6]));
+    HIPCHK(c, hipEventElapsedTime(&l1, c->ev[5], c->ev[7]));
     HIPCHK(c, hipEventElapsedTime(&b, c->ev[2], c->ev[3]));
     HIPCHK(c, hipEventElapsedTime(&t, c->ev[0], c->ev[4]));
     out_ms[0] = a + a2;
     out_ms[1] = b;
     out_ms[2] = t;
     out_ms[3] = l;
+    out_ms[4] = l1;
     return QP_OK;
 }
 

@@ -366,6 +366,7 @@ struct SweepArgs {
     unsigned long long *lean_conn; // [n_gen] connections of flagged cells (atomics)
     double *lean_dc;          // [n_gen][n_pairs][ns]  adjoint: the generator's dc share per batch
     uint32_t *taken_bits;     // [n_det][nbw]  adjoint: batches the clean-cell kernel takes (bit nel + pair)
+    unsigned long long *fine_total;   // fine-filter entries over the batches evaluated (atomics)
 };
 
 // Split sweep: the cells of the hole-pair batch (holes hc0, hc1 as spin << 8 |
@@ -382,24 +383,30 @@ struct SweepArgs {
 // same on every lane.
 template <class Sys>
 __device__ bool split_flags(const Sys &a, int64_t g, int n, int nup, int ndn, bool os, int rs, int hc0, int hc1,
-                            const uint16_t *sVidx, uint32_t *rowF, uint32_t *colF, int lane)
+                            const uint16_t *sVidx, uint32_t *rowF, uint32_t *colF, int lane,
+                            unsigned *nfine = nullptr)
 {
     const int64_t cbeg = a.coff[g], cend = a.coff[g + 1];
     const int nv0 = n - nup, nv1 = n - ndn;
     bool m0 = false;
+    unsigned nf = 0;
     for (int64_t base = cbeg; base < cend; base += 64) {
         const int64_t e = base + lane;
-        if (e >= cend) break;
-        const CoarseEnt ce = a.cent[e];
-        int dc = 0, inmask = 0;
+        int m = 3;
+        CoarseEnt ce;
+        if (e < cend) {
+            ce = a.cent[e];
+            int dc = 0, inmask = 0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int d = ce.D[t];
-            if (d == 0xFFFF) continue;
-            dc++;
-            inmask |= (d == hc0 ? 1 : 0) | (d == hc1 ? 2 : 0);
+            for (int t = 0; t < 4; ++t) {
+                const int d = ce.D[t];
+                if (d == 0xFFFF) continue;
+                dc++;
+                inmask |= (d == hc0 ? 1 : 0) | (d == hc1 ? 2 : 0);
+            }
+            m = dc - __popc(inmask);
         }
-        const int m = dc - __popc(inmask);
+        if (nfine) nf += (unsigned)__popcll(__ballot(m <= 2));
         if (m > 2) continue;
         if (m == 0) { m0 = true; continue; }
         int ner = 0, nec = 0, er[4] = {0, 0, 0, 0}, ec[4] = {0, 0, 0, 0};
@@ -447,6 +454,7 @@ __device__ bool split_flags(const Sys &a, int64_t g, int n, int nup, int ndn, bo
             }
         }
     }
+    if (nfine) *nfine = nf;
     return __ballot(m0) == 0ull;
 }
 

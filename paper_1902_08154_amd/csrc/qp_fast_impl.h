@@ -313,6 +313,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
         uint64_t fpsum = 0;
         double mind = __builtin_inf();
         double vtot = 0.0;
+        uint64_t nfine_item = 0;   // fine-filter entries of the item's batches
 
         for (int b = q; b < nb; b += Q) {
             // ---------------------------------------------------- batch
@@ -439,6 +440,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 nfine += __popcll(mask);
             }
             if (nfine > FCAP) slow = true;
+            nfine_item += (uint64_t)nfine;
             __syncthreads();
 
             // ------------------------------------------ classify corrections
@@ -1372,6 +1374,7 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
             a.cnt_item[slot] = (uint32_t)cc;
             if (a.fp_item) a.fp_item[slot] = ff;
             a.conn_item[slot] = (uint32_t)cn;
+            if (!BWD && nfine_item && a.fine_total) atomicAdd(a.fine_total, (unsigned long long)nfine_item);
             // non-negative doubles order like their bit patterns; most items
             // cannot lower the minimum, so read before the atomic
             const unsigned long long mb = (unsigned long long)__double_as_longlong(mind);

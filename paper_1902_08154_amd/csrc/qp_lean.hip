@@ -185,7 +185,7 @@ template <int NINT, int NS, bool BWD, bool FP>
 constexpr int lean_waves()
 {
     if (BWD) return NS == 1 ? 4 : (NS == 2 ? 3 : 2);
-    return FP && NS == 4 && NINT >= 3 ? 2 : (FP || NS == 4 ? 3 : (NS == 1 ? 5 : 4));
+    return FP && NS == 4 ? 2 : (FP || NS >= 3 ? 3 : 4);
 }
 
 template <int NINT, int NS, bool BWD, bool FP>
@@ -216,6 +216,13 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
     double *sDH = reinterpret_cast<double *>(lds);
     if (BWD)
         for (int p = lane; p < QPD_MAX_ORB; p += WAVE) sDH[p] = 0.0;
+    // fine-filter entries of the batches this wave takes (forward only: the
+    // adjoint sweeps the same batches again)
+    unsigned long long fine_acc = 0;
+    auto flush_fine = [&](ConstSys &s) {
+        if (!BWD && lane == 0 && fine_acc && s.fine_total) atomicAdd(s.fine_total, fine_acc);
+        fine_acc = 0;
+    };
     auto flush_dh = [&](ConstSys &s) {
         if (!BWD) return;
         for (int p = lane; p < s.n; p += WAVE) {
@@ -230,6 +237,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
             flush_dh(((ConstSys *)sys)[sid]);
+            flush_fine(((ConstSys *)sys)[sid]);
             while (it >= item_end[sid]) ibase = item_end[sid++];
             K = -1;
         }
@@ -328,8 +336,11 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         // ------------------------------------------------ which cells are clean
         // the flags of the dense kernel's corrections (split_flags); a batch
         // with a determinant that touches every cell is not split
-        const bool take = split_flags(a, g, n, nup, ndn, type == BT_OS, rs, hc0, hc1, sVidx, sRowF, sColF, lane);
+        unsigned nfl = 0;
+        const bool take =
+            split_flags(a, g, n, nup, ndn, type == BT_OS, rs, hc0, hc1, sVidx, sRowF, sColF, lane, &nfl);
         __syncthreads();
+        if (take) fine_acc += nfl;
         // the adjoint's dense kernel runs after this one and leaves out what it
         // takes
         if (BWD && take && lane == 0) {
@@ -537,34 +548,44 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 double GA, GB, xA, xB, jA, jB;
                 load(sRow[t], GA, xA, jA);
                 load(sRow[t + 1 < te ? t + 1 : t], GB, xB, jB);
-                for (; t < te; t += 2) {
+                // pairs of rows: both cells first, so that their dependency
+                // chains interleave, then the refills and the candidate lists
+                bool full = false;
+                for (; t + 1 < te; t += 2) {
+                    const RowE nA = sRow[t + 2 < te ? t + 2 : te - 1];
+                    const RowE nB = sRow[t + 3 < te ? t + 3 : te - 1];
+                    const int prA = orb(t), prB = orb(t + 1);
                     double vA = 0.0, vB = 0.0;
-                    const int prA = orb(t), prB = orb(t + 1 < te ? t + 1 : t);
-                    {
-                        const RowE nx = sRow[t + 2 < te ? t + 2 : te - 1];
-                        const double D = OS_ ? Gcl + (GA + jA) : (GA + Gcl) + jA;
-                        note(cell(xA, D, okc, OS_ ? prA : pc, OS_ ? pc : prA, thr, vA), t, ncand);
-                        load(nx, GA, xA, jA);
-                    }
-                    {
-                        const RowE nx = sRow[t + 3 < te ? t + 3 : te - 1];
-                        if (t + 1 < te) {
-                            const double D = OS_ ? Gcl + (GB + jB) : (GB + Gcl) + jB;
-                            note(cell(xB, D, okc, OS_ ? prB : pc, OS_ ? pc : prB, thr, vB), t + 1, ncand);
-                        }
-                        load(nx, GB, xB, jB);
-                    }
+                    const double DA = OS_ ? Gcl + (GA + jA) : (GA + Gcl) + jA;
+                    const double DB = OS_ ? Gcl + (GB + jB) : (GB + Gcl) + jB;
+                    const bool cA = cell(xA, DA, okc, OS_ ? prA : pc, OS_ ? pc : prA, thr, vA);
+                    const bool cB = cell(xB, DB, okc, OS_ ? prB : pc, OS_ ? pc : prB, thr, vB);
+                    load(nA, GA, xA, jA);
+                    load(nB, GB, xB, jB);
+                    note(cA, t, ncand);
+                    note(cB, t + 1, ncand);
                     if (BWD) {
-                        // the two rows' totals to their orbitals, each lane's
-                        // cells to its column
+                        // the two rows' totals to their orbitals (lane 31 holds
+                        // row t's, lane 63 row t + 1's), each lane's cells to its
+                        // column
                         colacc += vA + vB;
-                        // (lane 31 holds row t's total, lane 63 row t + 1's; past
-                        // the last row the second set holds row t again, whose
-                        // total must not be written twice)
                         const double rt = sum2(vA, vB);
-                        if ((lane & 31) == 31 && (lane < 32 || t + 1 < te)) sDH[lane < 32 ? prA : prB] += rt;
+                        if ((lane & 31) == 31) sDH[lane < 32 ? prA : prB] += rt;
                     }
-                    if (ncand > (uint32_t)(CL_CAP - 2 * WAVE)) { t += 2; break; }
+                    if (ncand > (uint32_t)(CL_CAP - 2 * WAVE)) { t += 2; full = true; break; }
+                }
+                if (!full && t < te) {
+                    // an odd row count: the last row, in the first set
+                    const int prA = orb(t);
+                    double vA = 0.0;
+                    const double DA = OS_ ? Gcl + (GA + jA) : (GA + Gcl) + jA;
+                    note(cell(xA, DA, okc, OS_ ? prA : pc, OS_ ? pc : prA, thr, vA), t, ncand);
+                    if (BWD) {
+                        colacc += vA;
+                        const double rt = wsum(vA);
+                        if (lane == 0) sDH[prA] += rt;
+                    }
+                    ++t;
                 }
                 if (ncand) flush(c0, ncand);
             }
@@ -685,6 +706,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
     if (total > 0) {
         flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
         flush_dh(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1]);
+        flush_fine(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1]);
     }
 }
 

@@ -40,7 +40,7 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
 
 def test_stats_struct_layout():
     from paper_1902_08154_amd import _lib
-    assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 8 * (4 + 1 + 4 + 4)
+    assert ctypes.sizeof(_lib.Stats) == 8 * 8 + 8 * (4 + 1 + 4 + 4) + 2 * 8
 
 
 def _c_layout(tmp_path, struct, fields):
