@@ -69,6 +69,7 @@ extern "C" {
 #define QP_MAX_STATES    4
 #define QP_MAX_ORB       256
 #define QP_MAX_SYSTEMS   4096
+#define QP_NOALLOC_MAX_DET (1 << 18)   /* largest n_det of qp_generator_order_noalloc */
 
 /* qp_pt2 flags */
 #define QP_FLAG_FINGERPRINT  1  /* also compute stats.fingerprint of the alpha set */
@@ -204,6 +205,26 @@ int qp_pt2_backward(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int6
  */
 int qp_generator_order(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
                        int n_states, int flags, int32_t *order_out, void *stream);
+
+/*
+ * qp_generator_order_noalloc -- qp_generator_order for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments and the same order_out,
+ * bit for bit, for n_det <= QP_NOALLOC_MAX_DET (2^18); larger n_det:
+ * QP_E_ARG, nothing launched.  It calls no hipMalloc or hipFree and allocates
+ * nothing else: its scratch (the weights sum_k c_Ik^2 and the index array of
+ * the sort, 12 bytes per determinant up to the limit, 3 MiB in all) is a
+ * file-scope device array that every GPU the library runs on holds until the
+ * process ends, its address taken once per device when a context is
+ * created.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (other streams, other contexts, other threads) race and must be
+ * serialised by the caller.  The inputs are not validated beyond pointers and
+ * sizes (as under QP_FLAG_NOCHECK; flags is otherwise unused), and the stream
+ * is not synchronised: order_out is complete when the stream's work is.
+ * Errors: QP_E_ARG, QP_E_NOINT, QP_E_STATES, QP_E_HIP.
+ */
+int qp_generator_order_noalloc(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
+                               int n_states, int flags, int32_t *order_out, void *stream);
 
 /*
  * qp_pt2_generators -- the generator decomposition E_PT2 = sum_I eps_I (same

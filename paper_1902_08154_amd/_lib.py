@@ -23,6 +23,7 @@ QP_E_NOCONV = -10
 QP_FLAG_FINGERPRINT = 1
 QP_FLAG_NOCHECK = 2
 QP_FLAG_REUSE_INTEGRALS = 4
+QP_NOALLOC_MAX_DET = 1 << 18
 QP_SIGMA_S2 = 8
 QP_SIGMA_REUSE = 16
 QP_MAX_STATES = 4
@@ -83,7 +84,7 @@ class System(ctypes.Structure):
 EXPORTS = ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
            "qp_pt2_backward", "qp_generator_order", "qp_pt2_generators", "qp_pt2_stochastic",
            "qp_pt2_batched", "qp_sigma", "qp_davidson", "qp_energy", "qp_set_timing", "qp_last_timing",
-           "qp_set_split")
+           "qp_set_split", "qp_generator_order_noalloc")
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -113,6 +114,8 @@ def load():
     lib.qp_pt2_backward.restype = _I
     lib.qp_generator_order.argtypes = [_P, _P, _P, _I64, _I, _I, _P, _P]
     lib.qp_generator_order.restype = _I
+    lib.qp_generator_order_noalloc.argtypes = [_P, _P, _P, _I64, _I, _I, _P, _P]
+    lib.qp_generator_order_noalloc.restype = _I
     lib.qp_pt2_generators.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I64, _I64, _I, _P, _P, _P, _P, _P, _P]
     lib.qp_pt2_generators.restype = _I
     lib.qp_pt2_stochastic.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I64, ctypes.c_double, _I64, _I64, _I,

@@ -107,6 +107,11 @@ class Context:
         self._check(self._lib.qp_generator_order(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], coefs.shape[0],
                                                  flags, _ptr(order_out), _stream(self.device)))
 
+    def qp_generator_order_noalloc(self, dets, coefs, order_out, flags=0):
+        self._check(self._lib.qp_generator_order_noalloc(self._h, _ptr(dets), _ptr(coefs), dets.shape[0],
+                                                         coefs.shape[0], flags, _ptr(order_out),
+                                                         _stream(self.device)))
+
     def qp_pt2_generators(self, dets, coefs, E0, gens, n_select=0, flags=0, eps_out=None, sel_dets=None,
                           sel_e=None, n_sel=None, stats=None):
         self._check(self._lib.qp_pt2_generators(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], coefs.shape[0],

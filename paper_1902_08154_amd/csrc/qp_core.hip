@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1077,6 +1078,7 @@ struct Prepared {
 
 struct qp_ctx {
     int device = 0;
+    void *noalloc = nullptr;   // this device's no-allocation scratch (qp_generator_order_noalloc)
     std::string err;
     int n = 0;
     double *h = nullptr, *X = nullptr, *Y = nullptr, *Cj = nullptr, *CXj = nullptr, *Jm = nullptr, *Km = nullptr,
@@ -2100,6 +2102,31 @@ void jacobi_eigen(std::vector<double> &a, int m, std::vector<double> &w, std::ve
 
 extern "C" {
 
+// ---------------------------------------------------------------- no-allocation generator order
+// The scratch of qp_generator_order_noalloc: the weights sum_k c_Ik^2 of up to
+// QP_NOALLOC_MAX_DET determinants, then their index array (padded to a power
+// of two for the sort).  Each GPU holds its own copy, at its own address,
+// until the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress gives for that device (the array's name is a host-side
+// stand-in).
+static __device__ __align__(256) unsigned char noalloc_scratch[(size_t)QP_NOALLOC_MAX_DET * (8 + 4)];
+
+static std::mutex noalloc_mu;
+static void *noalloc_ptr[64] = {};   // per device ordinal
+
+// the array's address on `device`, which must be current; taken once per device
+static void *noalloc_setup(int device)
+{
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (device < 0 || device >= 64) return nullptr;
+    if (!noalloc_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess) return nullptr;
+        noalloc_ptr[device] = p;
+    }
+    return noalloc_ptr[device];
+}
+
 int qp_create(qp_ctx **ctx, int device)
 {
     if (!ctx) return QP_E_ARG;
@@ -2121,6 +2148,11 @@ int qp_create(qp_ctx **ctx, int device)
         return QP_E_HIP;
     }
     c->host_sc_n = 1;
+    c->noalloc = noalloc_setup(device);
+    if (!c->noalloc) {
+        qp_destroy(c);
+        return QP_E_HIP;
+    }
     *ctx = c;
     return QP_OK;
 }
@@ -2229,6 +2261,35 @@ int qp_generator_order(qp_ctx *c, const uint64_t *dets, const double *coefs, int
     rc = prepare(c, 0, dev_ints(c), dets, coefs, n_det, n_states, flags, st, P);
     if (rc != QP_OK) return rc;
     HIPCHK(c, hipMemcpyAsync(order_out, P.perm, sizeof(int32_t) * n_det, hipMemcpyDeviceToDevice, st));
+    return QP_OK;
+}
+
+int qp_generator_order_noalloc(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det,
+                               int n_states, int flags, int32_t *order_out, void *stream)
+{
+    (void)flags;
+    int rc = common_checks(c, dets, coefs, n_det, n_states, coefs);
+    if (rc != QP_OK) return rc;
+    if (n_det > 0 && !order_out) return fail(c, QP_E_ARG, "order_out is required");
+    if (n_det > QP_NOALLOC_MAX_DET) return fail(c, QP_E_ARG, "n_det exceeds QP_NOALLOC_MAX_DET");
+    if (n_det == 0) return QP_OK;
+    if (!c->noalloc) return fail(c, QP_E_HIP, "no-allocation scratch unavailable");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t Pw = pow2_at_least(n_det);   // <= QP_NOALLOC_MAX_DET, a power of two
+    double *w = (double *)c->noalloc;
+    int32_t *idx = (int32_t *)((unsigned char *)c->noalloc + sizeof(double) * QP_NOALLOC_MAX_DET);
+    // the same kernels as the ordering inside every sweep: every entry the sort
+    // reads is written first (weights of the determinants, indices with -1
+    // padding), so nothing of an earlier call's contents is used
+    hipLaunchKernelGGL(gen_weights, dim3(grid_for(Pw)), dim3(256), 0, st, coefs, n_det, n_states, w, Pw, idx);
+    switch ((c->n - 1) / 64 + 1) {
+    case 1: bitonic_sort(idx, Pw, GenCmp<1>{w, dets}, st); break;
+    case 2: bitonic_sort(idx, Pw, GenCmp<2>{w, dets}, st); break;
+    case 3: bitonic_sort(idx, Pw, GenCmp<3>{w, dets}, st); break;
+    default: bitonic_sort(idx, Pw, GenCmp<4>{w, dets}, st); break;
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(order_out, idx, sizeof(int32_t) * n_det, hipMemcpyDeviceToDevice, st));
     return QP_OK;
 }
 
