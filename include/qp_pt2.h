@@ -70,6 +70,10 @@ extern "C" {
 #define QP_MAX_ORB       256
 #define QP_MAX_SYSTEMS   4096
 #define QP_NOALLOC_MAX_DET (1 << 18)   /* largest n_det of qp_generator_order_noalloc */
+#define QP_SPLIT_NEVER   0
+#define QP_SPLIT_AUTO    1
+#define QP_SPLIT_ALWAYS  2
+#define QP_SPLIT_MIN_VIRT 100              /* qp_set_split's automatic threshold */
 
 /* qp_pt2 flags */
 #define QP_FLAG_FINGERPRINT  1  /* also compute stats.fingerprint of the alpha set */
@@ -395,16 +399,19 @@ int qp_last_timing(qp_ctx *ctx, double *out_ms);
 /*
  * qp_set_split -- how sweeps (qp_pt2, qp_pt2_backward, qp_pt2_generators,
  * qp_pt2_batched and the rounds of qp_pt2_stochastic) divide their cells
- * between kernels.  enable = 1 (the default): the hole-pair batches that no
- * determinant touches in every cell go to the clean-cell kernel, in
+ * between kernels.  A split sweep gives the hole-pair batches that no
+ * determinant touches in every cell to the clean-cell kernel, in
  * hole-pair-major order, for the cells no other determinant touches, and to
  * the split-correction kernel for the rest; the dense kernel keeps the other
- * batches.  enable = 0: the dense kernel takes every batch.  Both give the
- * same alpha set, counts and selection, and energies and gradients equal to
- * rounding (the sums run in another order).  An adjoint call with
- * QP_FLAG_FINGERPRINT is not split.  No device work.  Errors: QP_E_ARG.
+ * batches.  mode = QP_SPLIT_AUTO (the default) splits a system whose batches
+ * hold at least QP_SPLIT_MIN_VIRT particles per spin (n_orb minus the larger
+ * electron count), QP_SPLIT_ALWAYS every system, QP_SPLIT_NEVER none.  All
+ * give the same alpha set, counts and selection, and energies and gradients
+ * equal to rounding (the sums run in another order).  An adjoint call with
+ * QP_FLAG_FINGERPRINT is not split.  No device work.  Errors: QP_E_ARG (an
+ * unknown mode).
  */
-int qp_set_split(qp_ctx *ctx, int enable);
+int qp_set_split(qp_ctx *ctx, int mode);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,9 @@ QP_FLAG_FINGERPRINT = 1
 QP_FLAG_NOCHECK = 2
 QP_FLAG_REUSE_INTEGRALS = 4
 QP_NOALLOC_MAX_DET = 1 << 18
+QP_SPLIT_NEVER = 0
+QP_SPLIT_AUTO = 1
+QP_SPLIT_ALWAYS = 2
 QP_SIGMA_S2 = 8
 QP_SIGMA_REUSE = 16
 QP_MAX_STATES = 4

@@ -171,8 +171,14 @@ class Context:
         self._check(self._lib.qp_last_timing(self._h, out))
         return tuple(float(out[i]) for i in range(5))
 
-    def qp_set_split(self, enable: bool):
-        self._check(self._lib.qp_set_split(self._h, 1 if enable else 0))
+    def qp_set_split(self, mode):
+        """mode: _lib.QP_SPLIT_NEVER / AUTO / ALWAYS; True and False stand for
+        ALWAYS and NEVER."""
+        if mode is True:
+            mode = _lib.QP_SPLIT_ALWAYS
+        elif mode is False:
+            mode = _lib.QP_SPLIT_NEVER
+        self._check(self._lib.qp_set_split(self._h, int(mode)))
 
     # ---------------------------------------------------------- conveniences
     def _inputs(self, dets, coefs, E0=None):

@@ -453,6 +453,68 @@ __global__ void make_coff(const int64_t *offs, int64_t n_det, int nchunk, const 
     if (g == n_det) { coff[g] = *total; sc->coarse_total = (unsigned long long)*total; }
 }
 
+// ---------------------------------------------------------------- batch marks and fine counts
+// One thread per generator of the call, over its coarse list.  An entry J
+// lacking dc of the generator's electrons lacks m = dc - |holes of J among
+// the batch's| electrons outside a batch's hole set.  The fine filter of a
+// batch keeps the entries with m <= 2, so their number over every batch
+// follows from dc alone: dc <= 2 reaches every batch; dc = 3 the 3 single
+// batches of its holes and the pairs holding one of them; dc = 4 the 6 pairs
+// inside its holes.  An entry with m = 0 (dc = 1: every pair holding its
+// hole; dc = 2: the pair of its holes) touches every cell of a batch, which
+// then stays with the dense kernel: split sweeps mark those pair batches,
+// bit nel + pair of the generator rank's words (the dense kernel's batch
+// numbering).
+template <int NINT>
+__global__ void split_mark(const uint64_t *dets, const int32_t *perm, const int32_t *gen_rank, int64_t n_gen,
+                           int nup, int ndn, const int64_t *coff, const CoarseEnt *cent, int nbw, uint32_t *keep,
+                           unsigned long long *fine_total)
+{
+    const int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int nel = nup + ndn;
+    const int64_t np = (int64_t)nel * (nel - 1) / 2;
+    const int64_t np3 = (int64_t)(nel - 3) * (nel - 4) / 2;   // pairs free of 3 given holes
+    unsigned long long fine = 0;
+    if (pos < n_gen) {
+        const int64_t g = gen_rank ? (int64_t)gen_rank[pos] : pos;
+        const uint64_t *I = dets + (int64_t)perm[g] * 2 * NINT;
+        // hole index over the occupied orbitals, up spin first
+        auto hidx = [&](int code) {
+            const int s = code >> 8, p = code & 255;
+            int c = s ? nup : 0;
+            for (int w = 0; w < NINT; ++w) {
+                const uint64_t x = I[s * NINT + w];
+                if (64 * w + 64 <= p) c += __popcll(x);
+                else if (64 * w <= p) c += __popcll(x & ((1ull << (p - 64 * w)) - 1ull));
+            }
+            return c;
+        };
+        auto mark = [&](int a, int b) {   // the pair of hole indices a < b
+            const int bb = nel + b * (b - 1) / 2 + a;
+            uint32_t *w = keep + g * nbw + (bb >> 5);
+            *w |= 1u << (bb & 31);
+        };
+        for (int64_t e = coff[g]; e < coff[g + 1]; ++e) {
+            const CoarseEnt ce = cent[e];
+            int dc = 0;
+            for (int t = 0; t < 4; ++t) dc += ce.D[t] != 0xFFFF ? 1 : 0;
+            if (dc <= 2) fine += (unsigned long long)(nel + np);
+            else if (dc == 3) fine += (unsigned long long)(3 + np - np3);
+            else fine += 6ull;
+            if (keep && dc == 1) {
+                const int i = hidx(ce.D[0]);
+                for (int j = 0; j < nel; ++j)
+                    if (j != i) mark(i < j ? i : j, i < j ? j : i);
+            } else if (keep && dc == 2) {
+                const int i = hidx(ce.D[0]), j = hidx(ce.D[1]);
+                mark(i < j ? i : j, i < j ? j : i);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) fine += __shfl_xor(fine, o);
+    if ((threadIdx.x & 63) == 0 && fine) atomicAdd(fine_total, fine);
+}
+
 // ---------------------------------------------------------------- hole-pair lists
 // The clean-cell kernel's items in hole-pair-major order.  Occupation bitsets
 // over the call's generators: bits[(s n + p) nw + w], bit i of word w set when
@@ -1049,7 +1111,7 @@ enum BufId {
     B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFE, B_DEFS, B_DEFC, B_DEFN, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
     B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_GENR,
     // split sweep: hole-pair lists and the clean-cell kernel's slots
-    B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP, B_LCONN, B_LDC, B_LTAKEN,
+    B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP, B_LCONN, B_LDC, B_LKEEP,
     // integral layouts of a system of a batched call
     B_LH, B_LX, B_LY, B_LCJ, B_LXJ, B_LJM, B_LKM, B_LJK,
     // Davidson
@@ -1107,7 +1169,7 @@ struct qp_ctx {
     size_t host_stage_bytes = 0;
     bool timing = false;
     bool timed = false;
-    bool split_enabled = true;     // forward sweeps split clean cells off (qp_set_split)
+    int split_mode = QP_SPLIT_AUTO;   // which sweeps split clean cells off (qp_set_split)
     // call start, dense sweep start, general kernel start, sweep end, call end
     // [5]: between the dense kernel and the clean-cell kernel
     hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -1781,7 +1843,13 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         // split sweep (forward): hole-pair lists for the clean-cell kernel
         // (a fingerprinted adjoint is not split: the adjoint kernels have no
         // fingerprint variant)
-        r.split = r.swept && nel >= 2 && c->split_enabled && !(bwd && fp);
+        // (auto: batches of at least QP_SPLIT_MIN_VIRT particles per spin, below
+        // which the clean-cell kernel's per-batch set-up outweighs its cell
+        // loop: n_orb 64, 10+10 electrons, 10^4 determinants forward 17.0 ms
+        // unsplit, 28.3 ms split; n_orb 128, 14+14, 10^5: 1.41 s, 1.28 s)
+        const int vmin = n - std::max(r.P.nup, r.P.ndn);
+        r.split = r.swept && nel >= 2 && !(bwd && fp) &&
+                  (c->split_mode == QP_SPLIT_ALWAYS || (c->split_mode == QP_SPLIT_AUTO && vmin >= QP_SPLIT_MIN_VIRT));
         if (r.split) {
             const int np = nel * (nel - 1) / 2;
             const int n_keys = n * n + n * (n - 1);
@@ -1799,8 +1867,8 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             unsigned long long *lfp = (unsigned long long *)scratch(c, s, B_LFP, sizeof(unsigned long long) * n_g);
             unsigned long long *lconn = (unsigned long long *)scratch(c, s, B_LCONN, sizeof(unsigned long long) * n_g);
             double *ldc = bwd ? (double *)scratch(c, s, B_LDC, sizeof(double) * tot * ns) : nullptr;
-            uint32_t *ltaken = bwd ? (uint32_t *)scratch(c, s, B_LTAKEN, sizeof(uint32_t) * n_det * r.nbw) : nullptr;
-            if (!bits || !kcnt || !koff || !kbs || !kpos || !leps || !lS || !lcnt || !lfp || !lconn || (bwd && (!ldc || !ltaken)))
+            uint32_t *lkeep = (uint32_t *)scratch(c, s, B_LKEEP, sizeof(uint32_t) * n_det * r.nbw);
+            if (!bits || !kcnt || !koff || !kbs || !kpos || !leps || !lS || !lcnt || !lfp || !lconn || !lkeep || (bwd && !ldc))
                 return fail(c, QP_E_OOM, "device allocation failed (clean-cell lists)");
             HIPCHK(c, hipMemsetAsync(lcnt, 0, sizeof(unsigned long long) * n_g, st));
             HIPCHK(c, hipMemsetAsync(lfp, 0, sizeof(unsigned long long) * n_g, st));
@@ -1828,10 +1896,23 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
             a.lean_fp = lfp;
             a.lean_conn = lconn;
             a.lean_dc = ldc;
-            a.taken_bits = ltaken;
-            if (bwd) HIPCHK(c, hipMemsetAsync(ltaken, 0, sizeof(uint32_t) * n_det * r.nbw, st));
+            a.split_keep = lkeep;
+            HIPCHK(c, hipMemsetAsync(lkeep, 0, sizeof(uint32_t) * n_det * r.nbw, st));
             r.n_pairs = np;
             litems[s] = tot;
+        }
+        // the fine filter's entries over every batch, and (split sweeps) the
+        // pair batches the dense kernel keeps
+        if (r.swept) {
+            const int gb = (int)((n_g + 255) / 256);
+            uint32_t *keep = r.split ? a.split_keep : nullptr;
+            switch (r.nint) {
+            case 1: hipLaunchKernelGGL(split_mark<1>, dim3(gb), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, r.P.nup, r.P.ndn, r.P.coff, r.P.cent, r.nbw, keep, &r.P.sc->fine_total); break;
+            case 2: hipLaunchKernelGGL(split_mark<2>, dim3(gb), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, r.P.nup, r.P.ndn, r.P.coff, r.P.cent, r.nbw, keep, &r.P.sc->fine_total); break;
+            case 3: hipLaunchKernelGGL(split_mark<3>, dim3(gb), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, r.P.nup, r.P.ndn, r.P.coff, r.P.cent, r.nbw, keep, &r.P.sc->fine_total); break;
+            default: hipLaunchKernelGGL(split_mark<4>, dim3(gb), dim3(256), 0, st, x.dets, r.P.perm, r.gen_rank, n_g, r.P.nup, r.P.ndn, r.P.coff, r.P.cent, r.nbw, keep, &r.P.sc->fine_total); break;
+            }
+            HIPCHK(c, hipGetLastError());
         }
     }
 
@@ -2815,11 +2896,13 @@ int qp_last_timing(qp_ctx *c, double *out_ms)
     return QP_OK;
 }
 
-int qp_set_split(qp_ctx *c, int enable)
+int qp_set_split(qp_ctx *c, int mode)
 {
     if (!c) return QP_E_ARG;
     c->err.clear();
-    c->split_enabled = enable != 0;
+    if (mode != QP_SPLIT_NEVER && mode != QP_SPLIT_AUTO && mode != QP_SPLIT_ALWAYS)
+        return fail(c, QP_E_ARG, "split mode must be QP_SPLIT_NEVER, QP_SPLIT_AUTO or QP_SPLIT_ALWAYS");
+    c->split_mode = mode;
     return QP_OK;
 }
 

@@ -365,7 +365,7 @@ struct SweepArgs {
     unsigned long long *lean_fp;   // [n_gen] fingerprint sums (atomics)
     unsigned long long *lean_conn; // [n_gen] connections of flagged cells (atomics)
     double *lean_dc;          // [n_gen][n_pairs][ns]  adjoint: the generator's dc share per batch
-    uint32_t *taken_bits;     // [n_det][nbw]  adjoint: batches the clean-cell kernel takes (bit nel + pair)
+    uint32_t *split_keep;     // [n_det][nbw]  split sweeps: pair batches the dense kernel keeps (bit nel + pair)
     unsigned long long *fine_total;   // fine-filter entries over the batches evaluated (atomics)
 };
 
@@ -383,13 +383,11 @@ struct SweepArgs {
 // same on every lane.
 template <class Sys>
 __device__ bool split_flags(const Sys &a, int64_t g, int n, int nup, int ndn, bool os, int rs, int hc0, int hc1,
-                            const uint16_t *sVidx, uint32_t *rowF, uint32_t *colF, int lane,
-                            unsigned *nfine = nullptr)
+                            const uint16_t *sVidx, uint32_t *rowF, uint32_t *colF, int lane)
 {
     const int64_t cbeg = a.coff[g], cend = a.coff[g + 1];
     const int nv0 = n - nup, nv1 = n - ndn;
     bool m0 = false;
-    unsigned nf = 0;
     for (int64_t base = cbeg; base < cend; base += 64) {
         const int64_t e = base + lane;
         int m = 3;
@@ -406,7 +404,6 @@ __device__ bool split_flags(const Sys &a, int64_t g, int n, int nup, int ndn, bo
             }
             m = dc - __popc(inmask);
         }
-        if (nfine) nf += (unsigned)__popcll(__ballot(m <= 2));
         if (m > 2) continue;
         if (m == 0) { m0 = true; continue; }
         int ner = 0, nec = 0, er[4] = {0, 0, 0, 0}, ec[4] = {0, 0, 0, 0};
@@ -454,7 +451,6 @@ __device__ bool split_flags(const Sys &a, int64_t g, int n, int nup, int ndn, bo
             }
         }
     }
-    if (nfine) *nfine = nf;
     return __ballot(m0) == 0ull;
 }
 

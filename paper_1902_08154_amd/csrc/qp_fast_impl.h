@@ -206,7 +206,6 @@ inline size_t lds_bytes(int n, int nvm, int ns, bool bwd, int rscap, int cscap)
     add(2 * n);                     // occ
     add(2 * n);                     // virt
     add(2 * n);                     // cnt
-    add(4 * 16);                    // split sweep flags
     return b + 16;
 }
 
@@ -261,7 +260,6 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
         uint8_t *sOcc = carve<uint8_t>(lds, off, 2 * n);
         uint8_t *sVirt = carve<uint8_t>(lds, off, 2 * n);
         uint8_t *sCnt = carve<uint8_t>(lds, off, 2 * n);
-        uint32_t *sSplitF = carve<uint32_t>(lds, off, 16);   // split sweep: row, column flags
 
         double E0[NS], gup[NS], cI[NS], invm[NS];
 #pragma unroll
@@ -313,7 +311,6 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
         uint64_t fpsum = 0;
         double mind = __builtin_inf();
         double vtot = 0.0;
-        uint64_t nfine_item = 0;   // fine-filter entries of the item's batches
 
         for (int b = q; b < nb; b += Q) {
             // ---------------------------------------------------- batch
@@ -355,18 +352,9 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
             const int hro = type == BT_OS ? (rs == 0 ? h2 : h1) : (type == BT_SS ? h2 : -1);
 
             // split sweep: a hole-pair batch that no determinant touches in every
-            // cell belongs to the clean-cell and split-correction kernels
-            if (!BWD && a.split && type != BT_SINGLE) {
-                if (lane < 16) sSplitF[lane] = 0u;
-                __syncthreads();
-                const bool taken = split_flags(a, g, n, a.nup, a.ndn, type == BT_OS, rs, hc0, hc1, sVidx, sSplitF,
-                                               sSplitF + 8, lane);
-                __syncthreads();
-                if (taken) continue;
-            }
-            // the adjoint runs the clean-cell kernel first, which marks the
-            // batches it takes
-            if (BWD && a.split && type != BT_SINGLE && ((a.taken_bits[g * a.nbw + (b >> 5)] >> (b & 31)) & 1u))
+            // cell belongs to the clean-cell and split-correction kernels; the
+            // batches marked before the sweep stay here
+            if (a.split && type != BT_SINGLE && !((a.split_keep[g * a.nbw + (b >> 5)] >> (b & 31)) & 1u))
                 continue;
 
             // particle tables: Fock-diagonal part of H_alpha,alpha and phase
@@ -440,7 +428,6 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
                 nfine += __popcll(mask);
             }
             if (nfine > FCAP) slow = true;
-            nfine_item += (uint64_t)nfine;
             __syncthreads();
 
             // ------------------------------------------ classify corrections
@@ -1374,7 +1361,6 @@ void fast_kernel(const SweepArgs *__restrict__ sys, const int64_t *__restrict__ 
             a.cnt_item[slot] = (uint32_t)cc;
             if (a.fp_item) a.fp_item[slot] = ff;
             a.conn_item[slot] = (uint32_t)cn;
-            if (!BWD && nfine_item && a.fine_total) atomicAdd(a.fine_total, (unsigned long long)nfine_item);
             // non-negative doubles order like their bit patterns; most items
             // cannot lower the minimum, so read before the atomic
             const unsigned long long mb = (unsigned long long)__double_as_longlong(mind);

@@ -216,13 +216,6 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
     double *sDH = reinterpret_cast<double *>(lds);
     if (BWD)
         for (int p = lane; p < QPD_MAX_ORB; p += WAVE) sDH[p] = 0.0;
-    // fine-filter entries of the batches this wave takes (forward only: the
-    // adjoint sweeps the same batches again)
-    unsigned long long fine_acc = 0;
-    auto flush_fine = [&](ConstSys &s) {
-        if (!BWD && lane == 0 && fine_acc && s.fine_total) atomicAdd(s.fine_total, fine_acc);
-        fine_acc = 0;
-    };
     auto flush_dh = [&](ConstSys &s) {
         if (!BWD) return;
         for (int p = lane; p < s.n; p += WAVE) {
@@ -237,7 +230,6 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
             flush_dh(((ConstSys *)sys)[sid]);
-            flush_fine(((ConstSys *)sys)[sid]);
             while (it >= item_end[sid]) ibase = item_end[sid++];
             K = -1;
         }
@@ -336,17 +328,8 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         // ------------------------------------------------ which cells are clean
         // the flags of the dense kernel's corrections (split_flags); a batch
         // with a determinant that touches every cell is not split
-        unsigned nfl = 0;
-        const bool take =
-            split_flags(a, g, n, nup, ndn, type == BT_OS, rs, hc0, hc1, sVidx, sRowF, sColF, lane, &nfl);
+        const bool take = split_flags(a, g, n, nup, ndn, type == BT_OS, rs, hc0, hc1, sVidx, sRowF, sColF, lane);
         __syncthreads();
-        if (take) fine_acc += nfl;
-        // the adjoint's dense kernel runs after this one and leaves out what it
-        // takes
-        if (BWD && take && lane == 0) {
-            const int b = a.nel + pb;
-            atomicOr(&a.taken_bits[g * a.nbw + (b >> 5)], 1u << (b & 31));
-        }
         if (!take) {
             if (lane < NS) {
                 a.lean_eps[slot * NS + lane] = 0.0;
@@ -706,7 +689,6 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
     if (total > 0) {
         flush_min(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1].min_delta_bits);
         flush_dh(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1]);
-        flush_fine(((ConstSys *)sys)[sid < n_sys ? sid : n_sys - 1]);
     }
 }
 

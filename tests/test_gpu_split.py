@@ -1,9 +1,11 @@
-"""GPU parity of the split sweep: the clean-cell kernel takes the cells of a
-hole-pair batch that no other determinant touches, in hole-pair-major order;
-the dense kernel (and the general kernel for batches it hands over) takes the
-rest.  Every case is checked against the oracle (|A|, fingerprint and
-selection bit-exact; E_PT2, S, eps_I within rounding) and against the same
-call with the split switched off."""
+"""GPU parity of the split sweep, forced on these small systems (below the
+automatic threshold): the clean-cell kernel takes the cells of a hole-pair
+batch that no other determinant touches, in hole-pair-major order; the
+split-correction kernel the batch's other cells; the dense kernel (and the
+general kernel for batches it hands over) the remaining batches.  Every
+case is checked against the oracle (|A|, fingerprint and selection
+bit-exact; E_PT2, S, eps_I within rounding) and against the same call with
+the split switched off."""
 import numpy as np
 import pytest
 
@@ -19,7 +21,7 @@ def ctx():
     from paper_1902_08154_amd.api import Context
     c = Context(0)
     yield c
-    c.qp_set_split(True)
+    c.qp_set_split(1)   # QP_SPLIT_AUTO, the default
     c.close()
 
 
@@ -175,3 +177,33 @@ def test_split_backward_n256_top_orbitals(ctx):
     c[:, 0] += 3.0
     c /= np.linalg.norm(c, axis=1, keepdims=True)
     _check_bwd(ctx, synth.System("bn256_top", 2561, n, 4, 4, h, eri, dets, c))
+
+
+def test_fine_filter_count(ctx):
+    """stats.n_fine: over every hole batch of every generator, the coarse
+    entries J (degree <= 4) lacking at most two of the generator's electrons
+    outside the batch's holes, counted here from the determinants: J lacking
+    dc electrons reaches all nel + npairs batches when dc <= 2, the 3 single
+    batches of its holes and the pairs holding one of them when dc = 3, and
+    the 6 pairs inside its holes when dc = 4."""
+    s = synth.make_system("fine", 91, 40, 6, 5, 400, n_states=1)
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    nel = s.n_up + s.n_dn
+    npair = nel * (nel - 1) // 2
+    d = s.dets.reshape(s.n_det, -1)
+    pc = np.vectorize(lambda x: bin(int(x)).count("1"), otypes=[np.int64])
+    want = 0
+    for i in range(s.n_det):
+        dc = pc(d[i][None, :] & ~d).sum(axis=1)
+        for c in dc[dc > 0]:
+            if c <= 2:
+                want += nel + npair
+            elif c == 3:
+                want += 3 + npair - (nel - 3) * (nel - 4) // 2
+            elif c == 4:
+                want += 6
+    for split in (True, False):
+        ctx.qp_set_split(split)
+        g = run_gpu(ctx, s, E0, n_select=0)
+        assert g["stats"]["n_fine"] == want, (split, g["stats"]["n_fine"], want)
+    ctx.qp_set_split(True)
