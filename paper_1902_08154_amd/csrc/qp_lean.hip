@@ -574,13 +574,23 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
             }
             ncell += okc ? (uint32_t)(te - tb) : 0u;
         };
-        int td = 0, tf = 0;
+        int td = 0, tf = 0;   // same spin: the chunk's rows inside its span are [td, tf)
         for (int c0 = 0; os ? c0 < nc : c0 + 1 < nc; c0 += WAVE) {
             const int c = c0 + lane;
             const bool okc = c < nc && !bit_of(sColF, c);
             if (!os) {
-                while (td < nrow && (int)(sRi[td] >> 8) <= c0) ++td;
-                while (tf < nrow && (int)(sRi[tf] >> 8) < c0 + WAVE) ++tf;
+                // the rows are in increasing virtual index: count, across the
+                // lanes, those at or below the chunk's first column and those
+                // below its end
+                int nd = 0, nf = 0;
+                for (int t0 = 0; t0 < nrow; t0 += WAVE) {
+                    const int t = t0 + lane;
+                    const int r = t < nrow ? (int)(sRi[t] >> 8) : 1 << 20;
+                    nd += __popcll(__ballot(r <= c0));
+                    nf += __popcll(__ballot(r < c0 + WAVE));
+                }
+                td = nd;
+                tf = nf;
             }
             if (__ballot(okc) == 0ull || td >= nrow) continue;
             // a lane past the last column reads a valid column: the last one, or
