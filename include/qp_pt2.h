@@ -84,8 +84,9 @@ extern "C" {
 #define QP_SIGMA_REUSE      16  /* qp_sigma: the determinants are those of the
                                    previous qp_sigma call on this context (same
                                    dets pointer and n_det, contents unchanged, no
-                                   qp_set_integrals since): its generator order
-                                   and coarse lists are reused                   */
+                                   qp_set_integrals since, same stream): its
+                                   generator order and coarse lists are reused;
+                                   otherwise they are prepared again            */
 #define QP_FLAG_REUSE_INTEGRALS 4 /* qp_pt2_batched: keep a system's integral layouts
                                      from the previous batched call when its h and
                                      eri_packed pointers and n_orb are the same, and
@@ -141,9 +142,13 @@ const char *qp_last_error(const qp_ctx *ctx);
  * two-electron integrals", Algorithm 1).
  *   h          device [n_orb][n_orb], symmetric.
  *   eri_packed device, length P(P+1)/2, layout above.
- * The context builds its own device layouts from these (dense per-hole-pair
- * blocks, about 1.5x the packed size plus n^3 tables) and does not keep the
- * caller's pointers: the caller may free them once the stream has synchronised.
+ * The context builds its own device layouts from these and does not keep the
+ * caller's pointers: a dense block per hole pair, n(n+1)/2 opposite-spin
+ * blocks of n^2 and (n(n-1)/2)^2 same-spin entries, plus 2 n^3 + 4 n^2 tables
+ * (doubles): at n_orb = 256 about 26 GB, six times the packed array.
+ * Host synchronisation: the call synchronises `stream` twice, before it
+ * releases the previous layouts and after it has built the new ones; the
+ * caller may free h and eri_packed when it returns.
  * Replaces any previous integrals.  Errors: QP_E_ARG, QP_E_NORB, QP_E_OOM,
  * QP_E_HIP.
  */
@@ -169,8 +174,11 @@ int qp_set_integrals(qp_ctx *ctx, const double *h, const double *eri_packed, int
  *   stats     qp_pt2_stats [1]                    (optional, NULL)
  *   eps_gen   double [n_states][n_det]: eps_I of determinant I (caller's index)
  *                                                 (optional, NULL)
- * Host synchronisation: the call synchronises `stream` once (to size the
- * coarse-filter lists and to check validation and overflow results).
+ * Host synchronisation: the call synchronises `stream` up to three times:
+ * after the preparation (coarse-filter list sizes and input checks), after
+ * the dense kernel when it handed batches over (their count), and before
+ * the selection sort when n_select > 0.  A call that needs more pinned
+ * host staging than earlier calls first waits for the device.
  * Errors: QP_E_ARG, QP_E_STATES, QP_E_NOINT, QP_E_NORB, QP_E_ELEC, QP_E_DUP,
  * QP_E_OOM, QP_E_HIP, QP_E_OVERFLOW.
  */
@@ -337,8 +345,8 @@ int qp_pt2_batched(qp_ctx *ctx, int n_sys, const qp_system *sys, int with_backwa
  *   U, W  device double [n_vec][n_det] (W overwritten)
  * Matrix elements by the Slater-Condon rules as in qp_pt2.  Synchronises
  * once (coarse-list sizes) to prepare the determinant space; with
- * QP_SIGMA_REUSE and the same dets pointer, n_det and integrals as the
- * previous qp_sigma call, the preparation is reused and the call only
+ * QP_SIGMA_REUSE and the same dets pointer, n_det, integrals and stream as
+ * the previous qp_sigma call, the preparation is reused and the call only
  * launches the sigma kernel.  Errors: QP_E_ARG, QP_E_NOINT, QP_E_NORB,
  * QP_E_ELEC, QP_E_DUP, QP_E_OOM, QP_E_HIP.
  */

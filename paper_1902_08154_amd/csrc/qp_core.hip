@@ -1155,8 +1155,11 @@ struct qp_ctx {
     size_t lds_per_cu = 163840;
     uint64_t ints_gen = 0;         // bumped by every qp_set_integrals
     // the sigma-build's prepared determinant space, kept in a slot of its own
-    // for QP_SIGMA_REUSE: valid while dets, n_det and the integrals match
+    // for QP_SIGMA_REUSE: valid while dets, n_det, the integrals and the stream
+    // match (the preparation's last kernels run after its host sync, so only
+    // later work on the same stream is ordered after them)
     bool sig_valid = false;
+    hipStream_t sig_stream = nullptr;
     const uint64_t *sig_dets = nullptr;
     int64_t sig_n_det = 0;
     uint64_t sig_gen = 0;
@@ -2615,7 +2618,7 @@ int qp_sigma(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_vec, const do
     // QP_SIGMA_REUSE can find it again
     const int slot = QP_MAX_SYSTEMS;
     const bool reuse = (flags & QP_SIGMA_REUSE) && c->sig_valid && c->sig_dets == dets && c->sig_n_det == n_det &&
-                       c->sig_gen == c->ints_gen;
+                       c->sig_gen == c->ints_gen && c->sig_stream == st;
     if (!reuse) {
         c->sig_valid = false;
         // the generator order does not matter here: every weight is 1
@@ -2628,6 +2631,7 @@ int qp_sigma(qp_ctx *c, const uint64_t *dets, int64_t n_det, int n_vec, const do
         c->sig_dets = dets;
         c->sig_n_det = n_det;
         c->sig_gen = c->ints_gen;
+        c->sig_stream = st;
     }
     launch_sigma(I, c->sig_P, dets, n_det, n_vec, (flags & QP_SIGMA_S2) != 0, U, W, st);
     HIPCHK(c, hipGetLastError());
