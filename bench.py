@@ -70,7 +70,7 @@ def clean_ops_per_alpha(ns, adjoint):
     return 15.0 * ns + ((4.0 * ns + 2.0) if adjoint else 0.0)
 
 
-def cpu_baseline(s, E0, n_gen, visit_cap=0):
+def cpu_baseline(s, E0, n_gen, visit_cap=0, threads=0):
     """The oracle's per-generator sweep on n_gen generators evenly spaced in
     generator order; visit_cap > 0 bounds each to its first visit_cap
     excitations (enumeration order), for workloads whose generators take
@@ -80,11 +80,11 @@ def cpu_baseline(s, E0, n_gen, visit_cap=0):
     order = np.argsort(rank)
     pick = order[np.linspace(0, s.n_det - 1, n_gen).astype(np.int64)]
     t0 = time.perf_counter()
-    r = oracle.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, pick, visit_cap=visit_cap)
+    r = oracle.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, pick, visit_cap=visit_cap, threads=threads)
     dt = time.perf_counter() - t0
     what = f"the first {visit_cap} excitations of each of " if visit_cap else ""
     return dict(value=float(r.count.sum()) / dt, unit="alpha/s",
-                cores=int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))),
+                cores=threads or int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))),
                 kind="oracle",
                 sample=f"{what}{n_gen} generators evenly spaced in generator order "
                        f"({int(r.count.sum())} alpha, {dt:.1f} s)")
@@ -390,6 +390,11 @@ def main():
         cap = 1000000 if s.n_orb >= 128 else 0
         cpu = cpu_baseline(s, E0.cpu().numpy(), threads if cap else 12 * threads, visit_cap=cap)
         log(f"cpu baseline: {cpu}")
+        # the same oracle on one core: one generator's first 5x10^5 excitations
+        # (a whole-sweep-shaped sample takes the same time per alpha)
+        extra["cpu_baseline_1core"] = cpu_baseline(s, E0.cpu().numpy(), 1, visit_cap=cap // 2 if cap else 0,
+                                                   threads=1)
+        log(f"cpu baseline, 1 core: {extra['cpu_baseline_1core']}")
 
     config = {"workload": s.name, "n_orb": s.n_orb, "n_up": s.n_up, "n_dn": s.n_dn, "n_det": s.n_det,
               "n_states": ns, "n_select": s.n_select, "seed": s.seed, "n_alpha": stats["n_alpha"],

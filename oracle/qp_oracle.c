@@ -40,6 +40,7 @@
  *
  * Build:  gcc -O2 -fPIC -shared -fopenmp -ffp-contract=off
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -848,7 +849,8 @@ static void gen_visit(void *vctx, const u64 *a)
  * det indices), plus per-generator |A_I|, fingerprint sum and S.  Optionally
  * dumps owned alpha with |e~| >= dump_thr (up to dump_cap per generator).
  * visit_cap > 0 stops each generator after that many excitations (a bounded
- * timing sample; its sums are then partial).
+ * timing sample; its sums are then partial).  nthreads > 0 sets the OpenMP
+ * team's size (0: the runtime's default).
  * OpenMP over the listed generators; each generator is summed sequentially
  * (the enumeration order of for_each_excitation), so results are
  * deterministic.
@@ -858,7 +860,7 @@ int orc_eps_generators(int n, int nint, const double *h, const double *eri_packe
                        const int64_t *gens, int64_t n_gen,
                        double *eps, double *S, int64_t *count, u64 *fp,
                        double dump_thr, int64_t dump_cap, u64 *dump_dets, double *dump_e,
-                       double *dump_key, int64_t *dump_n, int64_t visit_cap)
+                       double *dump_key, int64_t *dump_n, int64_t visit_cap, int nthreads)
 {
     if (ns < 1 || ns > ORC_MAX_STATES) return -1;
     orc_ints I = {n, nint, h, eri_packed};
@@ -880,7 +882,7 @@ int orc_eps_generators(int n, int nint, const double *h, const double *eri_packe
         }
     }
     int fail = 0;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
     for (int64_t g = 0; g < n_gen; ++g) {
         int64_t gi = gens[g];
         const u64 *dg = dets + (size_t)gi * 2 * nint;
