@@ -84,6 +84,10 @@ def check_full(g, o, s, n_select):
     assert st["n_alpha"] == o.n_alpha
     assert st["fingerprint"] == o.fp
     assert st["overflow"] == 0
+    # the observed errors, printed with -s
+    rel = lambda a, b: float(np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(b), 1e-300)))
+    print(f"  {getattr(s, 'name', '?')}: max rel err E_PT2 {rel(g['e_pt2'], o.e_pt2):.2e}, "
+          f"S {rel(st['S'], o.S):.2e}, eps_I {rel(g['eps_gen'], o.eps_gen) if 'eps_gen' in g else float('nan'):.2e}")
     for k in range(s.n_states):
         assert abs(g["e_pt2"][k] - o.e_pt2[k]) <= e_tolerance(o, k), (k, g["e_pt2"], o.e_pt2)
         assert abs(st["S"][k] - o.S[k]) <= s_tolerance(o, k), (k, st["S"], o.S)
