@@ -184,7 +184,7 @@ namespace qplean {
 template <int NINT, int NS, bool BWD, bool FP>
 constexpr int lean_waves()
 {
-    if (BWD) return NS == 1 ? 4 : (NS == 2 ? 3 : 2);
+    if (BWD) return NS <= 2 ? 4 : 3;
     return FP && NS == 4 ? 2 : (FP || NS >= 3 ? 3 : 4);
 }
 
@@ -405,10 +405,11 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
                 sq[k] = fma(t, rc, sq[k]);
                 if (BWD) v = fma(t * gc[k], rc, v);
                 mind = min_abs(mind, delta);
-                tsel = k == 0 ? cw[0] * t : fma(cw[k], t, tsel);
+                if (!BWD) tsel = k == 0 ? cw[0] * t : fma(cw[k], t, tsel);
             }
             if (FP && live) fpsum += fold(pa, pb);
-            return fabs(tsel) >= thr;
+            // (the adjoint selects nothing)
+            return !BWD && fabs(tsel) >= thr;
         };
 
         // The cell loop.  Lanes run over a chunk of 64 columns (virtual indices
@@ -501,6 +502,7 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
         };
         // list the lanes of row t whose cell passed the pretest
         auto note = [&](bool cnd, int t, uint32_t &ncand) {
+            if (BWD) return;
             const uint64_t mk = __builtin_amdgcn_ballot_w64(cnd);
             if (mk) {
                 if (cnd) sCl[ncand + __popcll(mk & ((1ull << lane) - 1ull))] = (uint32_t)t | ((uint32_t)lane << 16);
