@@ -63,7 +63,7 @@ def _load():
         lib.orc_s2_matrix.argtypes = [_I, _I, _P, _I64, _P]
         lib.orc_eps_generators.restype = _I
         lib.orc_eps_generators.argtypes = [_I, _I, _P, _P, _P, _P, _I64, _I, _P, _P, _I64,
-                                           _P, _P, _P, _P, _D, _I64, _P, _P, _P, _P, _I64, _I]
+                                           _P, _P, _P, _P, _D, _I64, _P, _P, _P, _P, _I64, _I64, _I]
         _lib = lib
     return _lib
 
@@ -312,11 +312,13 @@ def alpha_eval(n_orb, h, eri, dets, coefs, rank, alpha):
     return N, float(D[0]), int(own[0]), bool(internal[0])
 
 
-def eps_generators(n_orb, h, eri, dets, coefs, E0, gens, dump_thr=None, dump_cap=0, visit_cap=0, threads=0):
+def eps_generators(n_orb, h, eri, dets, coefs, E0, gens, dump_thr=None, dump_cap=0, visit_cap=0, threads=0,
+                   visit_start=0):
     """Per-generator eps_I [n_gen][ns], S, |A_I|, fingerprint sums, and optional
-    dumps of owned alpha with |e~| >= dump_thr.  visit_cap > 0 bounds the work
-    to the generator's first visit_cap excitations in enumeration order (a
-    timing sample: the sums are then partial); threads > 0 sets the OpenMP
+    dumps of owned alpha with |e~| >= dump_thr.  visit_start and visit_cap > 0
+    restrict each generator to its excitations [visit_start, visit_start +
+    visit_cap) in enumeration order (a timing sample, or one slice of a
+    generator whose slices the caller sums); threads > 0 sets the OpenMP
     team's size."""
     dets = _c(dets, np.uint64); coefs = _c(np.atleast_2d(coefs), np.float64)
     E0 = _c(np.atleast_1d(E0), np.float64)
@@ -332,7 +334,8 @@ def eps_generators(n_orb, h, eri, dets, coefs, E0, gens, dump_thr=None, dump_cap
                                     _ptr(dets), _ptr(coefs), dets.shape[0], ns, _ptr(E0),
                                     _ptr(gens), ng, _ptr(eps), _ptr(S), _ptr(count), _ptr(fp),
                                     float(dump_thr if dump_thr is not None else np.inf), dump_cap,
-                                    _ptr(dd), _ptr(de), _ptr(dk), _ptr(dn), int(visit_cap), int(threads))
+                                    _ptr(dd), _ptr(de), _ptr(dk), _ptr(dn), int(visit_start), int(visit_cap),
+                                    int(threads))
     if rc != 0:
         raise MemoryError("oracle eps_generators failed")
     out = FullResult(eps=eps, S=S, count=count, fp=fp)

@@ -798,16 +798,19 @@ typedef struct {
     double thr;
     int64_t dump_cap, ndump;
     u64 *dump_dets; double *dump_e; double *dump_key;
-    /* a bounded sample (timing only): at most visit_cap of the generator's
-     * excitations, in enumeration order, are evaluated (0: all) */
-    int64_t visit_cap, visits;
+    /* a slice of the generator's excitations, in enumeration order: those
+     * numbered [visit_start, visit_start + visit_cap) are evaluated (cap 0:
+     * to the end).  Slices partition the generator's sums (a bounded timing
+     * sample, or one generator split over threads). */
+    int64_t visit_start, visit_cap, visits;
 } gen_ctx;
 
 static void gen_visit(void *vctx, const u64 *a)
 {
     gen_ctx *G = (gen_ctx *)vctx;
     int nint = G->I->nint;
-    if (G->visit_cap > 0 && G->visits++ >= G->visit_cap) return;
+    const int64_t vi = G->visits++;
+    if (vi < G->visit_start || (G->visit_cap > 0 && vi >= G->visit_start + G->visit_cap)) return;
     if (detmap_find(G->psi, a) >= 0) return;
     /* owner: lowest rank among connected J; only J within degree 4 of the
      * generator can be within degree 2 of alpha (triangle inequality) */
@@ -848,8 +851,10 @@ static void gen_visit(void *vctx, const u64 *a)
  * orc_eps_generators: eps_I (per state) for the listed generators (caller's
  * det indices), plus per-generator |A_I|, fingerprint sum and S.  Optionally
  * dumps owned alpha with |e~| >= dump_thr (up to dump_cap per generator).
- * visit_cap > 0 stops each generator after that many excitations (a bounded
- * timing sample; its sums are then partial).  nthreads > 0 sets the OpenMP
+ * visit_start, visit_cap select a slice of each generator's excitations in
+ * enumeration order: [visit_start, visit_start + visit_cap), cap 0 = to the
+ * end (a bounded timing sample, or slices of one generator summed by the
+ * caller).  nthreads > 0 sets the OpenMP
  * team's size (0: the runtime's default).
  * OpenMP over the listed generators; each generator is summed sequentially
  * (the enumeration order of for_each_excitation), so results are
@@ -860,7 +865,8 @@ int orc_eps_generators(int n, int nint, const double *h, const double *eri_packe
                        const int64_t *gens, int64_t n_gen,
                        double *eps, double *S, int64_t *count, u64 *fp,
                        double dump_thr, int64_t dump_cap, u64 *dump_dets, double *dump_e,
-                       double *dump_key, int64_t *dump_n, int64_t visit_cap, int nthreads)
+                       double *dump_key, int64_t *dump_n, int64_t visit_start, int64_t visit_cap,
+                       int nthreads)
 {
     if (ns < 1 || ns > ORC_MAX_STATES) return -1;
     orc_ints I = {n, nint, h, eri_packed};
@@ -896,6 +902,7 @@ int orc_eps_generators(int n, int nint, const double *h, const double *eri_packe
         G.I = &I; G.dets = dets; G.coefs = coefs; G.n_det = n_det; G.ns = ns; G.rank = rank;
         G.psi = &psi; G.cand = cand; G.ncand = nc; G.gen = gi; G.E0 = E0; G.maxc2 = maxc2;
         G.thr = dump_thr; G.dump_cap = dump_cap;
+        G.visit_start = visit_start;
         G.visit_cap = visit_cap;
         if (dump_cap > 0) {
             G.dump_dets = dump_dets + (size_t)g * dump_cap * 2 * nint;

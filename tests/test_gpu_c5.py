@@ -4,8 +4,10 @@ forward and adjoint, in the launch configuration the benchmark times.
 
 The oracle needs about five core-minutes per generator of this workload (its
 H_aa is summed from scratch for each of some 2x10^7 external determinants),
-so it checks a few sampled generators, evaluated on host threads while the
-GPU runs, and a random sample of the selection:
+so it checks a few sampled generators, each split into 16 slices of its
+excitations (in the oracle's enumeration order; the slices' sums add up to
+the generator's) evaluated on host threads while the GPU runs, and a random
+sample of the selection:
   * eps_I of the generator of rank 0 and of two random ranks,
   * completeness: every alpha owned by a sampled generator whose criterion
     clears the selection's cut is among the selected ones,
@@ -21,7 +23,8 @@ shape with 1,500 determinants.
 E0 is the oracle's energy of the 2,000 largest determinants (the whole-Psi
 energy is a 10^12-pair sum for the oracle); the sweep is defined for any E0,
 and both sides take the same one."""
-import threading
+import os
+from concurrent.futures import ThreadPoolExecutor, as_completed
 
 import numpy as np
 import pytest
@@ -77,19 +80,21 @@ def test_c5_full_size_sampled(ctx):
         assert keys[r - 1] > keys[r] or (keys[r - 1] == keys[r] and _key(sel[r - 1]) < _key(sel[r]))
     cut = keys[-1]
 
-    # sampled generators on host threads while the GPU runs the adjoint
+    # sampled generators, in slices, on host threads while the GPU runs the adjoint
     rank = orc.generator_rank(s.dets, s.coefs)
     order = np.argsort(rank)
     rng = np.random.default_rng(5005)
     ranks = [0] + sorted(int(x) for x in rng.choice(np.arange(1, s.n_det), 2, replace=False))
     gens = order[ranks]
-    box = {}
+    n_slices = 16
+    width = -(-cells // n_slices)
 
-    def oracle_run():
-        box["o"] = orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens,
-                                      dump_thr=cut * (1 + 1e-6), dump_cap=4096)
-    th = threading.Thread(target=oracle_run)
-    th.start()
+    def oracle_slice(i, c):
+        return i, c, orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens[i:i + 1],
+                                        dump_thr=cut * (1 + 1e-6), dump_cap=4096, threads=1,
+                                        visit_start=c * width, visit_cap=width)
+    pool = ThreadPoolExecutor(max_workers=max(1, min(15, len(os.sched_getaffinity(0)) - 1)))
+    futures = [pool.submit(oracle_slice, i, c) for i in range(len(gens)) for c in range(n_slices)]
 
     gup = np.array([1.0, -0.7])
     dets, coefs = gpu_system(ctx, s)
@@ -125,20 +130,26 @@ def test_c5_full_size_sampled(ctx):
             assert abs(sel_e[r, k] - e) <= tol, (r, k, sel_e[r, k], e)
     print(f"256 selected alpha re-evaluated: max rel err {worst:.2e}", flush=True)
 
-    th.join()
-    o = box["o"]
-    print("oracle generators done", flush=True)
-    for i, gi in enumerate(gens):
-        for k in range(ns):
-            tol = 1e-10 * abs(o.eps[i, k]) + 32 * U * (abs(E0[k]) + 1) * o.S[i, k] + 1e-15
-            print(f"rank {ranks[i]} state {k}: eps {eps[k, gi]:.15e} oracle {o.eps[i, k]:.15e} "
-                  f"rel err {abs(eps[k, gi] - o.eps[i, k]) / abs(o.eps[i, k]):.2e}", flush=True)
-            assert abs(eps[k, gi] - o.eps[i, k]) <= tol, (ranks[i], k, eps[k, gi], o.eps[i, k])
+    parts = {}
+    for f in as_completed(futures):
+        i, c, r = f.result()
+        parts[(i, c)] = r
+        print(f"oracle: rank {ranks[i]} slice {c} done ({len(parts)} of {len(futures)})", flush=True)
+    pool.shutdown()
     chosen = {bytes(d.tobytes()) for d in sel}
-    for i in range(len(gens)):
-        assert o.dump_n[i] < 4096
-        for t in range(int(o.dump_n[i])):
-            assert bytes(o.dump_dets[i, t].tobytes()) in chosen, (ranks[i], o.dump_key[i, t], cut)
+    for i, gi in enumerate(gens):
+        sl = [parts[(i, c)] for c in range(n_slices)]
+        o_eps = np.sum([p.eps[0] for p in sl], axis=0)
+        o_S = np.sum([p.S[0] for p in sl], axis=0)
+        for k in range(ns):
+            tol = 1e-10 * abs(o_eps[k]) + 32 * U * (abs(E0[k]) + 1) * o_S[k] + 1e-15
+            print(f"rank {ranks[i]} state {k}: eps {eps[k, gi]:.15e} oracle {o_eps[k]:.15e} "
+                  f"rel err {abs(eps[k, gi] - o_eps[k]) / max(abs(o_eps[k]), 1e-300):.2e}", flush=True)
+            assert abs(eps[k, gi] - o_eps[k]) <= tol, (ranks[i], k, eps[k, gi], o_eps[k])
+        for p in sl:
+            assert p.dump_n[0] < 4096
+            for t in range(int(p.dump_n[0])):
+                assert bytes(p.dump_dets[0, t].tobytes()) in chosen, (ranks[i], p.dump_key[0, t], cut)
 
 
 @pytest.mark.timeout(900)

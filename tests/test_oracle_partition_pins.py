@@ -222,3 +222,25 @@ def test_selection_tie_break_on_equal_criteria(orc):
             pairs += 1
             assert _key(got[i], n) < _key(got[i + 1], n)
     assert pairs >= 3
+
+
+def test_slices_partition_a_generator():
+    """The oracle's excitation slices [start, start + cap) of a generator,
+    summed, give its whole eps_I, S, |A_I| and fingerprint sum (the full-size
+    tests split the largest workload's generators over host threads)."""
+    import numpy as np
+    from oracle import oracle as orc
+    from paper_1902_08154_amd import synth
+    s = synth.make_system("slices", 5, 24, 4, 4, 200, n_states=2)
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    gens = np.array([0, 17, 100])
+    full = orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens)
+    parts = [orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens, visit_start=c * 700,
+                                visit_cap=700) for c in range(13)]
+    assert np.array_equal(sum(p.count for p in parts), full.count)
+    assert np.array_equal(np.sum([p.fp for p in parts], axis=0, dtype=np.uint64), full.fp)
+    assert np.abs(sum(p.eps for p in parts) - full.eps).max() <= 1e-14 * np.abs(full.eps).max()
+    assert np.abs(sum(p.S for p in parts) - full.S).max() <= 1e-14 * np.abs(full.S).max()
+    # past the last excitation a slice is empty
+    assert orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens, visit_start=10 ** 6,
+                              visit_cap=10).count.sum() == 0
