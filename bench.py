@@ -383,6 +383,16 @@ def main():
         "dE_dE0": w.gE.cpu().tolist(),
     }
 
+    # the issue rate the device reaches on one-instruction chains, beside the
+    # derived ceiling the roofline uses (the clean-cell ops are FP64: the
+    # FP64 FMA rate is the probed ceiling they are set against)
+    from paper_1902_08154_amd import _lib
+    probe = {name: ctx.qp_alu_probe(kind, 1 << 14) / 1e12
+             for name, kind in (("f64_fma", _lib.QP_PROBE_F64_FMA), ("i32_add", _lib.QP_PROBE_I32_ADD),
+                                ("mixed", _lib.QP_PROBE_MIXED))}
+    extra["alu_probe_tops"] = probe
+    log(f"ALU probe (T lane-ops/s): {probe}")
+
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle's OpenMP team: OMP_NUM_THREADS if set, else every CPU of the
@@ -441,6 +451,7 @@ def main():
         "config": config,
         "roofline": {"bound": "alu", "achieved": ops_b / kb / 1e12, "peak": ALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": ops_b / kb / ALU_PEAK_OPS, "traffic": traffic,
+                     "peak_probed": probe["f64_fma"], "frac_of_probed": ops_b / kb / 1e12 / probe["f64_fma"],
                      "kernel": "qplean::lean_kernel (adjoint)", "kernel_ms": 1e3 * kb, "ops_per_launch": ops_b,
                      "alpha_per_launch": alpha_clean, "ops_per_alpha": clean_ops_per_alpha(ns, True)},
         "cpu_baseline": cpu,

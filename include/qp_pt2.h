@@ -405,6 +405,25 @@ int qp_set_timing(qp_ctx *ctx, int enable);
 int qp_last_timing(qp_ctx *ctx, double *out_ms);
 
 /*
+ * qp_alu_probe -- diagnostic: the vector-ALU issue rate this device reaches,
+ * the ceiling against which the sweep kernels' lane operations are priced.
+ * Launches 8 workgroups of 256 lanes per compute unit (8 waves per SIMD),
+ * each lane running eight independent chains of one instruction:
+ * kind = QP_PROBE_F64_FMA (v_fma_f64), QP_PROBE_I32_ADD (v_add_u32) or
+ * QP_PROBE_MIXED (the two alternating), iters x 64 instructions per chain
+ * set (x 128 for QP_PROBE_MIXED).  One untimed launch, then one launch timed
+ * with HIP events on `stream`; blocks until it ends.
+ *   out_lane_ops_per_s  host double: instructions x 64 lanes per second.
+ * The first call allocates 8 bytes of device memory, freed by qp_destroy.
+ * Errors: QP_E_ARG (unknown kind, iters outside [1, 2^24]), QP_E_OOM,
+ * QP_E_HIP.
+ */
+#define QP_PROBE_F64_FMA 0
+#define QP_PROBE_I32_ADD 1
+#define QP_PROBE_MIXED   2
+int qp_alu_probe(qp_ctx *ctx, int kind, int64_t iters, void *stream, double *out_lane_ops_per_s);
+
+/*
  * qp_set_split -- how sweeps (qp_pt2, qp_pt2_backward, qp_pt2_generators,
  * qp_pt2_batched and the rounds of qp_pt2_stochastic) divide their cells
  * between kernels.  A split sweep gives the hole-pair batches that no

@@ -27,6 +27,9 @@ QP_NOALLOC_MAX_DET = 1 << 18
 QP_SPLIT_NEVER = 0
 QP_SPLIT_AUTO = 1
 QP_SPLIT_ALWAYS = 2
+QP_PROBE_F64_FMA = 0
+QP_PROBE_I32_ADD = 1
+QP_PROBE_MIXED = 2
 QP_SIGMA_S2 = 8
 QP_SIGMA_REUSE = 16
 QP_MAX_STATES = 4
@@ -87,7 +90,7 @@ class System(ctypes.Structure):
 EXPORTS = ("qp_create", "qp_destroy", "qp_last_error", "qp_set_integrals", "qp_pt2",
            "qp_pt2_backward", "qp_generator_order", "qp_pt2_generators", "qp_pt2_stochastic",
            "qp_pt2_batched", "qp_sigma", "qp_davidson", "qp_energy", "qp_set_timing", "qp_last_timing",
-           "qp_set_split", "qp_generator_order_noalloc")
+           "qp_set_split", "qp_generator_order_noalloc", "qp_alu_probe")
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -138,5 +141,7 @@ def load():
     lib.qp_last_timing.restype = _I
     lib.qp_set_split.argtypes = [_P, _I]
     lib.qp_set_split.restype = _I
+    lib.qp_alu_probe.argtypes = [_P, _I, _I64, _P, ctypes.POINTER(ctypes.c_double)]
+    lib.qp_alu_probe.restype = _I
     _lib = lib
     return lib

@@ -171,6 +171,15 @@ class Context:
         self._check(self._lib.qp_last_timing(self._h, out))
         return tuple(float(out[i]) for i in range(5))
 
+    def qp_alu_probe(self, kind, iters=1 << 14):
+        """Vector-ALU lane operations per second this device issues for
+        `kind` (_lib.QP_PROBE_F64_FMA / I32_ADD / MIXED), on the current
+        stream."""
+        out = ctypes.c_double(0.0)
+        self._check(self._lib.qp_alu_probe(self._h, int(kind), int(iters), _stream(self.device),
+                                           ctypes.byref(out)))
+        return float(out.value)
+
     def qp_set_split(self, mode):
         """mode: _lib.QP_SPLIT_NEVER / AUTO / ALWAYS; True and False stand for
         ALWAYS and NEVER."""

@@ -1141,6 +1141,7 @@ struct Prepared {
 struct qp_ctx {
     int device = 0;
     void *noalloc = nullptr;   // this device's no-allocation scratch (qp_generator_order_noalloc)
+    void *probe_sink = nullptr;   // 8 bytes that qp_alu_probe's kernel never writes in practice
     std::string err;
     int n = 0;
     double *h = nullptr, *X = nullptr, *Y = nullptr, *Cj = nullptr, *CXj = nullptr, *Jm = nullptr, *Km = nullptr,
@@ -2184,6 +2185,45 @@ void jacobi_eigen(std::vector<double> &a, int m, std::vector<double> &w, std::ve
 // C ABI
 // ===========================================================================
 
+// ===========================================================================
+// ALU issue-rate probe: eight independent chains per lane of one VALU
+// instruction each (written in asm so that every op is exactly one
+// instruction), enough waves per SIMD to hide the chains' latency
+// ===========================================================================
+
+#define PROBE_FMA(a) asm volatile("v_fma_f64 %0, %1, %2, %0" : "+v"(a) : "v"(b), "v"(cc))
+#define PROBE_ADD(x) asm volatile("v_add_u32 %0, %1, %0" : "+v"(x) : "v"(y))
+
+template <int KIND>
+__global__ __launch_bounds__(256) void alu_probe(int64_t iters, double *sink)
+{
+    const double b = 1.0 - 0x1p-40, cc = 0x1p-40;
+    const uint32_t y = blockIdx.x | 1u;
+    double a0 = threadIdx.x, a1 = a0 + 1, a2 = a0 + 2, a3 = a0 + 3, a4 = a0 + 4, a5 = a0 + 5, a6 = a0 + 6,
+           a7 = a0 + 7;
+    uint32_t x0 = threadIdx.x, x1 = x0 + 1, x2 = x0 + 2, x3 = x0 + 3, x4 = x0 + 4, x5 = x0 + 5, x6 = x0 + 6,
+             x7 = x0 + 7;
+    for (int64_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (KIND != 1) {
+                PROBE_FMA(a0); PROBE_FMA(a1); PROBE_FMA(a2); PROBE_FMA(a3);
+                PROBE_FMA(a4); PROBE_FMA(a5); PROBE_FMA(a6); PROBE_FMA(a7);
+            }
+            if (KIND != 0) {
+                PROBE_ADD(x0); PROBE_ADD(x1); PROBE_ADD(x2); PROBE_ADD(x3);
+                PROBE_ADD(x4); PROBE_ADD(x5); PROBE_ADD(x6); PROBE_ADD(x7);
+            }
+        }
+    }
+    const double s = a0 + a1 + a2 + a3 + a4 + a5 + a6 + a7;
+    const uint32_t t = x0 ^ x1 ^ x2 ^ x3 ^ x4 ^ x5 ^ x6 ^ x7;
+    if (s == -1.0 && t == 0x5a5a5a5au) sink[0] = s;   // never true; keeps the chains' results live
+}
+
+#undef PROBE_FMA
+#undef PROBE_ADD
+
 extern "C" {
 
 // ---------------------------------------------------------------- no-allocation generator order
@@ -2250,6 +2290,7 @@ void qp_destroy(qp_ctx *c)
         for (auto &b : v) if (b.p) (void)hipFree(b.p);
     for (auto &b : c->args) if (b.p) (void)hipFree(b.p);
     if (c->defn.p) (void)hipFree(c->defn.p);
+    if (c->probe_sink) (void)hipFree(c->probe_sink);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     double *arrs[] = {c->h, c->X, c->Y, c->Cj, c->CXj, c->Jm, c->Km, c->JK};
     for (double *p : arrs) if (p) (void)hipFree(p);
@@ -2897,6 +2938,52 @@ int qp_last_timing(qp_ctx *c, double *out_ms)
     out_ms[2] = t;
     out_ms[3] = l;
     out_ms[4] = l1;
+    return QP_OK;
+}
+
+int qp_alu_probe(qp_ctx *c, int kind, int64_t iters, void *stream, double *out_lane_ops_per_s)
+{
+    if (!c || !out_lane_ops_per_s) return QP_E_ARG;
+    c->err.clear();
+    if (kind < QP_PROBE_F64_FMA || kind > QP_PROBE_MIXED || iters < 1 || iters > (int64_t)1 << 24)
+        return fail(c, QP_E_ARG, "probe kind must be QP_PROBE_F64_FMA, QP_PROBE_I32_ADD or QP_PROBE_MIXED, "
+                                 "iters in [1, 2^24]");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid((unsigned)c->num_cu * 8), block(256);   // 8 waves per SIMD
+    auto launch = [&]() {
+        if (kind == QP_PROBE_F64_FMA)
+            hipLaunchKernelGGL(alu_probe<0>, grid, block, 0, st, iters, (double *)c->probe_sink);
+        else if (kind == QP_PROBE_I32_ADD)
+            hipLaunchKernelGGL(alu_probe<1>, grid, block, 0, st, iters, (double *)c->probe_sink);
+        else
+            hipLaunchKernelGGL(alu_probe<2>, grid, block, 0, st, iters, (double *)c->probe_sink);
+    };
+    if (!c->probe_sink && hipMalloc(&c->probe_sink, sizeof(double)) != hipSuccess) {
+        c->probe_sink = nullptr;
+        return fail(c, QP_E_OOM, "device allocation failed (probe)");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float ms = 0.f;
+    if (e == hipSuccess) {
+        launch();   // untimed: brings the clocks up
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) {
+        launch();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(c, QP_E_HIP, std::string("probe: ") + hipGetErrorString(e));
+    const double per_lane = (double)iters * 64.0 * (kind == QP_PROBE_MIXED ? 2.0 : 1.0);
+    *out_lane_ops_per_s = per_lane * grid.x * block.x / (1e-3 * (double)ms);
     return QP_OK;
 }
 
