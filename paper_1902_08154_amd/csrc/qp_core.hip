@@ -1674,7 +1674,12 @@ int launch_plans(qp_ctx *c, int kind, bool bwd, bool fp, std::vector<LaunchPlan>
     size_t nsys = 0;
     for (auto &p : plans) nsys += p.sys.size();
     const size_t args_bytes = sizeof(SweepArgs) * nsys;
-    const size_t bytes = args_bytes + sizeof(int64_t) * nsys;
+    // clean-cell launches: each plan's item counters, zero, staged with the
+    // descriptors
+    const size_t ctr_at = (args_bytes + sizeof(int64_t) * nsys + 127) / 128 * 128;
+    const size_t ctr_bytes = sizeof(unsigned long long) * ITEM_CTR_GROUPS * ITEM_CTR_STRIDE;
+    const bool claims = kind == K_LEAN;
+    const size_t bytes = claims ? ctr_at + ctr_bytes * plans.size() : args_bytes + sizeof(int64_t) * nsys;
     // the staging area is reused only after a host synchronisation on `st`,
     // which every call performs between its two launch rounds
     const size_t quarter = c->host_stage_bytes / 4 / 16 * 16;
@@ -1685,11 +1690,15 @@ int launch_plans(qp_ctx *c, int kind, bool bwd, bool fp, std::vector<LaunchPlan>
     SweepArgs *ha = (SweepArgs *)stage;
     int64_t *he = (int64_t *)(stage + args_bytes);
     size_t k = 0;
-    for (auto &p : plans)
+    for (size_t pi = 0; pi < plans.size(); ++pi) {
+        auto &p = plans[pi];
         for (size_t i = 0; i < p.sys.size(); ++i, ++k) {
             ha[k] = kind == K_GENERAL ? run[p.sys[i]].d : run[p.sys[i]].a;
+            ha[k].item_ctr = claims ? (unsigned long long *)(dev + ctr_at + ctr_bytes * pi) : nullptr;
             he[k] = p.end[i];
         }
+    }
+    if (claims) memset(stage + ctr_at, 0, ctr_bytes * plans.size());
     HIPCHK(c, hipMemcpyAsync(dev, stage, bytes, hipMemcpyHostToDevice, st));
     k = 0;
     for (auto &p : plans) {
@@ -1715,7 +1724,12 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
     c->timed = false;
     if (n_sys == 0) return QP_OK;
     {
-        int rc = host_space(c, std::max<size_t>(4 << 16, 4 * ((sizeof(SweepArgs) + 8) * (size_t)n_sys + 256)), n_sys);
+        // a quarter per kernel kind: descriptors and end offsets, and for the
+        // clean-cell kind the item counters of up to 16 launches (4 word
+        // counts x 4 state counts)
+        const size_t ctr_room = 128 + 16 * sizeof(unsigned long long) * ITEM_CTR_GROUPS * ITEM_CTR_STRIDE;
+        int rc = host_space(c, std::max<size_t>(4 << 16, 4 * ((sizeof(SweepArgs) + 8) * (size_t)n_sys + 256 + ctr_room)),
+                            n_sys);
         if (rc != QP_OK) return rc;
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], st));

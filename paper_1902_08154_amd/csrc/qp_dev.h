@@ -367,7 +367,14 @@ struct SweepArgs {
     double *lean_dc;          // [n_gen][n_pairs][ns]  adjoint: the generator's dc share per batch
     uint32_t *split_keep;     // [n_det][nbw]  split sweeps: pair batches the dense kernel keeps (bit nel + pair)
     unsigned long long *fine_total;   // fine-filter entries over the batches evaluated (atomics)
+    unsigned long long *item_ctr;     // clean-cell launches: per group of waves, items claimed so far
+                                      // (ITEM_CTR_STRIDE apart; zero at launch; the same for every system)
 };
+
+// counters of one clean-cell launch: one per group of waves (8: one per XCD),
+// each on a 128-byte line of its own
+constexpr int ITEM_CTR_GROUPS = 8;
+constexpr int ITEM_CTR_STRIDE = 16;
 
 // Split sweep: the cells of the hole-pair batch (holes hc0, hc1 as spin << 8 |
 // orbital) of generator rank g that other determinants touch.  Of the

@@ -128,18 +128,22 @@ __device__ __forceinline__ int occ_below(const uint64_t *d, int s, int p)
     return c;
 }
 
-// The items of a launch in XCD-major blocks: the workgroups that the hardware
-// places on one XCD (block index mod 8) walk one contiguous eighth of the item
-// range, so that the items sharing a hole pair, which are consecutive, meet in
-// that XCD's L2 instead of every XCD's.
-__device__ __forceinline__ void xcd_items(int64_t total, int64_t &first, int64_t &end, int64_t &step)
+// The items of a launch in XCD-major shares: the workgroups that the
+// hardware places on one XCD (block index mod 8, when the grid is a multiple
+// of 8) form a group that owns one contiguous eighth of the item range, so
+// that the items sharing a hole pair, which are consecutive, meet in that
+// XCD's L2 instead of every XCD's.  The group's waves claim its items one at
+// a time (a counter per group), so that they stay within a few hundred
+// consecutive items of each other: statically dealt items let them drift
+// apart over a launch until they span many hole pairs, whose integral blocks
+// no longer fit in L2 together.
+__device__ __forceinline__ void xcd_share(int64_t total, int64_t &lo, int64_t &end, int &group)
 {
-    const int nx = (gridDim.x % 8u) == 0u ? 8 : 1;
+    const int nx = (gridDim.x % ITEM_CTR_GROUPS) == 0u ? ITEM_CTR_GROUPS : 1;
     const int64_t per = (total + nx - 1) / nx;
-    const int64_t lo = (int64_t)(blockIdx.x % nx) * per;
+    group = (int)(blockIdx.x % nx);
+    lo = (int64_t)group * per;
     end = lo + per < total ? lo + per : total;
-    first = lo + blockIdx.x / nx;
-    step = gridDim.x / nx;
 }
 
 __device__ __forceinline__ bool bit_of(const uint32_t *m, int i) { return (m[i >> 5] >> (i & 31)) & 1u; }
@@ -185,7 +189,7 @@ template <int NINT, int NS, bool BWD, bool FP>
 constexpr int lean_waves()
 {
     if (BWD) return NS <= 2 ? 4 : 3;
-    return FP && NS == 4 ? 2 : (FP || NS >= 3 ? 3 : 4);
+    return FP && (NS == 4 || (NS == 3 && NINT == 4)) ? 2 : (FP || NS >= 3 ? 3 : 4);
 }
 
 template <int NINT, int NS, bool BWD, bool FP>
@@ -224,9 +228,18 @@ void lean_kernel(const SweepArgs *__restrict__ sys,
             sDH[p] = 0.0;
         }
     };
-    int64_t it0, iend, istep;
-    xcd_items(total, it0, iend, istep);
-    for (int64_t it = it0; it < iend; it += istep) {
+    int64_t ilo, iend;
+    int group;
+    xcd_share(total, ilo, iend, group);
+    unsigned long long *ctr = sys[0].item_ctr + group * ITEM_CTR_STRIDE;
+    for (;;) {
+        unsigned long long claim = 0;
+        if (lane == 0) claim = atomicAdd(ctr, 1ull);
+        // lane 0's claim, as a wave-uniform (scalar) value
+        const uint32_t clo = __builtin_amdgcn_readfirstlane((uint32_t)claim);
+        const uint32_t chi = __builtin_amdgcn_readfirstlane((uint32_t)(claim >> 32));
+        const int64_t it = ilo + (int64_t)(((uint64_t)chi << 32) | clo);
+        if (it >= iend) break;
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
             flush_dh(((ConstSys *)sys)[sid]);
@@ -771,7 +784,9 @@ __global__ __launch_bounds__(WAVE) void corr_kernel(const SweepArgs *__restrict_
     };
     // plain grid-stride order: its items differ widely in cost (most leave
     // at once), and contiguous per-XCD ranges balanced them worse (n_orb 256,
-    // 16+16, 10^5 determinants: 928 ms against 734 ms)
+    // 16+16, 10^5 determinants: 928 ms against 734 ms); claiming them one at
+    // a time, as the clean-cell kernel does, costs more per item than the
+    // locality brings (forward 844 ms against 744 ms, adjoint 1341 against 1112)
     for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
         if (it >= item_end[sid]) {
             flush_min(((ConstSys *)sys)[sid].min_delta_bits);
