@@ -48,7 +48,14 @@ def log(*a):
 # then WRITE_SIZE) scaled by the same counters on a device copy of known size.  Valid only for
 # the kernel sources it was measured on (SHA-256 of CLEAN_SOURCES); reported as null otherwise.
 CLEAN_SOURCES = ["qp_dev.h", "qp_lean.hip"]
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # adjoint clean-cell launch: FETCH_SIZE 993,539,733.4 KiB x 2.000 (a 1 GiB device copy reads
+    # 524,316.4 KiB) + WRITE_SIZE 77,483,339.1 KiB x 1.000 (the copy writes 1,048,576 KiB)
+    "c5_n256_16a16b_1e6det_2st_top1e5": {
+        "sources_sha256": "15f974cb5f8cd376b38e3e5ee54bb6500cc25d9a37eff2106afd56dab7fed85f",
+        "bytes": 2114002195515.0,
+    },
+}
 
 
 def clean_sources_sha256():
