@@ -46,8 +46,11 @@ def log(*a):
 
 # HBM traffic of one launch of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
 # then WRITE_SIZE) scaled by the same counters on a device copy of known size.  Valid only for
-# the kernel sources it was measured on (SHA-256 of CLEAN_SOURCES); reported as null otherwise.
+# the kernel sources it was measured on (SHA-256 of the kernel's sources); reported as null
+# otherwise.  The dominant kernel is the adjoint clean-cell kernel of a split sweep, else the
+# forward dense kernel.
 CLEAN_SOURCES = ["qp_dev.h", "qp_lean.hip"]
+DENSE_SOURCES = ["qp_dev.h", "qp_fast_caps.h", "qp_fast_impl.h", "qp_fast_fwd.hip"]
 MEASURED_TRAFFIC = {
     # adjoint clean-cell launch: FETCH_SIZE 993,539,733.4 KiB x 2.000 (a 1 GiB device copy reads
     # 524,316.4 KiB) + WRITE_SIZE 77,483,339.1 KiB x 1.000 (the copy writes 1,048,576 KiB)
@@ -55,13 +58,19 @@ MEASURED_TRAFFIC = {
         "sources_sha256": "15f974cb5f8cd376b38e3e5ee54bb6500cc25d9a37eff2106afd56dab7fed85f",
         "bytes": 2114002195515.0,
     },
+    # forward dense launch: FETCH_SIZE 21,773,386.3 KiB x 2.000 (the 1 GiB copy reads 524,306.5 KiB)
+    # + WRITE_SIZE 45,657.3 KiB x 1.000
+    "c2_n64_10a10b_1e4det_top1000": {
+        "sources_sha256": "915e54199ba634a1b4f4859df8ceadf4f06b86eb5279fd1da3f206f5c4babd8c",
+        "bytes": 44637074684.0,
+    },
 }
 
 
-def clean_sources_sha256():
+def clean_sources_sha256(sources=CLEAN_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in CLEAN_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1902_08154_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -381,9 +390,9 @@ def main():
         "forward_ms": 1e3 * float(np.mean(wall_f)), "forward_alpha_per_s": stats["n_alpha"] / float(np.mean(wall_f)),
         "forward_kernel_ms": kms(tf_list), "adjoint_kernel_ms": kms(tb_list),
         "alpha_clean": alpha_clean, "alpha_general_kernel": stats["n_alpha_general"],
-        "clean_cell_forward_roofline": {"achieved": ops_f / kf / 1e12, "frac": ops_f / kf / ALU_PEAK_OPS,
-                                        "kernel_ms": 1e3 * kf,
-                                        "ops_per_alpha": clean_ops_per_alpha(ns, False)},
+        "clean_cell_forward_roofline": ({"achieved": ops_f / kf / 1e12, "frac": ops_f / kf / ALU_PEAK_OPS,
+                                         "kernel_ms": 1e3 * kf, "ops_per_alpha": clean_ops_per_alpha(ns, False)}
+                                        if alpha_clean > 0 else None),
         "filter": filter_figures(s, stats),
         "e_pt2": w.e_out.cpu().tolist(), "rpt2_Z": stats["Z"], "e_rpt2": stats["e_rpt2"],
         "n_selected": int(w.nsl.item()), "n_candidates": stats["n_candidates"],
@@ -439,8 +448,22 @@ def main():
         log(f"copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written")
         del src, dst
 
+    split = alpha_clean > 0
     mt = MEASURED_TRAFFIC.get(s.name)
-    traffic = mt["bytes"] if mt and mt["sources_sha256"] == clean_sources_sha256() else None
+    traffic = (mt["bytes"] if mt and mt["sources_sha256"] == clean_sources_sha256(
+        CLEAN_SOURCES if split else DENSE_SOURCES) else None)
+    if split:
+        roof = {"kernel": "qplean::lean_kernel (adjoint)", "kernel_ms": 1e3 * kb, "ops_per_launch": ops_b,
+                "alpha_per_launch": alpha_clean, "ops_per_alpha": clean_ops_per_alpha(ns, True)}
+    else:
+        # an unsplit sweep: the forward dense kernel, 3 + 15 per state per alpha
+        # and 12 per word + 2 per state per connection
+        kd = float(np.mean([t[0] for t in tf_list])) * 1e-3
+        a_dense = stats["n_alpha"] - stats["n_alpha_general"]
+        ops_d = a_dense * (3.0 + 15.0 * ns) + stats["n_connections"] * (12.0 * nint + 2.0 * ns)
+        roof = {"kernel": "qpfast::fast_kernel (forward)", "kernel_ms": 1e3 * kd, "ops_per_launch": ops_d,
+                "alpha_per_launch": a_dense, "ops_per_alpha": ops_d / max(a_dense, 1)}
+    achieved = roof["ops_per_launch"] / (roof["kernel_ms"] * 1e-3) / 1e12
 
     out = {
         "metric": METRIC,
@@ -456,11 +479,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": config,
-        "roofline": {"bound": "alu", "achieved": ops_b / kb / 1e12, "peak": ALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s", "frac": ops_b / kb / ALU_PEAK_OPS, "traffic": traffic,
-                     "peak_probed": probe["f64_fma"], "frac_of_probed": ops_b / kb / 1e12 / probe["f64_fma"],
-                     "kernel": "qplean::lean_kernel (adjoint)", "kernel_ms": 1e3 * kb, "ops_per_launch": ops_b,
-                     "alpha_per_launch": alpha_clean, "ops_per_alpha": clean_ops_per_alpha(ns, True)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved * 1e12 / ALU_PEAK_OPS, "traffic": traffic,
+                     "peak_probed": probe["f64_fma"], "frac_of_probed": achieved / probe["f64_fma"], **roof},
         "cpu_baseline": cpu,
         "extra": extra,
     }
