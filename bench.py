@@ -196,8 +196,17 @@ def next_rows_bench(ctx, dev, s, dets, coefs, E0, steps):
                              "n_computed": g["n_computed"], "n_det": s.n_det, "n_rounds": g["n_rounds"],
                              "e_pt2": float(g["e_pt2"][0]), "err": float(g["err"][0]),
                              "e_pt2_deterministic": float(r_det["e_pt2"][0].item())}
+    # the same run selecting the top n_select alpha of its computed generators
+    # on the fly, against the deterministic sweep with its selection
+    t_dsel, _ = timed(lambda: ctx.pt2(dets, coefs, E0, n_select=s.n_select))
+    t_ssel, gs = timed(lambda: ctx.pt2_stochastic(dets, coefs, E0, u, rel_err=0.002, det_chunk=256,
+                                                  draws_per_round=1024, n_select=s.n_select))
+    out["semistochastic"].update({"with_selection_ms": t_ssel, "n_select": s.n_select,
+                                  "n_selected": int(gs["sel_e"].shape[0]),
+                                  "deterministic_with_selection_ms": t_dsel})
     log(f"semi-stochastic: {t_sto:.1f} ms ({g['n_computed']} of {s.n_det} generators, {g['n_rounds']} rounds), "
-        f"deterministic {t_det:.1f} ms")
+        f"deterministic {t_det:.1f} ms; with selection of {s.n_select}: {t_ssel:.1f} ms, deterministic "
+        f"{t_dsel:.1f} ms")
     gen = torch.Generator().manual_seed(7)
     U4 = torch.rand((4, s.n_det), generator=gen, dtype=torch.float64).to(dev)
     sig = {}

@@ -275,16 +275,27 @@ int qp_pt2_generators(qp_ctx *ctx, const uint64_t *dets, const double *coefs, in
  * tables and coarse lists are prepared once per call; each round is one sweep
  * of its list followed by a host decision, and lasts at least one work item's
  * time, so rounds of a few hundred generators keep the device busy.
+ * Selection on the fly (sec. "CIPSI selection and PT2 energy", the new
+ * stochastic selection): with n_select > 0 every round also selects among the
+ * alpha owned by the generators it sweeps, and the rounds' lists are merged,
+ * so the call returns the top n_select alpha of every generator it computed,
+ * ordered as qp_pt2 orders its selection -- the same list, bit for bit, as
+ * qp_pt2_generators over those generators gives.  No generator is swept twice.
  *   uniforms   HOST double [n_uniforms] in [0, 1): the random numbers, one per
  *              draw, consumed in order (the caller owns the generator)
  *   e_est, e_err  HOST double [n_states]; n_computed, n_rounds HOST int64 [1]
+ *   n_select, sel_dets, sel_e, n_sel: as qp_pt2 (device), over the alpha owned
+ *              by the computed generators; unused when n_select = 0
+ *   computed_out  optional device uint8 [n_det]: 1 for each determinant whose
+ *              eps was computed (in the caller's order), else 0
  * The call is synchronous.  Errors as qp_pt2; QP_E_ARG for det_chunk < 1,
- * draws_per_round < 0 or rel_err < 0.
+ * draws_per_round < 0, rel_err < 0 or n_select < 0.
  */
 int qp_pt2_stochastic(qp_ctx *ctx, const uint64_t *dets, const double *coefs, int64_t n_det,
                       int n_states, const double *E0, const double *uniforms, int64_t n_uniforms,
-                      double rel_err, int64_t det_chunk, int64_t draws_per_round, int flags,
-                      double *e_est, double *e_err, int64_t *n_computed, int64_t *n_rounds,
+                      double rel_err, int64_t det_chunk, int64_t draws_per_round, int64_t n_select,
+                      int flags, double *e_est, double *e_err, int64_t *n_computed, int64_t *n_rounds,
+                      uint64_t *sel_dets, double *sel_e, int64_t *n_sel, uint8_t *computed_out,
                       void *stream);
 
 /*

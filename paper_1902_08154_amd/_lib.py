@@ -124,8 +124,8 @@ def load():
     lib.qp_generator_order_noalloc.restype = _I
     lib.qp_pt2_generators.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I64, _I64, _I, _P, _P, _P, _P, _P, _P]
     lib.qp_pt2_generators.restype = _I
-    lib.qp_pt2_stochastic.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I64, ctypes.c_double, _I64, _I64, _I,
-                                      _P, _P, _P, _P, _P]
+    lib.qp_pt2_stochastic.argtypes = [_P, _P, _P, _I64, _I, _P, _P, _I64, ctypes.c_double, _I64, _I64, _I64, _I,
+                                      _P, _P, _P, _P, _P, _P, _P, _P, _P]
     lib.qp_pt2_stochastic.restype = _I
     lib.qp_pt2_batched.argtypes = [_P, _I, ctypes.POINTER(System), _I, _I, _P]
     lib.qp_pt2_batched.restype = _I

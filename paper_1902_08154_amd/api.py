@@ -119,8 +119,10 @@ class Context:
                                                 _ptr(eps_out), _ptr(sel_dets), _ptr(sel_e), _ptr(n_sel),
                                                 _ptr(stats), _stream(self.device)))
 
-    def qp_pt2_stochastic(self, dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round, flags=0):
-        """uniforms: host float64 numpy array.  Returns (e_est, e_err, n_computed, n_rounds)."""
+    def qp_pt2_stochastic(self, dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round, flags=0,
+                          n_select=0, sel_dets=None, sel_e=None, n_sel=None, computed=None):
+        """uniforms: host float64 numpy array.  Returns (e_est, e_err, n_computed, n_rounds);
+        with n_select > 0 the selection goes to the device tensors sel_dets, sel_e, n_sel."""
         import numpy as np
         ns = coefs.shape[0]
         u = np.ascontiguousarray(uniforms, dtype=np.float64)
@@ -131,7 +133,8 @@ class Context:
         hp = lambda a: ctypes.c_void_p(a.ctypes.data)
         self._check(self._lib.qp_pt2_stochastic(self._h, _ptr(dets), _ptr(coefs), dets.shape[0], ns, _ptr(E0),
                                                 hp(u) if u.size else None, u.size, float(rel_err), int(det_chunk),
-                                                int(draws_per_round), flags, hp(e), hp(err), hp(nc), hp(nr),
+                                                int(draws_per_round), int(n_select), flags, hp(e), hp(err), hp(nc),
+                                                hp(nr), _ptr(sel_dets), _ptr(sel_e), _ptr(n_sel), _ptr(computed),
                                                 _stream(self.device)))
         return e, err, int(nc[0]), int(nr[0])
 
@@ -259,9 +262,12 @@ class Context:
         m = int(nsel.item()) if n_select > 0 else 0
         return dict(eps=eps[:, :gens.numel()], stats=stats_to_dict(st, ns), sel_dets=sd[:m], sel_e=se[:m])
 
-    def pt2_stochastic(self, dets, coefs, E0, uniforms, rel_err=0.002, det_chunk=None, draws_per_round=None):
+    def pt2_stochastic(self, dets, coefs, E0, uniforms, rel_err=0.002, det_chunk=None, draws_per_round=None,
+                       n_select=0):
         """Semi-stochastic E_PT2.  uniforms: host random numbers in [0, 1), one
-        per draw.  Returns dict(e_pt2, err, n_computed, n_rounds)."""
+        per draw.  Returns dict(e_pt2, err, n_computed, n_rounds, computed);
+        with n_select > 0 also the selection over the computed generators,
+        made during the same sweeps: sel_dets, sel_e (trimmed to its length)."""
         self._inputs(dets, coefs, E0)
         n = dets.shape[0]
         # rounds large enough to keep the device busy: each one is a sweep launch
@@ -270,8 +276,21 @@ class Context:
             det_chunk = max(1, n // 40)
         if draws_per_round is None:
             draws_per_round = max(16, 4 * det_chunk)
-        e, err, nc, nr = self.qp_pt2_stochastic(dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round)
-        return dict(e_pt2=e, err=err, n_computed=nc, n_rounds=nr)
+        dev = self.device
+        computed = torch.zeros(n, dtype=torch.uint8, device=dev)
+        sd = se = nsl = None
+        if n_select > 0:
+            sd = torch.zeros((n_select,) + tuple(dets.shape[1:]), dtype=dets.dtype, device=dev)
+            se = torch.zeros((n_select, coefs.shape[0]), dtype=torch.float64, device=dev)
+            nsl = torch.zeros(1, dtype=torch.int64, device=dev)
+        e, err, nc, nr = self.qp_pt2_stochastic(dets, coefs, E0, uniforms, rel_err, det_chunk, draws_per_round,
+                                                n_select=n_select, sel_dets=sd, sel_e=se, n_sel=nsl,
+                                                computed=computed)
+        out = dict(e_pt2=e, err=err, n_computed=nc, n_rounds=nr, computed=computed.bool())
+        if n_select > 0:
+            m = int(nsl.item())
+            out["sel_dets"], out["sel_e"] = sd[:m], se[:m]
+        return out
 
     def sigma(self, dets, U, s2=False, reuse=False):
         """W = H U (or S^2 U) for U [n_vec, n_det] on the device.  reuse: the

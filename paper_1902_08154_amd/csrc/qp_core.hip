@@ -98,6 +98,13 @@ __device__ __forceinline__ int det_cmp_dev(const uint64_t *a, const uint64_t *b)
     return 0;
 }
 
+// key_bin on the host (the same bins as the kernels' histogram)
+inline int key_bin_host(uint64_t key)
+{
+    const int64_t b = (int64_t)(key >> 48) - QP_HIST_BASE;
+    return b < 0 ? 0 : (b >= QP_HIST_BINS ? QP_HIST_BINS - 1 : (int)b);
+}
+
 struct Scalars {
     unsigned int pad0;
     int tau_bin;
@@ -117,10 +124,10 @@ struct Scalars {
 
 // the per-sweep fields of the scalars, as a fresh preparation leaves them; the
 // fields that describe the inputs (coarse-list size, input checks) are kept
-__global__ void reset_sweep_scalars(Scalars *sc)
+__global__ void reset_sweep_scalars(Scalars *sc, int tau_bin0)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->tau_bin = 0;
+        sc->tau_bin = tau_bin0;
         sc->cand_count = 0ull;
         sc->overflow = 0ull;
         sc->min_delta_bits = 0x7ff0000000000000ull;
@@ -862,7 +869,8 @@ __global__ void sel_materialise(const Cand *cand, const int32_t *comp, int64_t M
 
 template <int NINT>
 __global__ void sel_output(const Cand *cand, const int32_t *comp, const int32_t *sorted, int64_t m, int ns,
-                           const uint64_t *bits, uint64_t *sel_dets, double *sel_e, int64_t *n_sel)
+                           const uint64_t *bits, const uint64_t *keys, uint64_t *sel_dets, double *sel_e,
+                           uint64_t *sel_key, int64_t *n_sel)
 {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
         int32_t i = sorted[r];
@@ -870,6 +878,7 @@ __global__ void sel_output(const Cand *cand, const int32_t *comp, const int32_t 
 #pragma unroll
         for (int w = 0; w < 2 * NINT; ++w) sel_dets[r * 2 * NINT + w] = bits[(int64_t)i * 2 * NINT + w];
         for (int k = 0; k < ns; ++k) sel_e[r * ns + k] = cd.e[k];
+        if (sel_key) sel_key[r] = keys[i];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *n_sel = m;
 }
@@ -1110,6 +1119,8 @@ enum BufId {
     B_DCI, B_EPSG, B_SG, B_CNTG, B_FPG, B_SC, B_HIST, B_CAND, B_COMP, B_SKEY, B_SBITS, B_SIDX, B_MAXC2,
     B_ROW, B_C2, B_TOTAL, B_DEFG, B_DEFB, B_DEFE, B_DEFS, B_DEFC, B_DEFN, B_DEFF, B_DEFD, B_CONNI, B_CONNG,
     B_DEFAG, B_DEFBITS, B_DEFCG, B_DEFOFF, B_DEFBS, B_GENR,
+    // semi-stochastic sweep: a round's selection
+    B_RSDET, B_RSE, B_RSKEY, B_RSN,
     // split sweep: hole-pair lists and the clean-cell kernel's slots
     B_LBITS, B_LKCNT, B_LKOFF, B_LKBS, B_LPOS, B_LEPS, B_LS, B_LCNT, B_LFP, B_LCONN, B_LDC, B_LKEEP,
     // integral layouts of a system of a batched call
@@ -1590,6 +1601,9 @@ struct SysIn {
     uint64_t *sel_dets;
     double *sel_e;
     int64_t *n_sel;
+    uint64_t *sel_key;          // optional: the selection's criterion keys, in its order
+    int sel_floor_bin;          // the selection threshold's starting histogram bin (0: none): alpha
+                                // with keys below its lower edge are not candidates
     qp_pt2_stats *stats;
     double *eps_gen;
     const double *gup;
@@ -1755,10 +1769,12 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
         }
         if (x.pre) {
             r.P = *x.pre;
-            hipLaunchKernelGGL(reset_sweep_scalars, dim3(1), dim3(1), 0, st, r.P.sc);
+            hipLaunchKernelGGL(reset_sweep_scalars, dim3(1), dim3(1), 0, st, r.P.sc, x.sel_floor_bin);
         } else {
             int rc = prepare(c, s, x.I, x.dets, x.coefs, x.n_det, ns, flags, st, r.P);
             if (rc != QP_OK) return rc;
+            if (x.sel_floor_bin > 0)
+                hipLaunchKernelGGL(reset_sweep_scalars, dim3(1), dim3(1), 0, st, r.P.sc, x.sel_floor_bin);
         }
         const int64_t n_det = x.n_det;
         r.n_g = n_det;
@@ -2103,7 +2119,7 @@ int run_sweeps(qp_ctx *c, std::vector<SysIn> &in, int flags, bool bwd, hipStream
                            r.P.perm, skey, sbits, PP, sidx);                                               \
         bitonic_sort(sidx, PP, SelCmp<NI>{skey, sbits}, st);                                              \
         hipLaunchKernelGGL(sel_output<NI>, dim3(grid_for(std::max<int64_t>(m, 1))), dim3(256), 0, st, r.cand, comp, \
-                           sidx, m, x.ns, sbits, x.sel_dets, x.sel_e, x.n_sel);                            \
+                           sidx, m, x.ns, sbits, skey, x.sel_dets, x.sel_e, x.sel_key, x.n_sel);          \
         break;
                     SELCASE(1) SELCASE(2) SELCASE(3) SELCASE(4)
 #undef SELCASE
@@ -2457,20 +2473,60 @@ int qp_pt2_generators(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
 
 int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int64_t n_det, int n_states,
                       const double *E0, const double *uniforms, int64_t n_uniforms, double rel_err,
-                      int64_t det_chunk, int64_t draws_per_round, int flags, double *e_est, double *e_err,
-                      int64_t *n_computed, int64_t *n_rounds, void *stream)
+                      int64_t det_chunk, int64_t draws_per_round, int64_t n_select, int flags, double *e_est,
+                      double *e_err, int64_t *n_computed, int64_t *n_rounds, uint64_t *sel_dets, double *sel_e,
+                      int64_t *n_sel, uint8_t *computed_out, void *stream)
 {
     int rc = common_checks(c, dets, coefs, n_det, n_states, E0);
     if (rc != QP_OK) return rc;
     if (!e_est || !e_err || !n_computed || !n_rounds) return fail(c, QP_E_ARG, "outputs are required");
     if (n_uniforms < 0 || (n_uniforms > 0 && !uniforms)) return fail(c, QP_E_ARG, "bad uniform list");
     if (det_chunk < 1 || draws_per_round < 0 || !(rel_err >= 0.0)) return fail(c, QP_E_ARG, "bad schedule");
+    if (n_select < 0) return fail(c, QP_E_ARG, "n_select < 0");
+    if (n_select > 0 && (!sel_dets || !sel_e || !n_sel)) return fail(c, QP_E_ARG, "selection outputs required");
+    if (n_select > (int64_t)INT32_MAX / 4) return fail(c, QP_E_ARG, "n_select too large");
     const int ns = n_states;
     for (int k = 0; k < ns; ++k) { e_est[k] = 0.0; e_err[k] = 0.0; }
     *n_computed = 0;
     *n_rounds = 0;
-    if (n_det == 0) return QP_OK;
     hipStream_t st = (hipStream_t)stream;
+    if (n_det == 0) {
+        if (n_select > 0) HIPCHK(c, hipMemsetAsync(n_sel, 0, sizeof(int64_t), st));
+        return QP_OK;
+    }
+    // on-the-fly selection: every round also selects the top n_select alpha
+    // owned by its generators (with the criterion keys the kernels computed);
+    // the rounds' generators partition the computed ones, so merging the
+    // rounds' lists and keeping the first n_select gives the selection over
+    // all computed generators, in the same order as one sweep of them
+    const int nint = (c->n + 63) / 64;
+    const int64_t dw = 2 * nint;
+    std::vector<uint64_t> mkey, mdet, rkey_h, rdet_h, tkey, tdet;
+    std::vector<double> me, re_h, te;
+    uint64_t *rdet = nullptr, *rkey = nullptr;
+    double *re = nullptr;
+    int64_t *rn = nullptr;
+    if (n_select > 0) {
+        rdet = (uint64_t *)scratch(c, 0, B_RSDET, sizeof(uint64_t) * n_select * dw);
+        re = (double *)scratch(c, 0, B_RSE, sizeof(double) * n_select * ns);
+        rkey = (uint64_t *)scratch(c, 0, B_RSKEY, sizeof(uint64_t) * n_select);
+        rn = (int64_t *)scratch(c, 0, B_RSN, sizeof(int64_t));
+        if (!rdet || !re || !rkey || !rn) return fail(c, QP_E_OOM, "device allocation failed (stochastic selection)");
+        rdet_h.resize((size_t)n_select * dw);
+        re_h.resize((size_t)n_select * ns);
+        rkey_h.resize((size_t)n_select);
+    }
+    // a before b in the selection order: larger key, then smaller bit string
+    // (each spin's words from the highest)
+    auto before = [&](uint64_t ka, const uint64_t *da, uint64_t kb, const uint64_t *db) {
+        if (ka != kb) return ka > kb;
+        for (int sp = 0; sp < 2; ++sp)
+            for (int w = nint - 1; w >= 0; --w) {
+                const uint64_t x = da[sp * nint + w], y = db[sp * nint + w];
+                if (x != y) return x < y;
+            }
+        return false;
+    };
     // generator order and weights w_r = sum_k c_k(det of rank r)^2
     std::vector<int32_t> perm(n_det);
     std::vector<double> ch((size_t)ns * n_det);
@@ -2542,9 +2598,23 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
             x.dets = dets; x.coefs = coefs; x.n_det = n_det; x.ns = ns; x.E0 = E0;
             x.gens = dgen; x.n_gen = m; x.eps_gen = deps;
             x.pre = &P;
+            if (n_select > 0) {
+                x.n_select = n_select; x.sel_dets = rdet; x.sel_e = re; x.n_sel = rn; x.sel_key = rkey;
+                // once n_select alpha are held, an alpha whose key is below the
+                // last one's can no longer enter: the round starts its
+                // threshold at the lower edge of that key's histogram bin
+                if ((int64_t)mkey.size() == n_select) x.sel_floor_bin = key_bin_host(mkey.back());
+            }
             rc = run_sweeps(c, in, flags | QP_FLAG_NOCHECK, false, st);
             if (rc != QP_OK) { cleanup(); return rc; }
             HIPCHK(c, hipMemcpyAsync(heps, deps, sizeof(double) * m * ns, hipMemcpyDeviceToHost, st));
+            int64_t rcount = 0;
+            if (n_select > 0) {
+                HIPCHK(c, hipMemcpyAsync(&rcount, rn, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipMemcpyAsync(rdet_h.data(), rdet, sizeof(uint64_t) * n_select * dw, hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipMemcpyAsync(re_h.data(), re, sizeof(double) * n_select * ns, hipMemcpyDeviceToHost, st));
+                HIPCHK(c, hipMemcpyAsync(rkey_h.data(), rkey, sizeof(uint64_t) * n_select, hipMemcpyDeviceToHost, st));
+            }
             HIPCHK(c, hipStreamSynchronize(st));
             for (int64_t i = 0; i < m; ++i) {
                 const int64_t r = todo[i];
@@ -2552,6 +2622,28 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
                 done[r] = 1;
             }
             computed += m;
+            if (n_select > 0 && rcount > 0) {
+                // merge the round's sorted list into the running one, keep n_select
+                const int64_t a_n = (int64_t)mkey.size(), tot = std::min<int64_t>(a_n + rcount, n_select);
+                tkey.resize(tot);
+                tdet.resize((size_t)tot * dw);
+                te.resize((size_t)tot * ns);
+                int64_t ia = 0, ib = 0;
+                for (int64_t o = 0; o < tot; ++o) {
+                    const bool take_a = ib >= rcount ||
+                                        (ia < a_n && before(mkey[ia], &mdet[(size_t)ia * dw], rkey_h[ib],
+                                                            &rdet_h[(size_t)ib * dw]));
+                    const uint64_t *kd = take_a ? &mdet[(size_t)ia * dw] : &rdet_h[(size_t)ib * dw];
+                    const double *ke = take_a ? &me[(size_t)ia * ns] : &re_h[(size_t)ib * ns];
+                    tkey[o] = take_a ? mkey[ia] : rkey_h[ib];
+                    std::copy(kd, kd + dw, &tdet[(size_t)o * dw]);
+                    std::copy(ke, ke + ns, &te[(size_t)o * ns]);
+                    if (take_a) ++ia; else ++ib;
+                }
+                mkey.swap(tkey);
+                mdet.swap(tdet);
+                me.swap(te);
+            }
         }
         for (int64_t r = d; r < d_new; ++r)
             for (int k = 0; k < ns; ++k) det_sum[k] += eps[(size_t)r * ns + k];
@@ -2590,6 +2682,25 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
     cleanup();
     *n_computed = computed;
     *n_rounds = rounds;
+    if (n_select > 0) {
+        // the merged selection, and the computed flags, to the caller's device
+        // arrays; the host vectors live until the copies end
+        const int64_t msel = (int64_t)mkey.size();
+        if (msel > 0) {
+            HIPCHK(c, hipMemcpyAsync(sel_dets, mdet.data(), sizeof(uint64_t) * msel * dw, hipMemcpyHostToDevice, st));
+            HIPCHK(c, hipMemcpyAsync(sel_e, me.data(), sizeof(double) * msel * ns, hipMemcpyHostToDevice, st));
+        }
+        HIPCHK(c, hipMemcpyAsync(n_sel, &msel, sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
+    if (computed_out) {
+        // 1 for every determinant whose eps was computed, in the caller's order
+        std::vector<uint8_t> fl((size_t)n_det, 0);
+        for (int64_t r = 0; r < n_det; ++r)
+            if (done[r]) fl[(size_t)perm[r]] = 1;
+        HIPCHK(c, hipMemcpyAsync(computed_out, fl.data(), (size_t)n_det, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
     return QP_OK;
 }
 

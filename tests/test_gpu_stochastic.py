@@ -8,7 +8,7 @@ against the deterministic E_PT2."""
 import numpy as np
 import pytest
 
-from gpu_helpers import U, gpu_system, run_gpu
+from gpu_helpers import U, gpu_system, run_gpu, selection_keys
 from oracle import oracle as orc
 from paper_1902_08154_amd import synth
 
@@ -167,3 +167,96 @@ def test_stochastic_c2_full_size(ctx):
     assert err <= 0.002 * abs(e)
     assert abs(e - full["e_pt2"][0]) <= 4 * err
     assert g["n_computed"] < s.n_det
+
+
+def _oracle_computed(s, E0, u, rel_err, chunk, draws):
+    """The generators (determinant indices) whose eps the oracle's estimator
+    computes on this schedule."""
+    order = np.argsort(orc.generator_rank(s.dets, s.coefs))
+    w = (s.coefs[:, order] ** 2).sum(axis=0)
+    seen = set()
+
+    def eps_of(ranks):
+        seen.update(int(order[r]) for r in ranks)
+        return orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, order[np.asarray(ranks)]).eps
+
+    orc.semistochastic(eps_of, w, u, rel_err, chunk, draws)
+    return seen
+
+
+def test_stochastic_selection_on_the_fly(ctx):
+    """Selection during the semi-stochastic sweep (the paper's new stochastic
+    selection): the computed generators are the oracle estimator's on the same
+    random numbers; the selection, merged over several rounds, is bit for bit
+    the generator-list sweep's selection over those generators; every
+    selected alpha is owned by a computed generator (re-evaluated from
+    scratch, its e_alpha within 1e-10), and every alpha of a computed
+    generator whose criterion clears the cut is selected."""
+    import torch
+    from paper_1902_08154_amd.api import from_device_dets
+    s = _mid()
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    u = synth.uniforms(13, 120)
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    n_select = 60
+    g = ctx.pt2_stochastic(dets, coefs, E0t, u, rel_err=0.01, det_chunk=7, draws_per_round=10, n_select=n_select)
+    comp = g["computed"].cpu().numpy()
+    gens = np.flatnonzero(comp).astype(np.int32)
+    print(f"rounds {g['n_rounds']}, computed {g['n_computed']}, selected {len(g['sel_e'])}", flush=True)
+    assert g["n_rounds"] > 1 and len(gens) == g["n_computed"] < s.n_det
+    assert set(gens.tolist()) == _oracle_computed(s, E0, u, 0.01, 7, 10)
+    r = ctx.pt2_generators(dets, coefs, E0t, torch.from_numpy(gens), n_select=n_select)
+    assert len(g["sel_e"]) == len(r["sel_e"]) == n_select
+    assert g["sel_dets"].cpu().numpy().tobytes() == r["sel_dets"].cpu().numpy().tobytes()
+    assert g["sel_e"].cpu().numpy().tobytes() == r["sel_e"].cpu().numpy().tobytes()
+    sel = from_device_dets(g["sel_dets"])
+    sel_e = g["sel_e"].cpu().numpy()
+    rank = orc.generator_rank(s.dets, s.coefs)
+    listed = set(int(rank[i]) for i in gens)
+    for a, ea in zip(sel, sel_e):
+        N, D, own, internal = orc.alpha_eval(s.n_orb, s.h, s.eri, s.dets, s.coefs, rank, a)
+        assert not internal and own in listed
+        for k in range(s.n_states):
+            e = N[k] ** 2 / (E0[k] - D)
+            assert abs(ea[k] - e) <= 1e-10 * abs(e) + 32 * U * (abs(E0[k]) + 1) * abs(e / (E0[k] - D)) + 1e-300
+    keys = selection_keys(sel_e, s.coefs)
+    od = orc.eps_generators(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, gens, dump_thr=keys[-1] * (1 + 1e-6),
+                            dump_cap=400)
+    chosen = {bytes(d.tobytes()) for d in sel}
+    for i in range(len(gens)):
+        assert od.dump_n[i] < 400
+        for t in range(od.dump_n[i]):
+            assert bytes(od.dump_dets[i, t].tobytes()) in chosen
+
+
+def test_stochastic_selection_complete_run_is_the_full_selection(ctx):
+    """When the rounds reach every generator, the merged selection is the
+    deterministic sweep's, bit for bit, and the oracle's."""
+    import torch
+    from gpu_helpers import assert_selection_equal
+    s = _mid()
+    E0 = orc.energy(s.n_orb, s.h, s.eri, s.dets, s.coefs)
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.tensor(E0, device=ctx.device)
+    g = ctx.pt2_stochastic(dets, coefs, E0t, synth.uniforms(3, 40), rel_err=0.0, det_chunk=45, draws_per_round=4,
+                           n_select=50)
+    assert g["n_computed"] == s.n_det and g["n_rounds"] > 1 and bool(g["computed"].all())
+    full = run_gpu(ctx, s, E0, n_select=50)
+    from paper_1902_08154_amd.api import from_device_dets
+    assert np.array_equal(from_device_dets(g["sel_dets"]), full["sel_dets"])
+    assert g["sel_e"].cpu().numpy().tobytes() == np.ascontiguousarray(full["sel_e"]).tobytes()
+    o = orc.pt2_full(s.n_orb, s.h, s.eri, s.dets, s.coefs, E0, n_select=50)
+    assert_selection_equal(from_device_dets(g["sel_dets"]), g["sel_e"].cpu().numpy(), o, s.coefs)
+
+
+def test_stochastic_selection_refuses_bad_arguments(ctx):
+    import torch
+    from paper_1902_08154_amd.api import QPError
+    s = _mid()
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.zeros(s.n_states, dtype=torch.float64, device=ctx.device)
+    with pytest.raises(QPError):
+        ctx.qp_pt2_stochastic(dets, coefs, E0t, synth.uniforms(1, 4), 0.0, 10, 2, n_select=-1)
+    with pytest.raises(QPError):   # selection outputs missing
+        ctx.qp_pt2_stochastic(dets, coefs, E0t, synth.uniforms(1, 4), 0.0, 10, 2, n_select=5)
