@@ -259,6 +259,7 @@ class Sweep:
         self.se = torch.empty((max(nsel, 1), ns), dtype=torch.float64, device=dev)
         self.nsl = torch.zeros(1, dtype=torch.int64, device=dev)
         self.st = torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev)
+        self.stb = torch.zeros(ctypes.sizeof(_lib.Stats), dtype=torch.uint8, device=dev)
         self.gup = torch.ones(ns, dtype=torch.float64, device=dev)
         self.gc = torch.empty((ns, nd), dtype=torch.float64, device=dev)
         self.gE = torch.empty(ns, dtype=torch.float64, device=dev)
@@ -269,11 +270,11 @@ class Sweep:
                         self.nsl, self.st, None)
 
     def backward(self):
-        self.ctx.qp_pt2_backward(self.dets, self.coefs, self.E0, self.gup, 0, self.gc, self.gE, self.gh, None)
+        self.ctx.qp_pt2_backward(self.dets, self.coefs, self.E0, self.gup, 0, self.gc, self.gE, self.gh, self.stb)
 
-    def stats(self):
+    def stats(self, adjoint=False):
         from paper_1902_08154_amd.api import stats_to_dict
-        return stats_to_dict(self.st, self.s.n_states)
+        return stats_to_dict(self.stb if adjoint else self.st, self.s.n_states)
 
 
 def filter_figures(s, stats):
@@ -399,6 +400,10 @@ def main():
         "forward_ms": 1e3 * float(np.mean(wall_f)), "forward_alpha_per_s": stats["n_alpha"] / float(np.mean(wall_f)),
         "forward_kernel_ms": kms(tf_list), "adjoint_kernel_ms": kms(tb_list),
         "alpha_clean": alpha_clean, "alpha_general_kernel": stats["n_alpha_general"],
+        # the adjoint hands the dense kernel's integral-plane batches (NS > 1 or
+        # more than two words per spin) to the general kernel
+        "adjoint_alpha_general_kernel": w.stats(adjoint=True)["n_alpha_general"],
+        "adjoint_general_fraction": w.stats(adjoint=True)["n_alpha_general"] / max(stats["n_alpha"], 1),
         "clean_cell_forward_roofline": ({"achieved": ops_f / kf / 1e12, "frac": ops_f / kf / ALU_PEAK_OPS,
                                          "kernel_ms": 1e3 * kf, "ops_per_alpha": clean_ops_per_alpha(ns, False)}
                                         if alpha_clean > 0 else None),
