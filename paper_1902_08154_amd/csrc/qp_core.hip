@@ -2555,7 +2555,7 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
     const double W = run;
     // memoised eps_r,k, the draw log, and the deterministic prefix [0, d)
     std::vector<double> eps((size_t)n_det * ns, 0.0);
-    std::vector<char> done(n_det, 0);
+    std::vector<char> done(n_det, 0), queued(n_det, 0);   // queued: in this round's list
     std::vector<int64_t> draws;
     int64_t d = 0, next_u = 0, computed = 0, rounds = 0;
     std::vector<double> det_sum(ns, 0.0);
@@ -2577,7 +2577,7 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
         todo.clear();
         const int64_t d_new = std::min<int64_t>(n_det, d + det_chunk);
         for (int64_t r = d; r < d_new; ++r)
-            if (!done[r]) todo.push_back(r);
+            if (!done[r]) { todo.push_back(r); queued[r] = 1; }
         int64_t drawn = 0;
         while (drawn < draws_per_round && next_u < n_uniforms && W > 0.0) {
             const double t = uniforms[next_u++] * W;
@@ -2585,7 +2585,7 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
             if (r >= n_det) r = n_det - 1;
             draws.push_back(r);
             ++drawn;
-            if (r >= d_new && !done[r] && std::find(todo.begin(), todo.end(), r) == todo.end()) todo.push_back(r);
+            if (r >= d_new && !done[r] && !queued[r]) { todo.push_back(r); queued[r] = 1; }
         }
         if (!todo.empty()) {
             for (size_t i = 0; i < todo.size(); ++i) hgen[i] = perm[todo[i]];
@@ -2620,6 +2620,7 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
                 const int64_t r = todo[i];
                 for (int k = 0; k < ns; ++k) eps[(size_t)r * ns + k] = heps[(size_t)k * m + i];
                 done[r] = 1;
+                queued[r] = 0;
             }
             computed += m;
             if (n_select > 0 && rcount > 0) {
