@@ -8,8 +8,8 @@ so it checks a few sampled generators, each split into 16 slices of its
 excitations (in the oracle's enumeration order; the slices' sums add up to
 the generator's) evaluated on host threads while the GPU runs, and a random
 sample of the selection:
-  * eps_I of the generator of rank 0, of a random rank below 1,000 and of
-    a random rank above,
+  * eps_I of the generators of ranks 0 to 3, of a random rank below 1,000
+    and of a random rank above,
   * completeness: every alpha owned by a sampled generator whose criterion
     clears the selection's cut is among the selected ones,
   * 256 selected alpha re-evaluated from scratch over all of Psi (numerator,
@@ -85,9 +85,10 @@ def test_c5_full_size_sampled(ctx):
     rank = orc.generator_rank(s.dets, s.coefs)
     order = np.argsort(rank)
     rng = np.random.default_rng(5005)
-    # rank 0, a random rank among the first thousand (coefficients there are
-    # still large enough for eps_I to test the numerators) and one anywhere
-    ranks = [0, int(rng.integers(1, 1000)), int(rng.integers(1000, s.n_det))]
+    # the four largest generators, a random rank among the first thousand
+    # (coefficients there are still large enough for eps_I to test the
+    # numerators) and one anywhere
+    ranks = [0, 1, 2, 3, int(rng.integers(4, 1000)), int(rng.integers(1000, s.n_det))]
     gens = order[ranks]
     n_slices = 16
     width = -(-cells // n_slices)
