@@ -2491,7 +2491,10 @@ int qp_pt2_stochastic(qp_ctx *c, const uint64_t *dets, const double *coefs, int6
     *n_rounds = 0;
     hipStream_t st = (hipStream_t)stream;
     if (n_det == 0) {
-        if (n_select > 0) HIPCHK(c, hipMemsetAsync(n_sel, 0, sizeof(int64_t), st));
+        if (n_select > 0) {
+            HIPCHK(c, hipMemsetAsync(n_sel, 0, sizeof(int64_t), st));
+            HIPCHK(c, hipStreamSynchronize(st));
+        }
         return QP_OK;
     }
     // on-the-fly selection: every round also selects the top n_select alpha

@@ -260,3 +260,15 @@ def test_stochastic_selection_refuses_bad_arguments(ctx):
         ctx.qp_pt2_stochastic(dets, coefs, E0t, synth.uniforms(1, 4), 0.0, 10, 2, n_select=-1)
     with pytest.raises(QPError):   # selection outputs missing
         ctx.qp_pt2_stochastic(dets, coefs, E0t, synth.uniforms(1, 4), 0.0, 10, 2, n_select=5)
+
+
+def test_stochastic_empty_wave_function(ctx):
+    """No determinants: estimate and error 0, nothing computed or selected."""
+    import torch
+    s = _mid()
+    dets, coefs = gpu_system(ctx, s)
+    E0t = torch.zeros(s.n_states, dtype=torch.float64, device=ctx.device)
+    g = ctx.pt2_stochastic(dets[:0].contiguous(), coefs[:, :0].contiguous(), E0t, synth.uniforms(1, 4),
+                           rel_err=0.0, det_chunk=4, draws_per_round=2, n_select=5)
+    assert np.all(g["e_pt2"] == 0) and np.all(g["err"] == 0)
+    assert (g["n_computed"], g["n_rounds"]) == (0, 0) and g["sel_e"].shape[0] == 0
